@@ -1,0 +1,104 @@
+"""Pins for the whole method in the oracle (oracle/ruqlp.py)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import philox
+from oracle.metrics import optimal_error
+import workloads
+from tests import pins
+
+
+def _small(spec, m=300, n=200, seed=0, **kw):
+    sigma = workloads.spectrum(spec, min(m, n), **kw)
+    A, s, U, V = workloads.dense_from_spectrum(m, n, sigma, seed, trunc=0.0)
+    full = np.zeros(min(m, n))
+    full[:len(s)] = s
+    return A, full, U, V
+
+
+@pytest.mark.parametrize("q", [0, 1, 2])
+@pytest.mark.parametrize("spec,kw", [("geometric", dict(rho=0.8)), ("gapped", dict(gap_at=10))])
+def test_invariants(q, spec, kw):
+    A, s, U, V = _small(spec, seed=q + 3, **kw)
+    Q, L, Vf = oracle.ruqlp(A, 10, 5, q, seed=17)
+    ok, info = pins.check_ruqlp_invariants(A, Q, L, Vf)
+    assert ok, info
+    ok, info = pins.check_sv_interlacing(s, L)
+    assert ok, info
+    # Eckart-Young: no rank-d approximation beats the truncated SVD
+    err = np.linalg.norm(A - Q @ L @ Vf.T)
+    assert err >= optimal_error(s, 15, "fro") * (1 - 1e-12)
+
+
+@pytest.mark.parametrize("q", [0, 1, 2])
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+@pytest.mark.parametrize("spec,kw", [("geometric", dict(rho=0.8)), ("gapped", dict(gap_at=10))])
+def test_theorem2_and_theorem5_bounds(q, seed, spec, kw):
+    m, n, k, p = 300, 200, 10, 5
+    A, s, U, V = _small(spec, m, n, seed=100 + seed, **kw)
+    Omega = philox.gaussian_matrix(seed, n, k + p)
+    Q, L, Vf = oracle.ruqlp(A, k, p, q, seed=seed)
+    ok, info = pins.check_theorem_bounds(A, s, U[:, :k], V[:, :k], Omega, Q, Vf, k, q)
+    assert ok, info
+
+
+@pytest.mark.parametrize("rank,k,p", [(6, 8, 4), (10, 10, 0), (1, 3, 2)])
+def test_exact_recovery_when_rank_le_d(rank, k, p):
+    sigma = np.zeros(80)
+    sigma[:rank] = np.linspace(2.0, 0.5, rank)
+    A, _, _, _ = workloads.dense_from_spectrum(120, 80, sigma, seed=rank, trunc=0.0)
+    for q in (0, 1):
+        Q, L, Vf = oracle.ruqlp(A, k, p, q, seed=5)
+        assert oracle.recon_error(A, Q, L, Vf) <= 1e-13
+        ok, info = pins.check_ruqlp_invariants(A, Q, L, Vf)
+        assert ok, info
+        # rank revealed: diag(L) beyond the rank is negligible
+        assert np.all(np.abs(np.diag(L)[rank:]) <= 1e-13 * np.abs(np.diag(L)).max())
+
+
+def test_zero_matrix():
+    A = np.zeros((30, 20))
+    Q, L, Vf = oracle.ruqlp(A, 3, 2, 1, seed=1)
+    assert np.all(L == 0.0)
+    assert oracle.orth_error(Q) < 1e-13 and oracle.orth_error(Vf) < 1e-13
+
+
+def test_orthogonal_iteration_limit():
+    # Section III-C: with many power steps the method is orthogonal
+    # iteration and L tends to diag(sigma_1..sigma_d) (diag(L) >= 0 here).
+    A, s, _, _ = _small("geometric", m=60, n=50, seed=9, rho=0.7)
+    Q, L, Vf = oracle.ruqlp(A, 6, 2, 60, seed=4)
+    ok, info = pins.check_orth_iteration_limit(L, s)
+    assert ok, info
+
+
+@pytest.mark.parametrize("m,n,k,p", [(90, 60, 5, 3), (40, 40, 10, 0)])
+def test_q0_matches_lapack_composition(m, n, k, p):
+    # q = 0: Q = qr(A Omega).Q, [V, Rt] = qr(A^T Q), L = Rt^T, each QR unique
+    A, s, _, _ = _small("geometric", m=m, n=n, seed=m, rho=0.9)
+    Omega = philox.gaussian_matrix(21, n, k + p)
+    Ql, _ = pins.lapack_qr_positive(A @ Omega)
+    Vl, Rl = pins.lapack_qr_positive(A.T @ Ql)
+    Q, L, Vf = oracle.ruqlp(A, k, p, 0, seed=21)
+    assert np.linalg.norm(Q - Ql) < 1e-9
+    assert np.linalg.norm(Vf - Vl) < 1e-9
+    assert np.linalg.norm(L - Rl.T) < 1e-9 * np.linalg.norm(L)
+
+
+def test_csr_path_equals_dense_path():
+    rowptr, colidx, vals = workloads.csr_uniform(400, 150, 3000, seed=8)
+    from oracle.csr import csr_to_dense
+    D = csr_to_dense(rowptr, colidx, vals, 400, 150)
+    Qs, Ls, Vs = oracle.ruqlp_csr(rowptr, colidx, vals, 400, 150, 8, 4, 1, seed=3, omega_dtype="f32")
+    Qd, Ld, Vd = oracle.ruqlp(D, 8, 4, 1, seed=3, omega_dtype="f32")
+    assert np.linalg.norm(Qs - Qd) < 1e-11 and np.linalg.norm(Vs - Vd) < 1e-11
+    assert np.linalg.norm(Ls - Ld) < 1e-11 * np.linalg.norm(Ld)
+
+
+def test_omega_rounding_modes():
+    A, _, _, _ = _small("geometric", m=50, n=40, seed=1, rho=0.8)
+    Q64, _, _ = oracle.ruqlp(A, 5, 2, 0, seed=2, omega_dtype="f64")
+    Q32, _, _ = oracle.ruqlp(A, 5, 2, 0, seed=2, omega_dtype="f32")
+    # float32 rounding of Omega moves Q by ~1e-8, not more
+    assert 0 < np.linalg.norm(Q64 - Q32) < 1e-5
