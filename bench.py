@@ -1,0 +1,250 @@
+"""Benchmark: RU-QLP throughput on one MI355X.
+
+One step = one full decomposition (Gaussian sketch, 2q+2 products with A,
+2q+2 CholeskyQR2 factorizations, L = R^T) of the 8000 x 8000 float32 gapped
+workload, k = 200, p = 10, q = 1, with A already resident in HBM.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--no-cpu-baseline] [--copy-calibration]
+
+Prints one JSON line.  `value` is algorithmic GFLOP/s = F_alg / time, with
+F_alg = 2 m n d (2q + 2) + sum over the QRs of (4 r d^2 - 4 d^3 / 3).
+`roofline` is for the dominant kernel (the dense product on the matrix
+cores), timed with HIP events recorded by the library on the launch stream
+during the timed steps.  `cpu_baseline` times the float64 oracle on the host.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published dense peaks
+    "f32_mfma_tflops": 157.3,
+    "f64_mfma_tflops": 78.6,
+    "hbm_gbs": 8000.0,
+}
+
+WORKLOADS = {
+    "dense8000": dict(kind="dense", m=8000, n=8000, k=200, p=10, q=1, dtype="f32", spectrum="gapped"),
+    "dense8000_q0": dict(kind="dense", m=8000, n=8000, k=200, p=10, q=0, dtype="f32", spectrum="gapped"),
+    "small_fp64": dict(kind="dense", m=1000, n=800, k=20, p=5, q=0, dtype="f64", spectrum="geometric"),
+    "csr100k": dict(kind="csr", m=100000, n=50000, k=100, p=10, q=1, dtype="f32", density=1e-3),
+}
+
+
+def f_alg(m, n, k, p, q):
+    d = k + p
+    qr = lambda r: 4.0 * r * d * d - 4.0 * d ** 3 / 3.0  # noqa: E731
+    prods = 2.0 * m * n * d * (2 * q + 2)
+    qrs = qr(m) * (q + 1) + qr(n) * (q + 1)
+    return prods + qrs
+
+
+def f_alg_csr(nnz, m, n, k, p, q):
+    d = k + p
+    qr = lambda r: 4.0 * r * d * d - 4.0 * d ** 3 / 3.0  # noqa: E731
+    return 2.0 * nnz * d * (2 * q + 2) + qr(m) * (q + 1) + qr(n) * (q + 1)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(os.path.join(ROOT, "paper_2209_12464_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2209_12464_amd", "csrc", name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` measured by rocprofv3 PMC runs and
+    committed under profiles/, if taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(workload, {}).get(kernel)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def make_inputs(w, seed):
+    import workloads
+    if w["kind"] == "dense":
+        if w["spectrum"] == "gapped":
+            c = workloads.cfg_gapped_fp32(seed=seed, m=w["m"], n=w["n"], q=w["q"])
+            return c["A"]
+        c = workloads.cfg_small_fp64(seed=seed)
+        return c["A"]
+    c = workloads.cfg_sparse(seed=seed, m=w["m"], n=w["n"], density=w["density"])
+    return c
+
+
+def cpu_baseline(w, A_host, seed, flops):
+    """Time the float64 oracle on this host on one decomposition (or, for
+    the sparse workload, the same)."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    if w["kind"] == "dense":
+        oracle.ruqlp(A_host.astype(np.float64), w["k"], w["p"], w["q"], seed,
+                     omega_dtype="f32" if w["dtype"] == "f32" else "f64")
+        sample = f"one full decomposition of the same {w['m']}x{w['n']} workload (q={w['q']})"
+    else:
+        c = A_host
+        oracle.ruqlp_csr(c["rowptr"], c["colidx"], c["vals"], c["m"], c["n"], w["k"], w["p"], w["q"], seed,
+                         omega_dtype="f32")
+        sample = f"one full decomposition of the same {w['m']}x{w['n']} CSR workload (q={w['q']})"
+    dt = time.perf_counter() - t0
+    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": sample, "seconds": dt}
+
+
+def copy_calibration(nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of known size, for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of a profiled run."""
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="dense8000", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}), flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_2209_12464_amd import rqlp
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda", 0)
+    host = make_inputs(w, args.seed)
+    ctx = rqlp.Context(0)
+    k, p, q = w["k"], w["p"], w["q"]
+    d = k + p
+    if w["kind"] == "dense":
+        A = torch.from_numpy(host).to(dev)
+        m, n = A.shape
+        flops = f_alg(m, n, k, p, q)
+        ws = rqlp.alloc_workspace(rqlp.workspace_size(m, n, k, p, q, A.dtype), dev)
+        out = (torch.empty((m, d), dtype=A.dtype, device=dev), torch.empty((d, d), dtype=A.dtype, device=dev),
+               torch.empty((n, d), dtype=A.dtype, device=dev))
+        step = lambda: rqlp.decompose(A, k, p, q, seed=args.seed, ctx=ctx, workspace=ws, out=out)  # noqa: E731
+        dom = ["gemm_nn", "gemm_tn"]
+        dom_flops = {"gemm_nn": 2.0 * m * n * d, "gemm_tn": 2.0 * m * n * d}
+        dtype_name = "f32" if A.dtype == torch.float32 else "f64"
+    else:
+        c = host
+        m, n = c["m"], c["n"]
+        rp, ci, vv = (torch.from_numpy(c[x]).to(dev) for x in ("rowptr", "colidx", "vals"))
+        nnz = ci.numel()
+        flops = f_alg_csr(nnz, m, n, k, p, q)
+        ws = rqlp.alloc_workspace(rqlp.workspace_size_csr(m, n, nnz, k, p, q, vv.dtype), dev)
+        out = (torch.empty((m, d), dtype=vv.dtype, device=dev), torch.empty((d, d), dtype=vv.dtype, device=dev),
+               torch.empty((n, d), dtype=vv.dtype, device=dev))
+        step = lambda: rqlp.decompose_csr(rp, ci, vv, m, n, k, p, q, seed=args.seed, ctx=ctx, workspace=ws,  # noqa: E731
+                                          out=out)
+        dom = ["spmm"]
+        dtype_name = "f32"
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per_kernel = {}
+    for name in rqlp.KERNEL_CLASSES:
+        ms, cnt = ctx.timing(name)
+        if cnt:
+            per_kernel[name] = {"avg_ms": ms / cnt, "launches": cnt, "total_ms": ms}
+    ctx.set_timing(False)
+    info = ctx.info()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = flops / (ms_per_step * 1e-3) / 1e9
+
+    roofline = None
+    dom_present = [k_ for k_ in dom if k_ in per_kernel]
+    if dom_present:
+        kname = max(dom_present, key=lambda x: per_kernel[x]["total_ms"])
+        avg_s = per_kernel[kname]["avg_ms"] * 1e-3
+        if w["kind"] == "dense":
+            peak = PEAK["f32_mfma_tflops"] if dtype_name == "f32" else PEAK["f64_mfma_tflops"]
+            achieved = dom_flops[kname] / avg_s / 1e12
+            traffic = load_traffic(args.workload, kname)
+            roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                        "frac": achieved / peak, "traffic": traffic, "kernel": kname}
+        else:
+            # gather-inclusive bytes of one A X product: indices+values, row
+            # pointers, one gathered X row per entry, the output rows
+            es = 4
+            byts = nnz * (4 + es) + (m + 1) * 4 + nnz * d * es + m * d * es
+            achieved = byts / avg_s / 1e9
+            traffic = load_traffic(args.workload, kname)
+            roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                        "frac": achieved / PEAK["hbm_gbs"], "traffic": traffic, "kernel": kname}
+
+    res = {
+        "metric": "RU-QLP GFLOP/s (8000^2 FP32, k=200, p=10, q=1)" if args.workload == "dense8000"
+        else f"RU-QLP GFLOP/s ({args.workload})",
+        "value": value,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype_name,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "n": n, "k": k, "p": p, "q": q,
+                   "flops_per_step": flops},
+        "roofline": roofline,
+        "kernels": per_kernel,
+        "info": info,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(w, host, args.seed, flops)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * rqlp.h -- C ABI of the MI355X (gfx950) randomized unpivoted QLP library.
+ *
+ * The library factors a real m x n matrix A as A ~ Q L V^T, where Q (m x d)
+ * and V (n x d) have orthonormal columns, L (d x d) is lower triangular, and
+ * d = k + p (target rank k plus oversampling p).  The steps follow the paper
+ * "Randomized Rank-Revealing QLP for Low-Rank Matrix Decomposition",
+ * Algorithm 1 (Section III-A) with the power iteration of Algorithm 2
+ * (Section III-B), applied in the column-sketch orientation:
+ *
+ *   Omega = randn(n, d)           Gaussian test matrix (Section III-A, step 1)
+ *   Q     = orth(A Omega)         sketch and orthonormal basis
+ *   q times: W = orth(A^T Q); Q = orth(A W)        (Algorithm 2)
+ *   B^T   = A^T Q                 projection (Section III-A, step 4)
+ *   [V, Rt] = qr(B^T);  L = Rt^T  unpivoted QR; the L-values diag(L) reveal
+ *                                 the numerical rank (Theorem 1, Corollary 1)
+ *
+ * orth() and qr() are the unpivoted QR with a positive diagonal in R,
+ * computed by CholeskyQR2 with a float64 Gram matrix and Cholesky factor.
+ *
+ * Conventions for every entry point:
+ *  - Matrices are row-major with an explicit leading dimension (elements).
+ *  - Pointers named A, Q, L, V, X, Y, rowptr, colidx, vals, workspace are
+ *    DEVICE pointers owned by the caller; the library never frees them and
+ *    keeps no reference after the call returns.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default
+ *    stream.  All work is enqueued on it; calls return before it finishes.
+ *  - `workspace` may be NULL: the context then uses (and grows) a device
+ *    buffer of its own, kept until rqlp_destroy.  Otherwise it must hold at
+ *    least the bytes the matching *_workspace_size function reports.
+ *  - Argument errors are returned synchronously and enqueue nothing.
+ *  - Numerical events (rank-deficient sketches completed with fresh random
+ *    columns, non-finite values) are recorded on the device; read them with
+ *    rqlp_get_info after synchronizing the stream.
+ *  - Calls on one context must not overlap in time (the info record and the
+ *    internal workspace belong to the context).  Use one context per stream.
+ */
+#ifndef RQLP_H
+#define RQLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RQLP_OK = 0,
+  RQLP_ERR_INVALID_ARG = 1,   /* bad sizes, null pointers, bad enum       */
+  RQLP_ERR_UNSUPPORTED = 2,   /* valid request this build does not cover  */
+  RQLP_ERR_OUT_OF_MEMORY = 3, /* workspace too small or allocation failed */
+  RQLP_ERR_HIP = 4,           /* a HIP runtime call failed                */
+  RQLP_ERR_NUMERICAL = 5      /* non-finite values met (rqlp_get_info)    */
+} rqlp_status;
+
+/* Working precision.  A, Q, L, V (and X, Y of the step entry points) are
+ * double for RQLP_FP64 and float otherwise.  Gram matrices, Cholesky
+ * factors and the first CholeskyQR pass are always float64. */
+typedef enum {
+  RQLP_FP64 = 0,
+  RQLP_FP32 = 1,
+  RQLP_BF16_REFINED = 2 /* reserved: bfloat16 products; returns UNSUPPORTED */
+} rqlp_precision;
+
+typedef struct rqlp_ctx rqlp_ctx;
+
+/* Device-side record of the last call on a context. */
+typedef struct {
+  int32_t status;          /* RQLP_OK or RQLP_ERR_NUMERICAL                  */
+  int32_t completed_cols;  /* columns replaced by random completion (all QRs) */
+  int32_t breakdown_pass;  /* 1-based index of the first QR that completed a
+                              column (0 if none)                             */
+  int32_t nonfinite;       /* 1 if a Gram matrix held NaN or Inf             */
+} rqlp_info;
+
+/* Create a context on HIP device `device` (its ordinal).  Allocates a small
+ * device buffer for the info record.  *ctx is set to NULL on failure. */
+rqlp_status rqlp_create(rqlp_ctx** ctx, int device);
+
+/* Destroy a context and free its internal buffers.  Synchronizes the device
+ * first.  NULL is accepted. */
+rqlp_status rqlp_destroy(rqlp_ctx* ctx);
+
+/* Bytes of workspace rqlp_decompose needs; 0 if the arguments are invalid. */
+size_t rqlp_workspace_size(int64_t m, int64_t n, int k, int p, int q, rqlp_precision prec);
+
+/* Bytes of workspace rqlp_decompose_csr needs; 0 if invalid. */
+size_t rqlp_workspace_size_csr(int64_t m, int64_t n, int64_t nnz, int k, int p, int q,
+                               rqlp_precision prec);
+
+/* RU-QLP of a dense A (Algorithms 1 and 2; see the top of this file).
+ *  A    : m x n, row-major, leading dimension lda >= n.
+ *  k, p : target rank (k >= 1) and oversampling (p >= 0); d = k + p must
+ *         satisfy d <= min(m, n) and d <= 256 in this build.
+ *  q    : number of power iterations (q >= 0), each two more passes over A.
+ *  seed : key of the Gaussian test matrix (Philox4x64-10, see rqlp_gaussian).
+ *  Q    : m x d output, leading dimension d.
+ *  L    : d x d output, lower triangular, leading dimension d.
+ *  V    : n x d output, leading dimension d.
+ * Rank-deficient sketches are completed with fresh random orthonormal
+ * columns; their L-values are exactly zero. */
+rqlp_status rqlp_decompose(rqlp_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda,
+                           int k, int p, int q, rqlp_precision prec, uint64_t seed,
+                           void* Q, void* L, void* V, void* workspace, size_t ws_bytes,
+                           void* stream);
+
+/* RU-QLP of a CSR matrix A (m x n) with nnz stored entries (Section III-D:
+ * O(nnz d) work per pass).  rowptr: m+1 int32, colidx: nnz int32 (column
+ * indices, no duplicates within a row), vals: nnz values in the working
+ * precision.  Builds the CSR of A^T once in the workspace.  Other arguments
+ * as for rqlp_decompose. */
+rqlp_status rqlp_decompose_csr(rqlp_ctx* ctx, const int32_t* rowptr, const int32_t* colidx,
+                               const void* vals, int64_t m, int64_t n, int64_t nnz, int k, int p,
+                               int q, rqlp_precision prec, uint64_t seed, void* Q, void* L,
+                               void* V, void* workspace, size_t ws_bytes, void* stream);
+
+/* Copy the info record of the last call to *out (host).  Synchronizes with
+ * the device copy; valid once the call's stream has been synchronized. */
+rqlp_status rqlp_get_info(rqlp_ctx* ctx, rqlp_info* out);
+
+/* Static English description of a status code. */
+const char* rqlp_status_string(rqlp_status s);
+
+/* ---- Step entry points: each runs one step of the path on its own ---- */
+
+/* Gaussian test matrix (Section III-A step 1; randn of Section II-A).
+ * out: rows x cols, leading dimension ldo >= cols; entries in columns
+ * [cols, ldo) are set to zero.  Entry (i, j) has logical index
+ * l = j*rows + i; block c = l / 4 is Philox4x64-10 at counter (c, 0, 0, 0)
+ * with key (seed, 0x52514C50 + stream_id); its words (w0, w1) give the
+ * values for l = 4c and 4c+1, (w2, w3) those for 4c+2 and 4c+3, through
+ * u1 = ((w >> 11) + 1) 2^-53, u2 = (w' >> 11) 2^-53 and Box-Muller
+ * z = sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2), evaluated in float64 and
+ * rounded to the working precision. */
+rqlp_status rqlp_gaussian(rqlp_ctx* ctx, uint64_t seed, uint32_t stream_id, int64_t rows,
+                          int64_t cols, rqlp_precision prec, void* out, int64_t ldo, void* stream);
+
+/* Dense product with A (Algorithm 1: the sketch A*Omega and the projection
+ * A^T Q; Algorithm 2: the power steps).
+ *  trans = 0: Y (m x d) = A X,   X is n x d;   trans = 1: Y (n x d) = A^T X,
+ *  X is m x d.  A is m x n row-major (lda).  X, Y leading dims ldx, ldy
+ *  >= d.  Working precision only (float or double); d <= 256. */
+size_t rqlp_gemm_workspace_size(int trans, int64_t m, int64_t n, int d, rqlp_precision prec);
+rqlp_status rqlp_gemm(rqlp_ctx* ctx, int trans, const void* A, int64_t m, int64_t n, int64_t lda,
+                      const void* X, int64_t ldx, int d, void* Y, int64_t ldy,
+                      rqlp_precision prec, void* workspace, size_t ws_bytes, void* stream);
+
+/* Unpivoted QR of a tall matrix, Y = Q R with diag(R) >= 0 (Section II-B;
+ * orth() of Section II-A), by CholeskyQR2 with float64 Gram and Cholesky.
+ *  Y: rows x d (ldy), not modified.  Q: rows x d output (ldq).  R: optional
+ *  d x d output (row-major, leading dimension d, working precision), NULL to
+ *  skip.  Columns found linearly dependent (relative residual below about
+ *  sqrt(64 d eps64)) are replaced by random unit columns; their R row is
+ *  zero.  Requires d <= rows and d <= 256. */
+size_t rqlp_orth_workspace_size(int64_t rows, int d, rqlp_precision prec);
+rqlp_status rqlp_orth(rqlp_ctx* ctx, const void* Y, int64_t rows, int d, int64_t ldy, void* Q,
+                      int64_t ldq, void* R, rqlp_precision prec, uint64_t seed, void* workspace,
+                      size_t ws_bytes, void* stream);
+
+/* CSR times dense (Section III-D, sparse A): Y (rows x d) = A X with A a
+ * rows x cols CSR matrix and X cols x d (ldx).  Working precision only. */
+rqlp_status rqlp_spmm(rqlp_ctx* ctx, const int32_t* rowptr, const int32_t* colidx,
+                      const void* vals, int64_t rows, int64_t cols, int64_t nnz, const void* X,
+                      int64_t ldx, int d, void* Y, int64_t ldy, rqlp_precision prec, void* stream);
+
+/* CSR transpose: CSR(A) (m x n, nnz entries) -> CSR(A^T) (n x m).  Entries
+ * of each output row are ordered by increasing input row, so the result is
+ * unique.  rowptr_t: n+1, colidx_t: nnz, vals_t: nnz (device, caller-owned).
+ * Bit-exact and deterministic. */
+size_t rqlp_csr_transpose_workspace_size(int64_t m, int64_t n, int64_t nnz);
+rqlp_status rqlp_csr_transpose(rqlp_ctx* ctx, const int32_t* rowptr, const int32_t* colidx,
+                               const void* vals, int64_t m, int64_t n, int64_t nnz,
+                               rqlp_precision prec, int32_t* rowptr_t, int32_t* colidx_t,
+                               void* vals_t, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- Timing hooks (benchmarking) ---- */
+
+/* Kernel classes whose launches can be timed with HIP events recorded on
+ * the call's stream around each launch. */
+typedef enum {
+  RQLP_KT_GEMM_NN = 0,   /* dense A X main kernel      */
+  RQLP_KT_GEMM_TN = 1,   /* dense A^T X main kernel    */
+  RQLP_KT_SPMM = 2,      /* CSR times dense            */
+  RQLP_KT_GRAM = 3,      /* float64 Gram partials      */
+  RQLP_KT_CHOL = 4,      /* float64 Cholesky           */
+  RQLP_KT_APPLY = 5,     /* triangular solve Q = Y R^-1 */
+  RQLP_KT_COUNT = 6
+} rqlp_kernel_class;
+
+/* Turn per-launch event timing on (1) or off (0); resets the totals. */
+rqlp_status rqlp_set_timing(rqlp_ctx* ctx, int enabled);
+
+/* After synchronizing: total milliseconds and launch count of a class since
+ * timing was enabled (all recorded event pairs are resolved). */
+rqlp_status rqlp_get_timing(rqlp_ctx* ctx, rqlp_kernel_class cls, double* total_ms,
+                            int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RQLP_H */

@@ -1,0 +1,321 @@
+// Dense products with A on the matrix cores: Y = A X (NN) and Y = A^T X (TN),
+// the sketch, power-step and projection products of Algorithms 1 and 2.
+//
+// The output is tall and skinny (d <= 256 columns), so one workgroup owns a
+// BM-row slab of Y and ALL of its columns: A is streamed from HBM exactly
+// once per product.  To fill 256 CUs the reduction dimension is split
+// (split-K); each split writes a partial slab and a second kernel sums the
+// partials in a fixed order, so results are bitwise reproducible.
+// Workgroup ids are remapped so that an XCD works on a contiguous range of
+// (split, slab) pairs: the X chunk of a split then stays in that XCD's L2.
+//
+// Tiles: 4 waves x TM rows (TM = 32 for float MFMA 32x32x2, 16 for double
+// MFMA 16x16x4), BK = 16 along the reduction, all BN = 32*NB (float) or
+// 16*NB (double) columns.  A and X tiles are staged through LDS, double
+// buffered with register prefetch, one barrier per K step.
+#include "common.h"
+#include "kernels.h"
+
+namespace rqlp {
+
+constexpr int kGemmThreads = 256;
+constexpr int kBK = 16;
+
+template <typename T, int NB, bool TRANS, bool AVEC>
+__global__ __launch_bounds__(kGemmThreads, 2) void gemm_kernel(
+    const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
+    T* __restrict__ C, int64_t ldc, int64_t cslice, int M, int N, int K, int kchunk, int mtiles,
+    int nst) {
+  typedef Mfma<T> MF;
+  constexpr int TM = MF::TM, TN = MF::TN, TK = MF::TK;
+  constexpr int BM = 4 * TM;
+  constexpr int BN = NB * TN;
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int APAD = TRANS ? VEC : 2;
+  constexpr int AS = BM + APAD;                       // LDS row stride of the A tile
+  constexpr int A_ELEMS = BM * kBK / kGemmThreads;    // per thread
+  constexpr int A_VECS = A_ELEMS / VEC;
+  constexpr int B_ELEMS = (kBK * BN + kGemmThreads - 1) / kGemmThreads;
+
+  __shared__ __attribute__((aligned(16))) T As[2][kBK][AS];
+  __shared__ __attribute__((aligned(16))) T Bs[2][kBK][BN];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int split = logical / mtiles;
+  const int mt = logical - split * mtiles;
+  const int m0 = mt * BM;
+  const int kbeg = split * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+
+  T areg[A_ELEMS];
+  T breg[B_ELEMS];
+
+  // ---- global -> registers ----
+  auto load_tile = [&](int k0) {
+    if constexpr (!TRANS) {
+      // A tile rows m0..m0+BM, cols k0..k0+BK (A is M x K)
+      if constexpr (AVEC) {
+#pragma unroll
+        for (int v = 0; v < A_VECS; ++v) {
+          const int idx = tid + kGemmThreads * v;
+          const int r = idx / (kBK / VEC), kv = idx % (kBK / VEC);
+          const int gr = m0 + r, gk = k0 + kv * VEC;
+          if (gr < M && gk + VEC <= kend) {
+            const T* p = A + (int64_t)gr * lda + gk;
+            if constexpr (VEC == 4) {
+              const floatx4 x = *reinterpret_cast<const floatx4*>(p);
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) areg[v * VEC + e] = x[e];
+            } else {
+              const double2 x = *reinterpret_cast<const double2*>(p);
+              areg[v * VEC + 0] = x.x;
+              areg[v * VEC + 1] = x.y;
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+              areg[v * VEC + e] = (gr < M && gk + e < kend) ? A[(int64_t)gr * lda + gk + e] : (T)0;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < A_ELEMS; ++i) {
+          const int idx = tid + kGemmThreads * i;
+          const int r = idx / kBK, kk = idx % kBK;
+          const int gr = m0 + r, gk = k0 + kk;
+          areg[i] = (gr < M && gk < kend) ? A[(int64_t)gr * lda + gk] : (T)0;
+        }
+      }
+    } else {
+      // A^T tile: rows k0..k0+BK of A (K x M), cols m0..m0+BM
+      if constexpr (AVEC) {
+#pragma unroll
+        for (int v = 0; v < A_VECS; ++v) {
+          const int idx = tid + kGemmThreads * v;
+          const int kk = idx / (BM / VEC), rv = idx % (BM / VEC);
+          const int gk = k0 + kk, gc = m0 + rv * VEC;
+          if (gk < kend && gc + VEC <= M) {
+            const T* p = A + (int64_t)gk * lda + gc;
+            if constexpr (VEC == 4) {
+              const floatx4 x = *reinterpret_cast<const floatx4*>(p);
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) areg[v * VEC + e] = x[e];
+            } else {
+              const double2 x = *reinterpret_cast<const double2*>(p);
+              areg[v * VEC + 0] = x.x;
+              areg[v * VEC + 1] = x.y;
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+              areg[v * VEC + e] = (gk < kend && gc + e < M) ? A[(int64_t)gk * lda + gc + e] : (T)0;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < A_ELEMS; ++i) {
+          const int idx = tid + kGemmThreads * i;
+          const int kk = idx / BM, r = idx % BM;
+          const int gk = k0 + kk, gc = m0 + r;
+          areg[i] = (gk < kend && gc < M) ? A[(int64_t)gk * lda + gc] : (T)0;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < B_ELEMS; ++i) {
+      const int idx = tid + kGemmThreads * i;
+      const int kk = idx / BN, n = idx % BN;
+      const int gk = k0 + kk;
+      breg[i] = (idx < kBK * BN && gk < kend && n < N) ? B[(int64_t)gk * ldb + n] : (T)0;
+    }
+  };
+
+  // ---- registers -> LDS buffer `buf` ----
+  auto store_tile = [&](int buf) {
+    if constexpr (!TRANS) {
+      if constexpr (AVEC) {
+#pragma unroll
+        for (int v = 0; v < A_VECS; ++v) {
+          const int idx = tid + kGemmThreads * v;
+          const int r = idx / (kBK / VEC), kv = idx % (kBK / VEC);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) As[buf][kv * VEC + e][r] = areg[v * VEC + e];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < A_ELEMS; ++i) {
+          const int idx = tid + kGemmThreads * i;
+          As[buf][idx % kBK][idx / kBK] = areg[i];
+        }
+      }
+    } else {
+      if constexpr (AVEC) {
+#pragma unroll
+        for (int v = 0; v < A_VECS; ++v) {
+          const int idx = tid + kGemmThreads * v;
+          const int kk = idx / (BM / VEC), rv = idx % (BM / VEC);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) As[buf][kk][rv * VEC + e] = areg[v * VEC + e];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < A_ELEMS; ++i) {
+          const int idx = tid + kGemmThreads * i;
+          As[buf][idx / BM][idx % BM] = areg[i];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < B_ELEMS; ++i) {
+      const int idx = tid + kGemmThreads * i;
+      if (idx < kBK * BN) Bs[buf][idx / BN][idx % BN] = breg[i];
+    }
+  };
+
+  typename MF::acc_t acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = MF::zero();
+
+  if (kbeg < kend) {
+    load_tile(kbeg);
+    store_tile(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += kBK) {
+      const bool more = k0 + kBK < kend;
+      if (more) load_tile(k0 + kBK);
+#pragma unroll
+      for (int ks = 0; ks < kBK / TK; ++ks) {
+        const T a = As[buf][ks * TK + lane / TM][wave * TM + lane % TM];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const T b = Bs[buf][ks * TK + lane / TN][nb * TN + lane % TN];
+          acc[nb] = MF::mma(a, b, acc[nb]);
+        }
+      }
+      if (more) store_tile(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  // ---- epilogue: write the slab (or this split's partial slab) ----
+  T* Cs = C + (int64_t)split * cslice;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int col = nb * TN + MF::col(lane);
+#pragma unroll
+    for (int r = 0; r < MF::NACC; ++r) {
+      const int row = m0 + wave * TM + MF::row(lane, r);
+      if (row < M && col < nst) Cs[(int64_t)row * ldc + col] = acc[nb][r];
+    }
+  }
+}
+
+// Y[i][j] = sum_s P[s][i][j] in order s = 0..nsplit-1 (i < M, j < nst).
+template <typename T>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const T* __restrict__ P, int64_t ldp,
+                                                            int64_t pslice, int nsplit, T* __restrict__ Y,
+                                                            int64_t ldy, int M, int nst) {
+  const int64_t total = (int64_t)M * nst;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / nst, j = e - i * nst;
+    T s = P[i * ldp + j];
+    for (int t = 1; t < nsplit; ++t) s += P[t * pslice + i * ldp + j];
+    Y[i * ldy + j] = s;
+  }
+}
+
+template <typename T, int NB, bool TRANS>
+static void launch_nb(const GemmArgs<T>& g, hipStream_t s, int grid, T* C, int64_t ldc,
+                      int64_t cslice, int nst, bool avec) {
+  if (avec)
+    hipLaunchKernelGGL((gemm_kernel<T, NB, TRANS, true>), dim3(grid), dim3(kGemmThreads), 0, s, g.A,
+                       g.lda, g.B, g.ldb, C, ldc, cslice, g.M, g.N, g.K, g.kchunk, g.mtiles, nst);
+  else
+    hipLaunchKernelGGL((gemm_kernel<T, NB, TRANS, false>), dim3(grid), dim3(kGemmThreads), 0, s,
+                       g.A, g.lda, g.B, g.ldb, C, ldc, cslice, g.M, g.N, g.K, g.kchunk, g.mtiles, nst);
+}
+
+template <typename T, bool TRANS>
+static void dispatch_nb(const GemmArgs<T>& g, hipStream_t s, int grid, T* C, int64_t ldc,
+                        int64_t cslice, int nst, bool avec) {
+  constexpr int TN = Mfma<T>::TN;
+  const int nb = (int)ceil_div(g.N, TN);
+  if constexpr (sizeof(T) == 4) {
+    switch (nb) {
+      case 1: launch_nb<T, 1, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+      case 2: launch_nb<T, 2, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+      case 3: launch_nb<T, 3, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+      case 4: launch_nb<T, 4, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+      case 5: launch_nb<T, 5, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+      case 6: launch_nb<T, 6, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+      case 7: launch_nb<T, 7, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+      default: launch_nb<T, 8, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+    }
+  } else {
+    switch ((nb + 1) / 2) {  // double: 16-wide blocks, instantiate even counts
+      case 1: launch_nb<T, 2, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+      case 2: launch_nb<T, 4, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+      case 3: launch_nb<T, 6, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+      case 4: launch_nb<T, 8, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+      case 5: launch_nb<T, 10, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+      case 6: launch_nb<T, 12, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+      case 7: launch_nb<T, 14, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+      default: launch_nb<T, 16, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
+    }
+  }
+}
+
+template <typename T>
+int gemm_block_rows() { return 4 * Mfma<T>::TM; }
+template int gemm_block_rows<float>();
+template int gemm_block_rows<double>();
+
+template <typename T>
+int gemm_block_cols(int N) {
+  constexpr int TN = Mfma<T>::TN;
+  int nb = (int)ceil_div(N, TN);
+  if (sizeof(T) == 8) nb = (int)round_up(nb, 2);
+  return nb * TN;
+}
+template int gemm_block_cols<float>(int);
+template int gemm_block_cols<double>(int);
+
+// Launch the main kernel (into C directly when nsplit == 1, else into the
+// partial buffer P) and, for nsplit > 1, the ordered reduction.
+template <typename T>
+hipError_t launch_gemm(GemmArgs<T> g, T* Y, int64_t ldy, int nst, T* P, hipStream_t s,
+                       hipEvent_t ev0, hipEvent_t ev1) {
+  if (g.M <= 0 || nst <= 0) return hipSuccess;
+  const int grid = g.mtiles * g.nsplit;
+  const bool avec = g.avec;
+  if (ev0) hipEventRecord(ev0, s);
+  if (g.nsplit == 1) {
+    if (g.trans) dispatch_nb<T, true>(g, s, grid, Y, ldy, 0, nst, avec);
+    else dispatch_nb<T, false>(g, s, grid, Y, ldy, 0, nst, avec);
+  } else {
+    const int64_t ldp = nst;
+    const int64_t pslice = (int64_t)g.M * ldp;
+    if (g.trans) dispatch_nb<T, true>(g, s, grid, P, ldp, pslice, nst, avec);
+    else dispatch_nb<T, false>(g, s, grid, P, ldp, pslice, nst, avec);
+  }
+  if (ev1) hipEventRecord(ev1, s);
+  if (g.nsplit > 1) {
+    const int64_t total = (int64_t)g.M * nst;
+    const int64_t gr = ceil_div(total, 256);
+    hipLaunchKernelGGL(splitk_reduce_kernel<T>, dim3((unsigned)(gr < 8192 ? gr : 8192)), dim3(256), 0,
+                       s, P, (int64_t)nst, (int64_t)g.M * nst, g.nsplit, Y, ldy, g.M, nst);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_gemm<float>(GemmArgs<float>, float*, int64_t, int, float*, hipStream_t,
+                                       hipEvent_t, hipEvent_t);
+template hipError_t launch_gemm<double>(GemmArgs<double>, double*, int64_t, int, double*,
+                                        hipStream_t, hipEvent_t, hipEvent_t);
+
+}  // namespace rqlp

@@ -1,0 +1,92 @@
+// Host-side launch functions of the gfx950 kernels (one translation unit per
+// kernel family).  Every launcher enqueues on `s` and returns the launch
+// status; none synchronizes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rqlp {
+
+// ---- Gaussian test matrix (k_gaussian.hip) ----
+template <typename T>
+hipError_t launch_gaussian(uint64_t seed, uint64_t key1, int64_t rows, int64_t cols, T* out,
+                           int64_t ldo, hipStream_t s);
+template <typename T>
+hipError_t launch_zero_cols(T* out, int64_t rows, int64_t c0, int64_t c1, int64_t ld, hipStream_t s);
+
+// ---- dense products (k_gemm.hip) ----
+template <typename T>
+struct GemmArgs {
+  const T* A;      // NN: M x K (lda); TN: K x M (lda)
+  int64_t lda;
+  const T* B;      // K x N (ldb)
+  int64_t ldb;
+  int M, N, K;     // output M x N, reduction K
+  int trans;       // 0: Y = A B, 1: Y = A^T B
+  int mtiles;      // ceil(M / gemm_block_rows)
+  int nsplit;      // split-K count
+  int kchunk;      // reduction length per split (multiple of 16)
+  bool avec;       // A rows 16-byte aligned: vector loads
+};
+template <typename T> int gemm_block_rows();
+template <typename T> int gemm_block_cols(int N);
+// Y (M x nst, ldy) = op(A) B; columns [N, nst) of Y are written as zero.
+// P: partial buffer of nsplit * M * nst elements (unused when nsplit == 1).
+// ev0/ev1 (may be null) are recorded around the main kernel.
+template <typename T>
+hipError_t launch_gemm(GemmArgs<T> g, T* Y, int64_t ldy, int nst, T* P, hipStream_t s,
+                       hipEvent_t ev0, hipEvent_t ev1);
+
+// ---- float64 Gram matrix (k_gram.hip) ----
+// G (dp x dp, ld dp, float64, full symmetric) = Y^T Y over rows [0, rows),
+// columns [0, d) of Y (ldy); entries outside d x d are zero.  Partials:
+// nchunks * dp * dp doubles in P.  Sets info->nonfinite on NaN/Inf.
+template <typename T>
+hipError_t launch_gram(const T* Y, int64_t ldy, int64_t rows, int d, int dp, double* P,
+                       int nchunks, double* G, void* info, hipStream_t s, hipEvent_t ev0,
+                       hipEvent_t ev1);
+int gram_chunks(int64_t rows, int dp);
+
+// ---- float64 Cholesky (k_chol.hip) ----
+// G = R^T R for the d x d leading block of G (ld dp).  Writes R (upper,
+// dp x dp, ld dp, identity beyond d; rows of dependent columns are e_j^T),
+// Rinv16 (inverses of the dp/16 diagonal 16x16 blocks of R, row-major
+// 16x16 each), flags[j] = 1 for dependent columns (j < dp).  Updates info.
+hipError_t launch_chol(const double* G, int d, int dp, double* R, double* Rinv16, int32_t* flags,
+                       void* info, int pass_id, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+
+// ---- triangular solve Q = Y R^-1 (k_apply.hip) ----
+// Y: rows x dp (ldy, type Tin); out1 (ld1, first `ncols1` columns, type
+// Tout) and optional out2 (ld2, first `ncols2` columns).  Dependent columns (flags) are replaced
+// by Gaussian columns of stream (seed, key1) divided by sqrt(rows).
+template <typename Tin, typename Tout>
+hipError_t launch_apply(const Tin* Y, int64_t ldy, int64_t rows, int d, int dp, const double* R,
+                        const double* Rinv16, const int32_t* flags, Tout* out1, int64_t ld1,
+                        int ncols1, Tout* out2, int64_t ld2, int ncols2, uint64_t seed,
+                        uint64_t key1, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+
+// ---- small d x d helpers (k_small.hip) ----
+// L (d x d, ld ldl, type T) = (R2 * R1')^T where R1' is R1 with the rows of
+// dependent columns (flags1) zeroed; R2, R1 upper, ld dp.
+template <typename T>
+hipError_t launch_form_l(const double* R2, const double* R1, const int32_t* flags1, int d, int dp,
+                         T* L, int64_t ldl, hipStream_t s);
+// R (d x d, ld d, type T) = R2 * R1' (upper triangular)
+template <typename T>
+hipError_t launch_form_r(const double* R2, const double* R1, const int32_t* flags1, int d, int dp,
+                         T* R, int64_t ldr, hipStream_t s);
+hipError_t launch_info_reset(void* info, hipStream_t s);
+
+// ---- CSR (k_csr.hip) ----
+template <typename T>
+hipError_t launch_spmm(const int32_t* rowptr, const int32_t* colidx, const T* vals, int64_t rows,
+                       const T* X, int64_t ldx, int d, T* Y, int64_t ldy, int nst, hipStream_t s,
+                       hipEvent_t ev0, hipEvent_t ev1);
+size_t csr_transpose_scratch_bytes(int64_t m, int64_t n, int64_t nnz);
+template <typename T>
+hipError_t launch_csr_transpose(const int32_t* rowptr, const int32_t* colidx, const T* vals,
+                                int64_t m, int64_t n, int64_t nnz, int32_t* rowptr_t,
+                                int32_t* colidx_t, T* vals_t, void* scratch, hipStream_t s);
+
+}  // namespace rqlp

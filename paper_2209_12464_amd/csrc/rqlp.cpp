@@ -1,0 +1,596 @@
+// Host runtime behind include/rqlp.h: argument checks, workspace planning,
+// split-K planning and the launch sequence of the method (Algorithm 1 with
+// the power iteration of Algorithm 2, column-sketch orientation).  All work
+// goes on the caller's stream; nothing here synchronizes except
+// rqlp_destroy, rqlp_get_info and rqlp_get_timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/rqlp.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace rqlp;
+
+struct rqlp_ctx {
+  int device = 0;
+  DevInfo* info = nullptr;      // device record
+  void* ws_own = nullptr;       // internal workspace (grown on demand)
+  size_t ws_own_bytes = 0;
+  bool timing = false;
+  struct Pair { hipEvent_t a, b; };
+  std::vector<Pair> recorded[RQLP_KT_COUNT];
+  std::vector<hipEvent_t> pool;
+  double total_ms[RQLP_KT_COUNT] = {0};
+  int64_t launches[RQLP_KT_COUNT] = {0};
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return RQLP_ERR_HIP;          \
+  } while (0)
+
+// ---- timing ---------------------------------------------------------------
+struct EvPair { hipEvent_t a = nullptr, b = nullptr; };
+
+hipEvent_t take_event(rqlp_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+EvPair timer(rqlp_ctx* c, rqlp_kernel_class k) {
+  EvPair p;
+  if (!c->timing) return p;
+  p.a = take_event(c);
+  p.b = take_event(c);
+  if (p.a && p.b) c->recorded[k].push_back({p.a, p.b});
+  return p;
+}
+
+void resolve_timing(rqlp_ctx* c) {
+  for (int k = 0; k < RQLP_KT_COUNT; ++k) {
+    for (auto& pr : c->recorded[k]) {
+      float ms = 0.f;
+      if (hipEventSynchronize(pr.b) == hipSuccess && hipEventElapsedTime(&ms, pr.a, pr.b) == hipSuccess) {
+        c->total_ms[k] += ms;
+        c->launches[k] += 1;
+      }
+      c->pool.push_back(pr.a);
+      c->pool.push_back(pr.b);
+    }
+    c->recorded[k].clear();
+  }
+}
+
+// ---- planning -------------------------------------------------------------
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int padded_d(int d) { return (int)round_up(d, 32); }
+
+int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  if (!v || !*v) return dflt;
+  return atoi(v);
+}
+
+template <typename T>
+GemmArgs<T> plan_gemm(int trans, const T* A, int64_t lda, const T* B, int64_t ldb, int M, int N, int K) {
+  GemmArgs<T> g;
+  g.A = A;
+  g.lda = lda;
+  g.B = B;
+  g.ldb = ldb;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.trans = trans;
+  const int bm = gemm_block_rows<T>();
+  g.mtiles = (int)ceil_div(M, bm);
+  const int target = std::max(1, env_int("RQLP_GEMM_TARGET_WGS", 512));
+  const int64_t kmin = std::max(16, env_int("RQLP_GEMM_MIN_KCHUNK", 256));
+  int64_t ns = ceil_div(target, g.mtiles);
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, ceil_div(K, kmin)));
+  ns = std::max<int64_t>(1, ns);
+  g.kchunk = (int)round_up(ceil_div(std::max(K, 1), ns), 16);
+  g.nsplit = (int)ceil_div(std::max(K, 1), g.kchunk);
+  const int vec = 16 / (int)sizeof(T);
+  g.avec = (lda % vec == 0) && (((uintptr_t)A & 15) == 0);
+  return g;
+}
+
+template <typename T>
+size_t gemm_partial_elems(int M, int K, int dp) {
+  GemmArgs<T> g = plan_gemm<T>(0, (const T*)nullptr, 16, (const T*)nullptr, dp, M, dp, K);
+  return g.nsplit > 1 ? (size_t)g.nsplit * M * dp : 0;
+}
+
+// Layout of the dense / CSR decomposition workspace.
+struct Layout {
+  size_t om, yb, qi, q1, part, gp, g, r1, r2, rinv, flags, csr_rt, csr_ct, csr_vt, csr_scr, total;
+};
+
+template <typename T>
+Layout layout(int64_t m, int64_t n, int d, bool sparse, int64_t nnz) {
+  const int dp = padded_d(d);
+  const int64_t mx = std::max(m, n);
+  Layout L;
+  size_t off = 0;
+  auto put = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  L.om = put((size_t)n * dp * sizeof(T));
+  L.yb = put((size_t)mx * dp * sizeof(T));
+  L.qi = put((size_t)m * dp * sizeof(T));
+  L.q1 = put((size_t)mx * dp * sizeof(double));
+  size_t pe = 0;
+  if (!sparse) pe = std::max(gemm_partial_elems<T>((int)m, (int)n, dp), gemm_partial_elems<T>((int)n, (int)m, dp));
+  L.part = put(pe * sizeof(T));
+  const int gc = std::max(gram_chunks(m, dp), gram_chunks(n, dp));
+  L.gp = put((size_t)gc * dp * dp * sizeof(double));
+  L.g = put((size_t)dp * dp * sizeof(double));
+  L.r1 = put((size_t)dp * dp * sizeof(double));
+  L.r2 = put((size_t)dp * dp * sizeof(double));
+  L.rinv = put((size_t)dp * kTile * sizeof(double));
+  L.flags = put((size_t)2 * dp * sizeof(int32_t));
+  if (sparse) {
+    L.csr_rt = put((size_t)(n + 1) * sizeof(int32_t));
+    L.csr_ct = put((size_t)nnz * sizeof(int32_t));
+    L.csr_vt = put((size_t)nnz * sizeof(T));
+    L.csr_scr = put(csr_transpose_scratch_bytes(m, n, nnz));
+  } else {
+    L.csr_rt = L.csr_ct = L.csr_vt = L.csr_scr = 0;
+  }
+  L.total = off + 256;
+  return L;
+}
+
+rqlp_status get_workspace(rqlp_ctx* c, void* ws, size_t ws_bytes, size_t need, char** base) {
+  if (ws) {
+    if (ws_bytes < need) return RQLP_ERR_OUT_OF_MEMORY;
+    *base = (char*)ws;
+  } else {
+    if (c->ws_own_bytes < need) {
+      if (c->ws_own) {
+        if (hipDeviceSynchronize() != hipSuccess) return RQLP_ERR_HIP;
+        hipFree(c->ws_own);
+        c->ws_own = nullptr;
+        c->ws_own_bytes = 0;
+      }
+      if (hipMalloc(&c->ws_own, need) != hipSuccess) return RQLP_ERR_OUT_OF_MEMORY;
+      c->ws_own_bytes = need;
+    }
+    *base = (char*)c->ws_own;
+  }
+  // 256-byte alignment of the base
+  *base = (char*)(((uintptr_t)*base + 255) & ~(uintptr_t)255);
+  return RQLP_OK;
+}
+
+struct Bufs {
+  double *q1, *gp, *g, *r1, *r2, *rinv;
+  int32_t* flags;
+  int gchunks;
+};
+
+// Key of the completion stream of one CholeskyQR pass.
+uint64_t completion_key(int orth_index, int pass) {
+  return kSketchKey1 + 1 + 2 * (uint64_t)orth_index + (uint64_t)pass;
+}
+
+// orth()/qr() of a rows x d matrix Y (ld ldy) by CholeskyQR2.  Pass 1 writes
+// the float64 basis Q1; pass 2 writes out1 (ld1, ncols1 columns) and
+// optionally out2.  R1, R2 and the flags of both passes stay in `b`.
+template <typename T>
+rqlp_status cholqr2(rqlp_ctx* c, const T* Y, int64_t ldy, int64_t rows, int d, const Bufs& b,
+                    T* out1, int64_t ld1, int ncols1, T* out2, int64_t ld2, int ncols2,
+                    uint64_t seed, int orth_index, hipStream_t s) {
+  const int dp = padded_d(d);
+  const int gch = gram_chunks(rows, dp);
+  EvPair t;
+  t = timer(c, RQLP_KT_GRAM);
+  HIP_TRY(launch_gram<T>(Y, ldy, rows, d, dp, b.gp, gch, b.g, c->info, s, t.a, t.b));
+  t = timer(c, RQLP_KT_CHOL);
+  HIP_TRY(launch_chol(b.g, d, dp, b.r1, b.rinv, b.flags, c->info, orth_index, s, t.a, t.b));
+  t = timer(c, RQLP_KT_APPLY);
+  HIP_TRY((launch_apply<T, double>(Y, ldy, rows, d, dp, b.r1, b.rinv, b.flags, b.q1, dp, dp, nullptr, 0, 0,
+                                   seed, completion_key(orth_index, 0), s, t.a, t.b)));
+  t = timer(c, RQLP_KT_GRAM);
+  HIP_TRY(launch_gram<double>(b.q1, dp, rows, d, dp, b.gp, gch, b.g, c->info, s, t.a, t.b));
+  t = timer(c, RQLP_KT_CHOL);
+  HIP_TRY(launch_chol(b.g, d, dp, b.r2, b.rinv, b.flags + dp, c->info, orth_index, s, t.a, t.b));
+  t = timer(c, RQLP_KT_APPLY);
+  HIP_TRY((launch_apply<double, T>(b.q1, dp, rows, d, dp, b.r2, b.rinv, b.flags + dp, out1, ld1, ncols1, out2,
+                                   ld2, ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b)));
+  return RQLP_OK;
+}
+
+template <typename T>
+rqlp_status gemm(rqlp_ctx* c, int trans, const T* A, int64_t lda, int64_t m, int64_t n, const T* X,
+                 int64_t ldx, int d, T* Y, int64_t ldy, int nst, T* P, hipStream_t s) {
+  // trans = 0: Y (m x nst) = A X (K = n); trans = 1: Y (n x nst) = A^T X (K = m)
+  const int M = (int)(trans ? n : m), K = (int)(trans ? m : n);
+  GemmArgs<T> g = plan_gemm<T>(trans, A, lda, X, ldx, M, d, K);
+  EvPair t = timer(c, trans ? RQLP_KT_GEMM_TN : RQLP_KT_GEMM_NN);
+  HIP_TRY(launch_gemm<T>(g, Y, ldy, nst, P, s, t.a, t.b));
+  return RQLP_OK;
+}
+
+bool valid_prec(rqlp_precision p) { return p == RQLP_FP64 || p == RQLP_FP32 || p == RQLP_BF16_REFINED; }
+
+rqlp_status check_common(int64_t m, int64_t n, int k, int p, int q, rqlp_precision prec) {
+  if (m < 1 || n < 1 || k < 1 || p < 0 || q < 0 || !valid_prec(prec)) return RQLP_ERR_INVALID_ARG;
+  const int64_t d = (int64_t)k + p;
+  if (d > std::min(m, n)) return RQLP_ERR_INVALID_ARG;
+  if (m > INT32_MAX || n > INT32_MAX) return RQLP_ERR_UNSUPPORTED;
+  if (d > kDMax) return RQLP_ERR_UNSUPPORTED;
+  if (prec == RQLP_BF16_REFINED) return RQLP_ERR_UNSUPPORTED;
+  return RQLP_OK;
+}
+
+// The method's launch sequence for dense (mulA = GEMM) or CSR (mulA = SpMM) A.
+template <typename T, typename MulA, typename MulAt>
+rqlp_status run_method(rqlp_ctx* c, char* base, const Layout& Lo, int64_t m, int64_t n, int k, int p,
+                       int q, uint64_t seed, T* Q, T* Lout, T* V, hipStream_t s, MulA mulA, MulAt mulAt) {
+  const int d = k + p, dp = padded_d(d);
+  T* om = (T*)(base + Lo.om);
+  T* yb = (T*)(base + Lo.yb);
+  T* qi = (T*)(base + Lo.qi);
+  Bufs b;
+  b.q1 = (double*)(base + Lo.q1);
+  b.gp = (double*)(base + Lo.gp);
+  b.g = (double*)(base + Lo.g);
+  b.r1 = (double*)(base + Lo.r1);
+  b.r2 = (double*)(base + Lo.r2);
+  b.rinv = (double*)(base + Lo.rinv);
+  b.flags = (int32_t*)(base + Lo.flags);
+  rqlp_status st;
+  HIP_TRY(launch_info_reset(c->info, s));
+  // Omega (n x d, ld dp), then Y = A Omega and Q = orth(Y)
+  HIP_TRY(launch_gaussian<T>(seed, kSketchKey1, n, d, om, dp, s));
+  if ((st = mulA(om, yb)) != RQLP_OK) return st;
+  int oi = 1;
+  if ((st = cholqr2<T>(c, yb, dp, m, d, b, qi, dp, dp, q == 0 ? Q : nullptr, d, d, seed, oi++, s)) != RQLP_OK)
+    return st;
+  for (int it = 1; it <= q; ++it) {
+    // W = orth(A^T Q) (stored in the Omega buffer), Q = orth(A W)
+    if ((st = mulAt(qi, yb)) != RQLP_OK) return st;
+    if ((st = cholqr2<T>(c, yb, dp, n, d, b, om, dp, dp, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
+    if ((st = mulA(om, yb)) != RQLP_OK) return st;
+    if ((st = cholqr2<T>(c, yb, dp, m, d, b, qi, dp, dp, it == q ? Q : nullptr, d, d, seed, oi++, s)) != RQLP_OK)
+      return st;
+  }
+  // B^T = A^T Q; [V, R] = qr(B^T); L = R^T
+  if ((st = mulAt(qi, yb)) != RQLP_OK) return st;
+  if ((st = cholqr2<T>(c, yb, dp, n, d, b, V, d, d, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
+  HIP_TRY(launch_form_l<T>(b.r2, b.r1, b.flags, d, dp, Lout, d, s));
+  return RQLP_OK;
+}
+
+template <typename T>
+rqlp_status decompose_dense(rqlp_ctx* c, const T* A, int64_t m, int64_t n, int64_t lda, int k, int p, int q,
+                            uint64_t seed, T* Q, T* L, T* V, void* ws, size_t ws_bytes, hipStream_t s) {
+  const int d = k + p, dp = padded_d(d);
+  const Layout Lo = layout<T>(m, n, d, false, 0);
+  char* base = nullptr;
+  rqlp_status st = get_workspace(c, ws, ws_bytes, Lo.total, &base);
+  if (st != RQLP_OK) return st;
+  T* part = (T*)(base + Lo.part);
+  auto mulA = [&](const T* X, T* Y) { return gemm<T>(c, 0, A, lda, m, n, X, dp, d, Y, dp, dp, part, s); };
+  auto mulAt = [&](const T* X, T* Y) { return gemm<T>(c, 1, A, lda, m, n, X, dp, d, Y, dp, dp, part, s); };
+  return run_method<T>(c, base, Lo, m, n, k, p, q, seed, Q, L, V, s, mulA, mulAt);
+}
+
+template <typename T>
+rqlp_status decompose_csr(rqlp_ctx* c, const int32_t* rowptr, const int32_t* colidx, const T* vals, int64_t m,
+                          int64_t n, int64_t nnz, int k, int p, int q, uint64_t seed, T* Q, T* L, T* V, void* ws,
+                          size_t ws_bytes, hipStream_t s) {
+  const int d = k + p, dp = padded_d(d);
+  const Layout Lo = layout<T>(m, n, d, true, nnz);
+  char* base = nullptr;
+  rqlp_status st = get_workspace(c, ws, ws_bytes, Lo.total, &base);
+  if (st != RQLP_OK) return st;
+  int32_t* rt = (int32_t*)(base + Lo.csr_rt);
+  int32_t* ct = (int32_t*)(base + Lo.csr_ct);
+  T* vt = (T*)(base + Lo.csr_vt);
+  HIP_TRY(launch_csr_transpose<T>(rowptr, colidx, vals, m, n, nnz, rt, ct, vt, base + Lo.csr_scr, s));
+  auto mulA = [&](const T* X, T* Y) -> rqlp_status {
+    EvPair t = timer(c, RQLP_KT_SPMM);
+    HIP_TRY(launch_spmm<T>(rowptr, colidx, vals, m, X, dp, d, Y, dp, dp, s, t.a, t.b));
+    return RQLP_OK;
+  };
+  auto mulAt = [&](const T* X, T* Y) -> rqlp_status {
+    EvPair t = timer(c, RQLP_KT_SPMM);
+    HIP_TRY(launch_spmm<T>(rt, ct, vt, n, X, dp, d, Y, dp, dp, s, t.a, t.b));
+    return RQLP_OK;
+  };
+  return run_method<T>(c, base, Lo, m, n, k, p, q, seed, Q, L, V, s, mulA, mulAt);
+}
+
+size_t orth_ws_bytes(int64_t rows, int d, rqlp_precision prec) {
+  const int dp = padded_d(d);
+  size_t off = 0;
+  auto put = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  put((size_t)rows * dp * sizeof(double));                        // q1
+  put((size_t)gram_chunks(rows, dp) * dp * dp * sizeof(double));  // gp
+  put((size_t)dp * dp * sizeof(double) * 3);                      // g, r1, r2
+  put((size_t)dp * kTile * sizeof(double));                       // rinv
+  put((size_t)2 * dp * sizeof(int32_t));                          // flags
+  put((size_t)rows * dp * (prec == RQLP_FP64 ? 8 : 4));           // padded copy of the output
+  (void)prec;
+  return off + 256;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+rqlp_status rqlp_create(rqlp_ctx** ctx, int device) {
+  if (!ctx) return RQLP_ERR_INVALID_ARG;
+  *ctx = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) return RQLP_ERR_HIP;
+  if (device < 0 || device >= count) return RQLP_ERR_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return RQLP_ERR_HIP;
+  rqlp_ctx* c = new (std::nothrow) rqlp_ctx();
+  if (!c) return RQLP_ERR_OUT_OF_MEMORY;
+  c->device = device;
+  if (hipMalloc(&c->info, sizeof(DevInfo)) != hipSuccess) {
+    delete c;
+    return RQLP_ERR_OUT_OF_MEMORY;
+  }
+  if (hipMemset(c->info, 0, sizeof(DevInfo)) != hipSuccess) {
+    hipFree(c->info);
+    delete c;
+    return RQLP_ERR_HIP;
+  }
+  *ctx = c;
+  return RQLP_OK;
+}
+
+rqlp_status rqlp_destroy(rqlp_ctx* c) {
+  if (!c) return RQLP_OK;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  resolve_timing(c);
+  for (hipEvent_t e : c->pool) hipEventDestroy(e);
+  if (c->ws_own) hipFree(c->ws_own);
+  if (c->info) hipFree(c->info);
+  delete c;
+  return RQLP_OK;
+}
+
+size_t rqlp_workspace_size(int64_t m, int64_t n, int k, int p, int q, rqlp_precision prec) {
+  if (check_common(m, n, k, p, q, prec) != RQLP_OK) return 0;
+  return prec == RQLP_FP64 ? layout<double>(m, n, k + p, false, 0).total
+                           : layout<float>(m, n, k + p, false, 0).total;
+}
+
+size_t rqlp_workspace_size_csr(int64_t m, int64_t n, int64_t nnz, int k, int p, int q, rqlp_precision prec) {
+  if (check_common(m, n, k, p, q, prec) != RQLP_OK || nnz < 0 || nnz > INT32_MAX) return 0;
+  return prec == RQLP_FP64 ? layout<double>(m, n, k + p, true, nnz).total
+                           : layout<float>(m, n, k + p, true, nnz).total;
+}
+
+rqlp_status rqlp_decompose(rqlp_ctx* c, const void* A, int64_t m, int64_t n, int64_t lda, int k, int p, int q,
+                           rqlp_precision prec, uint64_t seed, void* Q, void* L, void* V, void* ws,
+                           size_t ws_bytes, void* stream) {
+  if (!c || !A || !Q || !L || !V) return RQLP_ERR_INVALID_ARG;
+  rqlp_status st = check_common(m, n, k, p, q, prec);
+  if (st != RQLP_OK) return st;
+  if (lda < n) return RQLP_ERR_INVALID_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == RQLP_FP64)
+    return decompose_dense<double>(c, (const double*)A, m, n, lda, k, p, q, seed, (double*)Q, (double*)L,
+                                   (double*)V, ws, ws_bytes, s);
+  return decompose_dense<float>(c, (const float*)A, m, n, lda, k, p, q, seed, (float*)Q, (float*)L, (float*)V,
+                                ws, ws_bytes, s);
+}
+
+rqlp_status rqlp_decompose_csr(rqlp_ctx* c, const int32_t* rowptr, const int32_t* colidx, const void* vals,
+                               int64_t m, int64_t n, int64_t nnz, int k, int p, int q, rqlp_precision prec,
+                               uint64_t seed, void* Q, void* L, void* V, void* ws, size_t ws_bytes,
+                               void* stream) {
+  if (!c || !rowptr || !Q || !L || !V) return RQLP_ERR_INVALID_ARG;
+  if (nnz < 0 || nnz > INT32_MAX) return RQLP_ERR_INVALID_ARG;
+  if (nnz > 0 && (!colidx || !vals)) return RQLP_ERR_INVALID_ARG;
+  rqlp_status st = check_common(m, n, k, p, q, prec);
+  if (st != RQLP_OK) return st;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == RQLP_FP64)
+    return decompose_csr<double>(c, rowptr, colidx, (const double*)vals, m, n, nnz, k, p, q, seed, (double*)Q,
+                                 (double*)L, (double*)V, ws, ws_bytes, s);
+  return decompose_csr<float>(c, rowptr, colidx, (const float*)vals, m, n, nnz, k, p, q, seed, (float*)Q,
+                              (float*)L, (float*)V, ws, ws_bytes, s);
+}
+
+rqlp_status rqlp_get_info(rqlp_ctx* c, rqlp_info* out) {
+  if (!c || !out) return RQLP_ERR_INVALID_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  DevInfo h;
+  if (hipMemcpy(&h, c->info, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return RQLP_ERR_HIP;
+  out->completed_cols = h.completed_cols;
+  out->breakdown_pass = h.breakdown_pass;
+  out->nonfinite = h.nonfinite;
+  out->status = h.nonfinite ? RQLP_ERR_NUMERICAL : RQLP_OK;
+  return RQLP_OK;
+}
+
+const char* rqlp_status_string(rqlp_status s) {
+  switch (s) {
+    case RQLP_OK: return "success";
+    case RQLP_ERR_INVALID_ARG: return "invalid argument";
+    case RQLP_ERR_UNSUPPORTED: return "unsupported by this build";
+    case RQLP_ERR_OUT_OF_MEMORY: return "workspace too small or allocation failed";
+    case RQLP_ERR_HIP: return "HIP runtime error";
+    case RQLP_ERR_NUMERICAL: return "non-finite values encountered";
+  }
+  return "unknown status";
+}
+
+// ---- step entry points ----------------------------------------------------
+
+rqlp_status rqlp_gaussian(rqlp_ctx* c, uint64_t seed, uint32_t stream_id, int64_t rows, int64_t cols,
+                          rqlp_precision prec, void* out, int64_t ldo, void* stream) {
+  if (!c || !out || rows < 0 || cols < 0 || ldo < cols || !valid_prec(prec)) return RQLP_ERR_INVALID_ARG;
+  if (prec == RQLP_BF16_REFINED) return RQLP_ERR_UNSUPPORTED;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t key1 = kSketchKey1 + stream_id;
+  if (prec == RQLP_FP64) HIP_TRY(launch_gaussian<double>(seed, key1, rows, cols, (double*)out, ldo, s));
+  else HIP_TRY(launch_gaussian<float>(seed, key1, rows, cols, (float*)out, ldo, s));
+  return RQLP_OK;
+}
+
+size_t rqlp_gemm_workspace_size(int trans, int64_t m, int64_t n, int d, rqlp_precision prec) {
+  if (m < 1 || n < 1 || d < 1 || d > kDMax || m > INT32_MAX || n > INT32_MAX) return 0;
+  const int dp = padded_d(d);
+  const int M = (int)(trans ? n : m), K = (int)(trans ? m : n);
+  const size_t e = prec == RQLP_FP64 ? gemm_partial_elems<double>(M, K, dp) * 8 : gemm_partial_elems<float>(M, K, dp) * 4;
+  return e + 512;
+}
+
+rqlp_status rqlp_gemm(rqlp_ctx* c, int trans, const void* A, int64_t m, int64_t n, int64_t lda, const void* X,
+                      int64_t ldx, int d, void* Y, int64_t ldy, rqlp_precision prec, void* ws, size_t ws_bytes,
+                      void* stream) {
+  if (!c || !A || !X || !Y || m < 1 || n < 1 || d < 1 || lda < n || ldx < d || ldy < d || !valid_prec(prec) ||
+      (trans != 0 && trans != 1))
+    return RQLP_ERR_INVALID_ARG;
+  if (d > kDMax || m > INT32_MAX || n > INT32_MAX || prec == RQLP_BF16_REFINED) return RQLP_ERR_UNSUPPORTED;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  const size_t need = rqlp_gemm_workspace_size(trans, m, n, d, prec);
+  char* base = nullptr;
+  rqlp_status st = get_workspace(c, ws, ws_bytes, need, &base);
+  if (st != RQLP_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // the partial buffer is laid out with row length d here (nst = d)
+  if (prec == RQLP_FP64)
+    return gemm<double>(c, trans, (const double*)A, lda, m, n, (const double*)X, ldx, d, (double*)Y, ldy, d,
+                        (double*)base, s);
+  return gemm<float>(c, trans, (const float*)A, lda, m, n, (const float*)X, ldx, d, (float*)Y, ldy, d,
+                     (float*)base, s);
+}
+
+size_t rqlp_orth_workspace_size(int64_t rows, int d, rqlp_precision prec) {
+  if (rows < 1 || d < 1 || d > rows || d > kDMax || !valid_prec(prec)) return 0;
+  return orth_ws_bytes(rows, d, prec);
+}
+
+rqlp_status rqlp_orth(rqlp_ctx* c, const void* Y, int64_t rows, int d, int64_t ldy, void* Q, int64_t ldq,
+                      void* R, rqlp_precision prec, uint64_t seed, void* ws, size_t ws_bytes, void* stream) {
+  if (!c || !Y || !Q || rows < 1 || d < 1 || d > rows || ldy < d || ldq < d || !valid_prec(prec))
+    return RQLP_ERR_INVALID_ARG;
+  if (d > kDMax || prec == RQLP_BF16_REFINED) return RQLP_ERR_UNSUPPORTED;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  const size_t need = orth_ws_bytes(rows, d, prec);
+  char* base = nullptr;
+  rqlp_status st = get_workspace(c, ws, ws_bytes, need, &base);
+  if (st != RQLP_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int dp = padded_d(d);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { char* p = base + off; off += align256(bytes); return p; };
+  Bufs b;
+  b.q1 = (double*)take((size_t)rows * dp * sizeof(double));
+  b.gp = (double*)take((size_t)gram_chunks(rows, dp) * dp * dp * sizeof(double));
+  char* gr = take((size_t)dp * dp * sizeof(double) * 3);
+  b.g = (double*)gr;
+  b.r1 = b.g + (size_t)dp * dp;
+  b.r2 = b.r1 + (size_t)dp * dp;
+  b.rinv = (double*)take((size_t)dp * kTile * sizeof(double));
+  b.flags = (int32_t*)take((size_t)2 * dp * sizeof(int32_t));
+  HIP_TRY(launch_info_reset(c->info, s));
+  if (prec == RQLP_FP64) {
+    st = cholqr2<double>(c, (const double*)Y, ldy, rows, d, b, (double*)Q, ldq, d, nullptr, 0, 0, seed, 1, s);
+    if (st == RQLP_OK && R) HIP_TRY(launch_form_r<double>(b.r2, b.r1, b.flags, d, dp, (double*)R, d, s));
+  } else {
+    st = cholqr2<float>(c, (const float*)Y, ldy, rows, d, b, (float*)Q, ldq, d, nullptr, 0, 0, seed, 1, s);
+    if (st == RQLP_OK && R) HIP_TRY(launch_form_r<float>(b.r2, b.r1, b.flags, d, dp, (float*)R, d, s));
+  }
+  return st;
+}
+
+rqlp_status rqlp_spmm(rqlp_ctx* c, const int32_t* rowptr, const int32_t* colidx, const void* vals, int64_t rows,
+                      int64_t cols, int64_t nnz, const void* X, int64_t ldx, int d, void* Y, int64_t ldy,
+                      rqlp_precision prec, void* stream) {
+  if (!c || !rowptr || !X || !Y || rows < 0 || cols < 1 || nnz < 0 || d < 1 || ldx < d || ldy < d ||
+      !valid_prec(prec) || (nnz > 0 && (!colidx || !vals)))
+    return RQLP_ERR_INVALID_ARG;
+  if (d > kDMax || prec == RQLP_BF16_REFINED || nnz > INT32_MAX) return RQLP_ERR_UNSUPPORTED;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  EvPair t = timer(c, RQLP_KT_SPMM);
+  if (prec == RQLP_FP64)
+    HIP_TRY(launch_spmm<double>(rowptr, colidx, (const double*)vals, rows, (const double*)X, ldx, d, (double*)Y,
+                                ldy, d, s, t.a, t.b));
+  else
+    HIP_TRY(launch_spmm<float>(rowptr, colidx, (const float*)vals, rows, (const float*)X, ldx, d, (float*)Y, ldy,
+                               d, s, t.a, t.b));
+  return RQLP_OK;
+}
+
+size_t rqlp_csr_transpose_workspace_size(int64_t m, int64_t n, int64_t nnz) {
+  if (m < 0 || n < 1 || nnz < 0) return 0;
+  return csr_transpose_scratch_bytes(m, n, nnz) + 256;
+}
+
+rqlp_status rqlp_csr_transpose(rqlp_ctx* c, const int32_t* rowptr, const int32_t* colidx, const void* vals,
+                               int64_t m, int64_t n, int64_t nnz, rqlp_precision prec, int32_t* rowptr_t,
+                               int32_t* colidx_t, void* vals_t, void* ws, size_t ws_bytes, void* stream) {
+  if (!c || !rowptr || !rowptr_t || m < 0 || n < 1 || nnz < 0 || !valid_prec(prec) ||
+      (nnz > 0 && (!colidx || !vals || !colidx_t || !vals_t)))
+    return RQLP_ERR_INVALID_ARG;
+  if (prec == RQLP_BF16_REFINED || nnz > INT32_MAX || m > INT32_MAX || n > INT32_MAX) return RQLP_ERR_UNSUPPORTED;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  char* base = nullptr;
+  rqlp_status st = get_workspace(c, ws, ws_bytes, rqlp_csr_transpose_workspace_size(m, n, nnz), &base);
+  if (st != RQLP_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == RQLP_FP64)
+    HIP_TRY(launch_csr_transpose<double>(rowptr, colidx, (const double*)vals, m, n, nnz, rowptr_t, colidx_t,
+                                         (double*)vals_t, base, s));
+  else
+    HIP_TRY(launch_csr_transpose<float>(rowptr, colidx, (const float*)vals, m, n, nnz, rowptr_t, colidx_t,
+                                        (float*)vals_t, base, s));
+  return RQLP_OK;
+}
+
+rqlp_status rqlp_set_timing(rqlp_ctx* c, int enabled) {
+  if (!c) return RQLP_ERR_INVALID_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  resolve_timing(c);
+  for (int k = 0; k < RQLP_KT_COUNT; ++k) {
+    c->total_ms[k] = 0;
+    c->launches[k] = 0;
+  }
+  c->timing = enabled != 0;
+  return RQLP_OK;
+}
+
+rqlp_status rqlp_get_timing(rqlp_ctx* c, rqlp_kernel_class cls, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches || (int)cls < 0 || (int)cls >= RQLP_KT_COUNT) return RQLP_ERR_INVALID_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  resolve_timing(c);
+  *total_ms = c->total_ms[cls];
+  *launches = c->launches[cls];
+  return RQLP_OK;
+}
+
+}  // extern "C"

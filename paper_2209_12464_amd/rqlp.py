@@ -1,0 +1,281 @@
+"""ctypes binding of librqlp.so (include/rqlp.h), same names as the C ABI.
+
+Argument marshalling only: torch tensors supply device pointers and the
+current HIP stream; every step runs in the library's HIP kernels.  Loading
+fails loudly when the library is missing -- there is no fallback path.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librqlp.so")
+
+RQLP_OK = 0
+RQLP_FP64, RQLP_FP32, RQLP_BF16_REFINED = 0, 1, 2
+KT_GEMM_NN, KT_GEMM_TN, KT_SPMM, KT_GRAM, KT_CHOL, KT_APPLY = range(6)
+KERNEL_CLASSES = {"gemm_nn": KT_GEMM_NN, "gemm_tn": KT_GEMM_TN, "spmm": KT_SPMM,
+                  "gram": KT_GRAM, "chol": KT_CHOL, "apply": KT_APPLY}
+
+
+class RqlpError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib().rqlp_status_string(status).decode() if _LIB is not None else str(status)
+        super().__init__(f"{where}: {msg} (status {status})")
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("completed_cols", ctypes.c_int32),
+                ("breakdown_pass", ctypes.c_int32), ("nonfinite", ctypes.c_int32)]
+
+
+_LIB = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_INT = ctypes.c_int
+_U64 = ctypes.c_uint64
+_SZ = ctypes.c_size_t
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2209_12464_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "rqlp_create": (_INT, [ctypes.POINTER(_P), _INT]),
+            "rqlp_destroy": (_INT, [_P]),
+            "rqlp_workspace_size": (_SZ, [_I64, _I64, _INT, _INT, _INT, _INT]),
+            "rqlp_workspace_size_csr": (_SZ, [_I64, _I64, _I64, _INT, _INT, _INT, _INT]),
+            "rqlp_decompose": (_INT, [_P, _P, _I64, _I64, _I64, _INT, _INT, _INT, _INT, _U64,
+                                      _P, _P, _P, _P, _SZ, _P]),
+            "rqlp_decompose_csr": (_INT, [_P, _P, _P, _P, _I64, _I64, _I64, _INT, _INT, _INT, _INT,
+                                          _U64, _P, _P, _P, _P, _SZ, _P]),
+            "rqlp_get_info": (_INT, [_P, ctypes.POINTER(Info)]),
+            "rqlp_status_string": (ctypes.c_char_p, [_INT]),
+            "rqlp_gaussian": (_INT, [_P, _U64, ctypes.c_uint32, _I64, _I64, _INT, _P, _I64, _P]),
+            "rqlp_gemm_workspace_size": (_SZ, [_INT, _I64, _I64, _INT, _INT]),
+            "rqlp_gemm": (_INT, [_P, _INT, _P, _I64, _I64, _I64, _P, _I64, _INT, _P, _I64, _INT,
+                                 _P, _SZ, _P]),
+            "rqlp_orth_workspace_size": (_SZ, [_I64, _INT, _INT]),
+            "rqlp_orth": (_INT, [_P, _P, _I64, _INT, _I64, _P, _I64, _P, _INT, _U64, _P, _SZ, _P]),
+            "rqlp_spmm": (_INT, [_P, _P, _P, _P, _I64, _I64, _I64, _P, _I64, _INT, _P, _I64, _INT, _P]),
+            "rqlp_csr_transpose_workspace_size": (_SZ, [_I64, _I64, _I64]),
+            "rqlp_csr_transpose": (_INT, [_P, _P, _P, _P, _I64, _I64, _I64, _INT, _P, _P, _P, _P,
+                                          _SZ, _P]),
+            "rqlp_set_timing": (_INT, [_P, _INT]),
+            "rqlp_get_timing": (_INT, [_P, _INT, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(_I64)]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def exported_symbols():
+    """Names of the C ABI functions this binding expects."""
+    return ["rqlp_create", "rqlp_destroy", "rqlp_workspace_size", "rqlp_workspace_size_csr",
+            "rqlp_decompose", "rqlp_decompose_csr", "rqlp_get_info", "rqlp_status_string",
+            "rqlp_gaussian", "rqlp_gemm_workspace_size", "rqlp_gemm", "rqlp_orth_workspace_size",
+            "rqlp_orth", "rqlp_spmm", "rqlp_csr_transpose_workspace_size", "rqlp_csr_transpose",
+            "rqlp_set_timing", "rqlp_get_timing"]
+
+
+def _check(status, where):
+    if status != RQLP_OK:
+        raise RqlpError(status, where)
+
+
+def _prec(dtype):
+    if dtype == torch.float64:
+        return RQLP_FP64
+    if dtype == torch.float32:
+        return RQLP_FP32
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """Owns an rqlp_ctx on one device (and its info record)."""
+
+    def __init__(self, device=0):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        h = ctypes.c_void_p()
+        _check(_lib().rqlp_create(ctypes.byref(h), self.device.index or 0), "rqlp_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().rqlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        out = Info()
+        _check(_lib().rqlp_get_info(self._h, ctypes.byref(out)), "rqlp_get_info")
+        return dict(status=out.status, completed_cols=out.completed_cols,
+                    breakdown_pass=out.breakdown_pass, nonfinite=out.nonfinite)
+
+    def set_timing(self, enabled):
+        _check(_lib().rqlp_set_timing(self._h, 1 if enabled else 0), "rqlp_set_timing")
+
+    def timing(self, cls):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(_lib().rqlp_get_timing(self._h, KERNEL_CLASSES.get(cls, cls), ctypes.byref(ms),
+                                      ctypes.byref(n)), "rqlp_get_timing")
+        return ms.value, n.value
+
+
+_DEFAULT = {}
+
+
+def default_context(device=0):
+    if device not in _DEFAULT:
+        _DEFAULT[device] = Context(device)
+    return _DEFAULT[device]
+
+
+def workspace_size(m, n, k, p, q, dtype):
+    return int(_lib().rqlp_workspace_size(m, n, k, p, q, _prec(dtype)))
+
+
+def workspace_size_csr(m, n, nnz, k, p, q, dtype):
+    return int(_lib().rqlp_workspace_size_csr(m, n, nnz, k, p, q, _prec(dtype)))
+
+
+def alloc_workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def decompose(A, k, p, q=0, seed=0, ctx=None, workspace=None, out=None):
+    """RU-QLP of a dense device matrix A (m x n, float32 or float64, row
+    stride >= n).  Returns (Q, L, V) on A's device; enqueued on the current
+    stream (not synchronized)."""
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D row-major tensor")
+    ctx = ctx or default_context(A.device.index or 0)
+    m, n = A.shape
+    d = k + p
+    prec = _prec(A.dtype)
+    if out is None:
+        Q = torch.empty((m, d), dtype=A.dtype, device=A.device)
+        L = torch.empty((d, d), dtype=A.dtype, device=A.device)
+        V = torch.empty((n, d), dtype=A.dtype, device=A.device)
+    else:
+        Q, L, V = out
+    if workspace is None:
+        ws_bytes = workspace_size(m, n, k, p, q, A.dtype)
+        workspace = alloc_workspace(ws_bytes, A.device) if ws_bytes else None
+    ws_ptr = _ptr(workspace)
+    ws_bytes = workspace.numel() if workspace is not None else 0
+    _check(_lib().rqlp_decompose(ctx.handle, _ptr(A), m, n, A.stride(0), k, p, q, prec, seed,
+                                 _ptr(Q), _ptr(L), _ptr(V), ws_ptr, ws_bytes, _stream(A.device)),
+           "rqlp_decompose")
+    return Q, L, V
+
+
+def decompose_csr(rowptr, colidx, vals, m, n, k, p, q=0, seed=0, ctx=None, workspace=None, out=None):
+    """RU-QLP of a CSR device matrix (int32 rowptr/colidx, float vals)."""
+    dev = vals.device
+    ctx = ctx or default_context(dev.index or 0)
+    d = k + p
+    nnz = colidx.numel()
+    prec = _prec(vals.dtype)
+    if out is None:
+        Q = torch.empty((m, d), dtype=vals.dtype, device=dev)
+        L = torch.empty((d, d), dtype=vals.dtype, device=dev)
+        V = torch.empty((n, d), dtype=vals.dtype, device=dev)
+    else:
+        Q, L, V = out
+    if workspace is None:
+        ws_bytes = workspace_size_csr(m, n, nnz, k, p, q, vals.dtype)
+        workspace = alloc_workspace(ws_bytes, dev) if ws_bytes else None
+    ws_bytes = workspace.numel() if workspace is not None else 0
+    _check(_lib().rqlp_decompose_csr(ctx.handle, _ptr(rowptr), _ptr(colidx), _ptr(vals), m, n, nnz, k, p,
+                                     q, prec, seed, _ptr(Q), _ptr(L), _ptr(V), _ptr(workspace), ws_bytes,
+                                     _stream(dev)), "rqlp_decompose_csr")
+    return Q, L, V
+
+
+def gaussian(rows, cols, seed, dtype=torch.float64, stream_id=0, ld=None, device="cuda", ctx=None):
+    ld = ld or cols
+    dev = torch.device(device)
+    ctx = ctx or default_context(dev.index or 0)
+    out = torch.empty((rows, ld), dtype=dtype, device=dev)
+    _check(_lib().rqlp_gaussian(ctx.handle, seed, stream_id, rows, cols, _prec(dtype), _ptr(out), ld,
+                                _stream(dev)), "rqlp_gaussian")
+    return out
+
+
+def gemm(A, X, trans=False, ctx=None):
+    """Y = A X (trans=False) or A^T X (trans=True) on the matrix cores."""
+    ctx = ctx or default_context(A.device.index or 0)
+    m, n = A.shape
+    d = X.shape[1]
+    rows_out = n if trans else m
+    Y = torch.empty((rows_out, d), dtype=A.dtype, device=A.device)
+    ws = alloc_workspace(_lib().rqlp_gemm_workspace_size(int(trans), m, n, d, _prec(A.dtype)), A.device)
+    _check(_lib().rqlp_gemm(ctx.handle, int(trans), _ptr(A), m, n, A.stride(0), _ptr(X), X.stride(0), d,
+                            _ptr(Y), Y.stride(0), _prec(A.dtype), _ptr(ws), ws.numel(), _stream(A.device)),
+           "rqlp_gemm")
+    return Y
+
+
+def orth(Y, seed=0, want_r=False, ctx=None):
+    """Unpivoted QR Y = Q R (diag(R) >= 0) by CholeskyQR2; returns Q or (Q, R)."""
+    ctx = ctx or default_context(Y.device.index or 0)
+    rows, d = Y.shape
+    Q = torch.empty((rows, d), dtype=Y.dtype, device=Y.device)
+    R = torch.empty((d, d), dtype=Y.dtype, device=Y.device) if want_r else None
+    ws = alloc_workspace(_lib().rqlp_orth_workspace_size(rows, d, _prec(Y.dtype)), Y.device)
+    _check(_lib().rqlp_orth(ctx.handle, _ptr(Y), rows, d, Y.stride(0), _ptr(Q), Q.stride(0), _ptr(R),
+                            _prec(Y.dtype), seed, _ptr(ws), ws.numel(), _stream(Y.device)), "rqlp_orth")
+    return (Q, R) if want_r else Q
+
+
+def spmm(rowptr, colidx, vals, rows, cols, X, ctx=None):
+    ctx = ctx or default_context(X.device.index or 0)
+    d = X.shape[1]
+    Y = torch.empty((rows, d), dtype=X.dtype, device=X.device)
+    _check(_lib().rqlp_spmm(ctx.handle, _ptr(rowptr), _ptr(colidx), _ptr(vals), rows, cols, colidx.numel(),
+                            _ptr(X), X.stride(0), d, _ptr(Y), Y.stride(0), _prec(X.dtype),
+                            _stream(X.device)), "rqlp_spmm")
+    return Y
+
+
+def csr_transpose(rowptr, colidx, vals, m, n, ctx=None):
+    dev = vals.device
+    ctx = ctx or default_context(dev.index or 0)
+    nnz = colidx.numel()
+    rt = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    ct = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    vt = torch.empty(max(nnz, 1), dtype=vals.dtype, device=dev)
+    ws = alloc_workspace(_lib().rqlp_csr_transpose_workspace_size(m, n, nnz), dev)
+    _check(_lib().rqlp_csr_transpose(ctx.handle, _ptr(rowptr), _ptr(colidx), _ptr(vals), m, n, nnz,
+                                     _prec(vals.dtype), _ptr(rt), _ptr(ct), _ptr(vt), _ptr(ws), ws.numel(),
+                                     _stream(dev)), "rqlp_csr_transpose")
+    return rt, ct[:nnz], vt[:nnz]

@@ -1,0 +1,164 @@
+"""Parity of the whole method (rqlp_decompose / rqlp_decompose_csr) with the
+oracle.  Delta = ||Q L V^T - Qo Lo Vo^T||_F / ||A||_F must be <= 1e-12 on the
+float64 path and <= 1e-5 on the float32 path."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.metrics import recon_diff, recon_error, orth_error
+import workloads
+from tests import pins
+from tests.gpu_util import announce, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+
+
+def _run(gpu_lib, A_np, k, p, q, seed, dtype):
+    A = to_dev(A_np)
+    Q, L, V = gpu_lib.decompose(A, k, p, q, seed=seed)
+    return to_np(Q), to_np(L), to_np(V)
+
+
+def _omega_dtype(dtype):
+    return "f32" if dtype == torch.float32 else "f64"
+
+
+def _check_against_oracle(A_np, Qg, Lg, Vg, k, p, q, seed, dtype, factors=True):
+    A64 = A_np.astype(np.float64)
+    Qo, Lo, Vo = oracle.ruqlp(A64, k, p, q, seed, omega_dtype=_omega_dtype(dtype))
+    nA = np.linalg.norm(A64)
+    delta = recon_diff(Qg, Lg, Vg, Qo, Lo, Vo) / nA
+    tol = TOL[dtype]
+    d = k + p
+    assert delta <= tol, f"Delta {delta:.3e} > {tol}"
+    assert orth_error(Qg) <= 100 * d * (tol if dtype == torch.float32 else 1e-15)
+    assert orth_error(Vg) <= 100 * d * (tol if dtype == torch.float32 else 1e-15)
+    assert np.all(np.triu(Lg, 1) == 0.0)
+    return delta, (Qo, Lo, Vo)
+
+
+def test_small_fp64_config(gpu_lib):
+    """1000 x 800 FP64, sigma_i = 0.9^i, k = 20, p = 5, q = 0."""
+    announce("decompose cfg small fp64")
+    c = workloads.cfg_small_fp64(seed=1)
+    Qg, Lg, Vg = _run(gpu_lib, c["A"], 20, 5, 0, 42, torch.float64)
+    delta, (Qo, Lo, Vo) = _check_against_oracle(c["A"], Qg, Lg, Vg, 20, 5, 0, 42, torch.float64)
+    # factors are unique here (full-rank sketch): compare them directly
+    assert np.linalg.norm(Qg - Qo) < 1e-11 and np.linalg.norm(Vg - Vo) < 1e-11
+    assert np.linalg.norm(Lg - Lo) < 1e-11 * np.linalg.norm(Lo)
+    ok, info = pins.check_sv_interlacing(c["sigma"], Lg)
+    assert ok, info
+
+
+@pytest.mark.parametrize("m,n,k,p,q", [(600, 450, 30, 10, 0), (600, 450, 30, 10, 2), (450, 600, 20, 5, 1),
+                                       (300, 300, 250, 6, 1), (97, 61, 60, 1, 1), (200, 40, 1, 0, 0)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_shapes_and_edges(gpu_lib, m, n, k, p, q, dtype):
+    announce("decompose shapes", m, n, k, p, q, dtype)
+    sigma = workloads.spectrum("geometric", min(m, n), rho=0.97)
+    A, _, _, _ = workloads.dense_from_spectrum(m, n, sigma, seed=m + n, trunc=0.0)
+    A = A.astype(np.float32) if dtype == torch.float32 else A
+    Qg, Lg, Vg = _run(gpu_lib, A, k, p, q, 3, dtype)
+    _check_against_oracle(A, Qg, Lg, Vg, k, p, q, 3, dtype)
+
+
+@pytest.mark.parametrize("q", [0, 1])
+def test_gapped_fp32_midsize(gpu_lib, q):
+    announce("decompose gapped fp32 midsize", q)
+    c = workloads.cfg_gapped_fp32(seed=5, m=3000, n=2500, q=q)
+    Qg, Lg, Vg = _run(gpu_lib, c["A"], 200, 10, q, 8, torch.float32)
+    _check_against_oracle(c["A"], Qg, Lg, Vg, 200, 10, q, 8, torch.float32, factors=False)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_exact_recovery_rank_deficient(gpu_lib, dtype):
+    """rank(A) = 12 <= k = 20: A is recovered exactly; the extra columns are
+    completed with random directions and their L-values are exactly zero."""
+    announce("decompose rank-deficient", dtype)
+    sigma = np.zeros(300)
+    sigma[:12] = np.linspace(3.0, 1.0, 12)
+    A, _, _, _ = workloads.dense_from_spectrum(500, 300, sigma, seed=4, trunc=0.0)
+    A = A.astype(np.float32) if dtype == torch.float32 else A
+    ctx = gpu_lib.default_context(0)
+    Qg, Lg, Vg = _run(gpu_lib, A, 20, 5, 1, 9, dtype)
+    info = ctx.info()
+    tol = TOL[dtype]
+    assert recon_error(A, Qg, Lg, Vg) <= tol
+    assert orth_error(Qg) <= 100 * 25 * (tol if dtype == torch.float32 else 1e-15)
+    assert orth_error(Vg) <= 100 * 25 * (tol if dtype == torch.float32 else 1e-15)
+    assert info["completed_cols"] > 0 and info["nonfinite"] == 0
+    assert np.all(np.abs(np.diag(Lg)[12:]) <= tol * np.abs(np.diag(Lg)).max())
+    # the reconstruction (unique) matches the oracle's
+    Qo, Lo, Vo = oracle.ruqlp(A.astype(np.float64), 20, 5, 1, 9, omega_dtype=_omega_dtype(dtype))
+    assert recon_diff(Qg, Lg, Vg, Qo, Lo, Vo) / np.linalg.norm(A) <= tol
+
+
+def test_zero_matrix(gpu_lib):
+    announce("decompose zero matrix")
+    A = np.zeros((120, 90))
+    Qg, Lg, Vg = _run(gpu_lib, A, 10, 4, 1, 2, torch.float64)
+    assert np.all(Lg == 0.0)
+    assert orth_error(Qg) < 1e-13 and orth_error(Vg) < 1e-13
+
+
+def test_nonfinite_input_is_reported(gpu_lib):
+    announce("decompose NaN input")
+    A = np.random.default_rng(0).standard_normal((100, 80))
+    A[3, 7] = np.nan
+    ctx = gpu_lib.default_context(0)
+    _run(gpu_lib, A, 5, 2, 0, 1, torch.float64)
+    assert ctx.info()["nonfinite"] == 1
+    # a clean call afterwards resets the record
+    _run(gpu_lib, np.nan_to_num(A), 5, 2, 0, 1, torch.float64)
+    assert ctx.info()["nonfinite"] == 0
+
+
+def test_bitwise_deterministic(gpu_lib):
+    announce("decompose determinism")
+    c = workloads.cfg_gapped_fp32(seed=6, m=2000, n=1800, q=1)
+    A = to_dev(c["A"])
+    r1 = [t.clone() for t in gpu_lib.decompose(A, 100, 10, 1, seed=3)]
+    r2 = [t.clone() for t in gpu_lib.decompose(A, 100, 10, 1, seed=3)]
+    torch.cuda.synchronize()
+    for a, b in zip(r1, r2):
+        assert torch.equal(a, b)
+
+
+def test_full_size_gapped_fp32(gpu_lib):
+    """8000 x 8000 FP32, gapped spectrum, k = 200, p = 10, q = 1: the
+    benchmark workload, in the launch configuration the benchmark uses."""
+    announce("decompose full 8000^2 fp32 q=1")
+    c = workloads.cfg_gapped_fp32(seed=2, q=1)
+    Qg, Lg, Vg = _run(gpu_lib, c["A"], 200, 10, 1, 2024, torch.float32)
+    _check_against_oracle(c["A"], Qg, Lg, Vg, 200, 10, 1, 2024, torch.float32, factors=False)
+
+
+# ---------------------------------------------------------------- CSR
+@pytest.mark.parametrize("m,n,density,k,p,q", [(3000, 2000, 0.01, 30, 10, 1), (2000, 3000, 0.005, 20, 5, 0)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_csr_matches_oracle(gpu_lib, m, n, density, k, p, q, dtype):
+    announce("decompose csr", m, n, density, k, p, q, dtype)
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    rowptr, colidx, vals = workloads.csr_uniform(m, n, int(density * m * n), seed=m, dtype=npdt)
+    Q, L, V = gpu_lib.decompose_csr(to_dev(rowptr), to_dev(colidx), to_dev(vals), m, n, k, p, q, seed=4)
+    Qg, Lg, Vg = to_np(Q), to_np(L), to_np(V)
+    Qo, Lo, Vo = oracle.ruqlp_csr(rowptr, colidx, vals, m, n, k, p, q, 4, omega_dtype=_omega_dtype(dtype))
+    nA = np.linalg.norm(vals.astype(np.float64))
+    assert recon_diff(Qg, Lg, Vg, Qo, Lo, Vo) / nA <= TOL[dtype]
+    assert np.all(np.triu(Lg, 1) == 0.0)
+
+
+def test_csr_full_size(gpu_lib):
+    """CSR 100000 x 50000, 0.1 % density, N(0,1) FP32, k = 100, p = 10, q = 1."""
+    announce("decompose csr full size")
+    c = workloads.cfg_sparse(seed=3)
+    m, n = c["m"], c["n"]
+    Q, L, V = gpu_lib.decompose_csr(to_dev(c["rowptr"]), to_dev(c["colidx"]), to_dev(c["vals"]), m, n,
+                                    100, 10, 1, seed=7)
+    Qg, Lg, Vg = to_np(Q), to_np(L), to_np(V)
+    Qo, Lo, Vo = oracle.ruqlp_csr(c["rowptr"], c["colidx"], c["vals"], m, n, 100, 10, 1, 7, omega_dtype="f32")
+    nA = np.linalg.norm(c["vals"].astype(np.float64))
+    assert recon_diff(Qg, Lg, Vg, Qo, Lo, Vo) / nA <= 1e-5
