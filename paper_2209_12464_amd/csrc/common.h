@@ -32,19 +32,19 @@ __device__ inline int xcd_remap(int b, int nblocks) {
 // MFMA shapes.  Operand layouts (verified on gfx950):
 //   A operand: lane l supplies A[m = l % TM][k = l / TM] (TM * TK = 64)
 //   B operand: lane l supplies B[k = l / TN][n = l % TN]
-//   f32 32x32x2: acc[r] = C[8 (r/4) + 4 (l/32) + r%4][l % 32]
+//   f32 16x16x4: acc[r] = C[4 (l/16) + r][l % 16]
 //   f64 16x16x4: acc[r] = C[l/16 + 4 r][l % 16]
 template <typename T> struct Mfma;
 
 template <> struct Mfma<float> {
-  static constexpr int TM = 32, TN = 32, TK = 2, NACC = 16;
-  typedef floatx16 acc_t;
-  __device__ static inline acc_t zero() { acc_t z; for (int i = 0; i < 16; ++i) z[i] = 0.f; return z; }
+  static constexpr int TM = 16, TN = 16, TK = 4, NACC = 4;
+  typedef floatx4 acc_t;
+  __device__ static inline acc_t zero() { acc_t z; for (int i = 0; i < 4; ++i) z[i] = 0.f; return z; }
   __device__ static inline acc_t mma(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
-  __device__ static inline int row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
-  __device__ static inline int col(int lane) { return lane & 31; }
+  __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  __device__ static inline int col(int lane) { return lane & 15; }
 };
 
 template <> struct Mfma<double> {

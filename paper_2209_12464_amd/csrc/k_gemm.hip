@@ -9,40 +9,44 @@
 // Workgroup ids are remapped so that an XCD works on a contiguous range of
 // (split, slab) pairs: the X chunk of a split then stays in that XCD's L2.
 //
-// Tiles: 4 waves x TM rows (TM = 32 for float MFMA 32x32x2, 16 for double
-// MFMA 16x16x4), BK = 16 along the reduction, all BN = 32*NB (float) or
-// 16*NB (double) columns.  A and X tiles are staged through LDS, double
-// buffered with register prefetch, one barrier per K step.
+// Tiles: 8 waves as 4 (rows) x 2 (columns); each wave owns 32 rows and half
+// of the BN = 32 * NBW columns, i.e. 2 x NBW blocks of 16 x 16 accumulated
+// with the 16x16x4 MFMA (float or double).  BK = 16 along the reduction.  A
+// and X tiles are staged through LDS, double buffered with register
+// prefetch, one barrier per K step.
 #include "common.h"
 #include "kernels.h"
 
 namespace rqlp {
 
-constexpr int kGemmThreads = 256;
+constexpr int kGemmThreads = 512;
 constexpr int kBK = 16;
 
-template <typename T, int NB, bool TRANS, bool AVEC>
-__global__ __launch_bounds__(kGemmThreads, 2) void gemm_kernel(
+template <typename T, int NBW, bool TRANS, bool AVEC, bool BVEC>
+__global__ __launch_bounds__(kGemmThreads) void gemm_kernel(
     const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
     T* __restrict__ C, int64_t ldc, int64_t cslice, int M, int N, int K, int kchunk, int mtiles,
     int nst) {
   typedef Mfma<T> MF;
-  constexpr int TM = MF::TM, TN = MF::TN, TK = MF::TK;
-  constexpr int BM = 4 * TM;
-  constexpr int BN = NB * TN;
+  constexpr int BM = 128;                  // 4 row groups x 32 rows
+  constexpr int BN = 32 * NBW;             // 2 column halves x NBW blocks of 16
   constexpr int VEC = 16 / sizeof(T);
-  constexpr int APAD = TRANS ? VEC : 2;
-  constexpr int AS = BM + APAD;                       // LDS row stride of the A tile
-  constexpr int A_ELEMS = BM * kBK / kGemmThreads;    // per thread
+  // LDS row strides of 16 (mod 32) words: the two k-rows an operand read
+  // touches in one 32-lane half then fall in disjoint banks
+  constexpr int AS = BM + 16;              // A tile, k-major
+  constexpr int BS = BN + 16;              // X tile
+  constexpr int A_ELEMS = BM * kBK / kGemmThreads;   // 4 per thread
   constexpr int A_VECS = A_ELEMS / VEC;
-  constexpr int B_ELEMS = (kBK * BN + kGemmThreads - 1) / kGemmThreads;
+  constexpr int B_VECS = (kBK * BN / VEC + kGemmThreads - 1) / kGemmThreads;
+  constexpr int B_ELEMS = BVEC ? B_VECS * VEC : (kBK * BN + kGemmThreads - 1) / kGemmThreads;
 
   __shared__ __attribute__((aligned(16))) T As[2][kBK][AS];
-  __shared__ __attribute__((aligned(16))) T Bs[2][kBK][BN];
+  __shared__ __attribute__((aligned(16))) T Bs[2][kBK][BS];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave & 3, wn = wave >> 2;
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   const int split = logical / mtiles;
   const int mt = logical - split * mtiles;
@@ -53,7 +57,6 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_kernel(
   T areg[A_ELEMS];
   T breg[B_ELEMS];
 
-  // ---- global -> registers ----
   auto load_tile = [&](int k0) {
     if constexpr (!TRANS) {
       // A tile rows m0..m0+BM, cols k0..k0+BK (A is M x K)
@@ -124,16 +127,37 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_kernel(
         }
       }
     }
+    if constexpr (BVEC) {
+      // X rows are BN wide with zero padding beyond N (internal buffers)
 #pragma unroll
-    for (int i = 0; i < B_ELEMS; ++i) {
-      const int idx = tid + kGemmThreads * i;
-      const int kk = idx / BN, n = idx % BN;
-      const int gk = k0 + kk;
-      breg[i] = (idx < kBK * BN && gk < kend && n < N) ? B[(int64_t)gk * ldb + n] : (T)0;
+      for (int v = 0; v < B_VECS; ++v) {
+        const int idx = tid + kGemmThreads * v;
+        const int kk = idx / (BN / VEC), nv = idx % (BN / VEC);
+        const int gk = k0 + kk;
+        const bool ok = idx < kBK * BN / VEC && gk < kend;
+        if constexpr (VEC == 4) {
+          floatx4 x = {0.f, 0.f, 0.f, 0.f};
+          if (ok) x = *reinterpret_cast<const floatx4*>(B + (int64_t)gk * ldb + nv * VEC);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) breg[v * VEC + e] = x[e];
+        } else {
+          double2 x = {0.0, 0.0};
+          if (ok) x = *reinterpret_cast<const double2*>(B + (int64_t)gk * ldb + nv * VEC);
+          breg[v * VEC + 0] = x.x;
+          breg[v * VEC + 1] = x.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < B_ELEMS; ++i) {
+        const int idx = tid + kGemmThreads * i;
+        const int kk = idx / BN, n = idx % BN;
+        const int gk = k0 + kk;
+        breg[i] = (idx < kBK * BN && gk < kend && n < N) ? B[(int64_t)gk * ldb + n] : (T)0;
+      }
     }
   };
 
-  // ---- registers -> LDS buffer `buf` ----
   auto store_tile = [&](int buf) {
     if constexpr (!TRANS) {
       if constexpr (AVEC) {
@@ -168,17 +192,33 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_kernel(
         }
       }
     }
+    if constexpr (BVEC) {
 #pragma unroll
-    for (int i = 0; i < B_ELEMS; ++i) {
-      const int idx = tid + kGemmThreads * i;
-      if (idx < kBK * BN) Bs[buf][idx / BN][idx % BN] = breg[i];
+      for (int v = 0; v < B_VECS; ++v) {
+        const int idx = tid + kGemmThreads * v;
+        if (idx < kBK * BN / VEC) {
+          const int kk = idx / (BN / VEC), nv = idx % (BN / VEC);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) Bs[buf][kk][nv * VEC + e] = breg[v * VEC + e];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < B_ELEMS; ++i) {
+        const int idx = tid + kGemmThreads * i;
+        if (idx < kBK * BN) Bs[buf][idx / BN][idx % BN] = breg[i];
+      }
     }
   };
 
-  typename MF::acc_t acc[NB];
+  typename MF::acc_t acc[2][NBW];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) acc[nb] = MF::zero();
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = MF::zero();
 
+  const int arow = wm * 32 + (lane & 15);
+  const int bcol = wn * (BN / 2) + (lane & 15);
   if (kbeg < kend) {
     load_tile(kbeg);
     store_tile(0);
@@ -188,12 +228,15 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_kernel(
       const bool more = k0 + kBK < kend;
       if (more) load_tile(k0 + kBK);
 #pragma unroll
-      for (int ks = 0; ks < kBK / TK; ++ks) {
-        const T a = As[buf][ks * TK + lane / TM][wave * TM + lane % TM];
+      for (int ks = 0; ks < kBK / 4; ++ks) {
+        const int kr = ks * 4 + (lane >> 4);
+        const T a0 = As[buf][kr][arow];
+        const T a1 = As[buf][kr][arow + 16];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const T b = Bs[buf][ks * TK + lane / TN][nb * TN + lane % TN];
-          acc[nb] = MF::mma(a, b, acc[nb]);
+        for (int nb = 0; nb < NBW; ++nb) {
+          const T b = Bs[buf][kr][bcol + nb * 16];
+          acc[0][nb] = MF::mma(a0, b, acc[0][nb]);
+          acc[1][nb] = MF::mma(a1, b, acc[1][nb]);
         }
       }
       if (more) store_tile(buf ^ 1);
@@ -205,14 +248,16 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_kernel(
   // ---- epilogue: write the slab (or this split's partial slab) ----
   T* Cs = C + (int64_t)split * cslice;
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    const int col = nb * TN + MF::col(lane);
+  for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int r = 0; r < MF::NACC; ++r) {
-      const int row = m0 + wave * TM + MF::row(lane, r);
-      if (row < M && col < nst) Cs[(int64_t)row * ldc + col] = acc[nb][r];
+    for (int nb = 0; nb < NBW; ++nb) {
+      const int col = wn * (BN / 2) + nb * 16 + MF::col(lane);
+#pragma unroll
+      for (int r = 0; r < MF::NACC; ++r) {
+        const int row = m0 + wm * 32 + mb * 16 + MF::row(lane, r);
+        if (row < M && col < nst) Cs[(int64_t)row * ldc + col] = acc[mb][nb][r];
+      }
     }
-  }
 }
 
 // Y[i][j] = sum_s P[s][i][j] in order s = 0..nsplit-1 (i < M, j < nst).
@@ -230,59 +275,41 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const T* __restrict_
   }
 }
 
-template <typename T, int NB, bool TRANS>
+template <typename T, int NBW, bool TRANS>
 static void launch_nb(const GemmArgs<T>& g, hipStream_t s, int grid, T* C, int64_t ldc,
-                      int64_t cslice, int nst, bool avec) {
-  if (avec)
-    hipLaunchKernelGGL((gemm_kernel<T, NB, TRANS, true>), dim3(grid), dim3(kGemmThreads), 0, s, g.A,
-                       g.lda, g.B, g.ldb, C, ldc, cslice, g.M, g.N, g.K, g.kchunk, g.mtiles, nst);
-  else
-    hipLaunchKernelGGL((gemm_kernel<T, NB, TRANS, false>), dim3(grid), dim3(kGemmThreads), 0, s,
-                       g.A, g.lda, g.B, g.ldb, C, ldc, cslice, g.M, g.N, g.K, g.kchunk, g.mtiles, nst);
+                      int64_t cslice, int nst) {
+#define RQLP_GEMM_LAUNCH(AV, BV)                                                                       \
+  hipLaunchKernelGGL((gemm_kernel<T, NBW, TRANS, AV, BV>), dim3(grid), dim3(kGemmThreads), 0, s, g.A, g.lda, \
+                     g.B, g.ldb, C, ldc, cslice, g.M, g.N, g.K, g.kchunk, g.mtiles, nst)
+  if (g.avec && g.bvec) RQLP_GEMM_LAUNCH(true, true);
+  else if (g.avec) RQLP_GEMM_LAUNCH(true, false);
+  else if (g.bvec) RQLP_GEMM_LAUNCH(false, true);
+  else RQLP_GEMM_LAUNCH(false, false);
+#undef RQLP_GEMM_LAUNCH
 }
 
 template <typename T, bool TRANS>
 static void dispatch_nb(const GemmArgs<T>& g, hipStream_t s, int grid, T* C, int64_t ldc,
-                        int64_t cslice, int nst, bool avec) {
-  constexpr int TN = Mfma<T>::TN;
-  const int nb = (int)ceil_div(g.N, TN);
-  if constexpr (sizeof(T) == 4) {
-    switch (nb) {
-      case 1: launch_nb<T, 1, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-      case 2: launch_nb<T, 2, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-      case 3: launch_nb<T, 3, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-      case 4: launch_nb<T, 4, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-      case 5: launch_nb<T, 5, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-      case 6: launch_nb<T, 6, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-      case 7: launch_nb<T, 7, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-      default: launch_nb<T, 8, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-    }
-  } else {
-    switch ((nb + 1) / 2) {  // double: 16-wide blocks, instantiate even counts
-      case 1: launch_nb<T, 2, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-      case 2: launch_nb<T, 4, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-      case 3: launch_nb<T, 6, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-      case 4: launch_nb<T, 8, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-      case 5: launch_nb<T, 10, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-      case 6: launch_nb<T, 12, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-      case 7: launch_nb<T, 14, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-      default: launch_nb<T, 16, TRANS>(g, s, grid, C, ldc, cslice, nst, avec); break;
-    }
+                        int64_t cslice, int nst) {
+  switch (gemm_block_cols<T>(g.N) / 32) {
+    case 1: launch_nb<T, 1, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
+    case 2: launch_nb<T, 2, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
+    case 3: launch_nb<T, 3, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
+    case 4: launch_nb<T, 4, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
+    case 5: launch_nb<T, 5, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
+    case 6: launch_nb<T, 6, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
+    case 7: launch_nb<T, 7, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
+    default: launch_nb<T, 8, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
   }
 }
 
 template <typename T>
-int gemm_block_rows() { return 4 * Mfma<T>::TM; }
+int gemm_block_rows() { return 128; }
 template int gemm_block_rows<float>();
 template int gemm_block_rows<double>();
 
 template <typename T>
-int gemm_block_cols(int N) {
-  constexpr int TN = Mfma<T>::TN;
-  int nb = (int)ceil_div(N, TN);
-  if (sizeof(T) == 8) nb = (int)round_up(nb, 2);
-  return nb * TN;
-}
+int gemm_block_cols(int N) { return (int)round_up(N, 32); }
 template int gemm_block_cols<float>(int);
 template int gemm_block_cols<double>(int);
 
@@ -293,18 +320,17 @@ hipError_t launch_gemm(GemmArgs<T> g, T* Y, int64_t ldy, int nst, T* P, hipStrea
                        hipEvent_t ev0, hipEvent_t ev1) {
   if (g.M <= 0 || nst <= 0) return hipSuccess;
   const int grid = g.mtiles * g.nsplit;
-  const bool avec = g.avec;
-  if (ev0) hipEventRecord(ev0, s);
+  if (ev0) (void)hipEventRecord(ev0, s);
   if (g.nsplit == 1) {
-    if (g.trans) dispatch_nb<T, true>(g, s, grid, Y, ldy, 0, nst, avec);
-    else dispatch_nb<T, false>(g, s, grid, Y, ldy, 0, nst, avec);
+    if (g.trans) dispatch_nb<T, true>(g, s, grid, Y, ldy, 0, nst);
+    else dispatch_nb<T, false>(g, s, grid, Y, ldy, 0, nst);
   } else {
     const int64_t ldp = nst;
     const int64_t pslice = (int64_t)g.M * ldp;
-    if (g.trans) dispatch_nb<T, true>(g, s, grid, P, ldp, pslice, nst, avec);
-    else dispatch_nb<T, false>(g, s, grid, P, ldp, pslice, nst, avec);
+    if (g.trans) dispatch_nb<T, true>(g, s, grid, P, ldp, pslice, nst);
+    else dispatch_nb<T, false>(g, s, grid, P, ldp, pslice, nst);
   }
-  if (ev1) hipEventRecord(ev1, s);
+  if (ev1) (void)hipEventRecord(ev1, s);
   if (g.nsplit > 1) {
     const int64_t total = (int64_t)g.M * nst;
     const int64_t gr = ceil_div(total, 256);

@@ -6,33 +6,38 @@
 
 namespace rqlp {
 
-// Entry (a, b), a <= b < d, of R2 * R1' (R1' = R1 with dependent rows zero).
-__device__ inline double r_entry(const double* R2, const double* R1, const int32_t* f1,
-                                 const int32_t* f2, int dp, int a, int b) {
-  if (f2[a]) return 0.0;
-  double s = 0.0;
-  for (int t = a; t <= b; ++t)
-    if (!f1[t]) s += R2[(int64_t)a * dp + t] * R1[(int64_t)t * dp + b];
-  return s;
-}
-
+// R = R2 * R1' (R1' = R1 with the rows of dependent columns zeroed, R2 with
+// its own dependent rows zeroed), one 16 x 16 output tile per wave with the
+// float64 MFMA; written as R (transpose = 0) or as L = R^T (transpose = 1).
 template <typename T>
-__global__ __launch_bounds__(256) void form_l_kernel(const double* __restrict__ R2,
-                                                     const double* __restrict__ R1,
-                                                     const int32_t* __restrict__ f1,
-                                                     const int32_t* __restrict__ f2, int d, int dp,
-                                                     T* __restrict__ L, int64_t ldl, int transpose) {
-  const int64_t total = (int64_t)d * d;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e / d), j = (int)(e % d);
-    double v = 0.0;
-    if (transpose) {  // L[i][j] = R[j][i], lower triangular
-      if (j <= i) v = r_entry(R2, R1, f1, f2, dp, j, i);
-    } else {          // R[i][j], upper triangular
-      if (i <= j) v = r_entry(R2, R1, f1, f2, dp, i, j);
+__global__ __launch_bounds__(64) void form_r_kernel(const double* __restrict__ R2,
+                                                    const double* __restrict__ R1,
+                                                    const int32_t* __restrict__ f1,
+                                                    const int32_t* __restrict__ f2, int d, int dp,
+                                                    T* __restrict__ out, int64_t ldo, int transpose) {
+  const int nT = dp / kTile;
+  const int I = blockIdx.x / nT, J = blockIdx.x % nT;  // output tile of R
+  const int lane = threadIdx.x, lr = lane >> 4, lc = lane & 15;
+  doublex4 acc = Mfma<double>::zero();
+  if (I <= J) {
+    for (int t = I; t <= J; ++t) {
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int kk = t * kTile + ks * 4 + lr;
+        const double a = R2[(int64_t)(I * kTile + lc) * dp + kk];        // A[m][kk], m = lc
+        const double b = f1[kk] ? 0.0 : R1[(int64_t)kk * dp + J * kTile + lc];
+        acc = Mfma<double>::mma(a, b, acc);
+      }
     }
-    L[(int64_t)i * ldl + j] = (T)v;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = I * kTile + lr + 4 * r, col = J * kTile + lc;
+    if (row < d && col < d) {
+      const double v = (row <= col && !f2[row]) ? acc[r] : 0.0;
+      if (transpose) out[(int64_t)col * ldo + row] = (T)v;
+      else out[(int64_t)row * ldo + col] = (T)v;
+    }
   }
 }
 
@@ -40,17 +45,17 @@ template <typename T>
 hipError_t launch_form_l(const double* R2, const double* R1, const int32_t* flags1, int d, int dp,
                          T* L, int64_t ldl, hipStream_t s) {
   // flags of the second pass follow the first pass's dp flags in memory
-  const int64_t g = ceil_div((int64_t)d * d, 256);
-  hipLaunchKernelGGL(form_l_kernel<T>, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, s, R2, R1,
-                     flags1, flags1 + dp, d, dp, L, ldl, 1);
+  const int nT = dp / kTile;
+  hipLaunchKernelGGL(form_r_kernel<T>, dim3(nT * nT), dim3(64), 0, s, R2, R1, flags1, flags1 + dp, d, dp, L,
+                     ldl, 1);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_form_r(const double* R2, const double* R1, const int32_t* flags1, int d, int dp,
                          T* R, int64_t ldr, hipStream_t s) {
-  const int64_t g = ceil_div((int64_t)d * d, 256);
-  hipLaunchKernelGGL(form_l_kernel<T>, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, s, R2, R1,
-                     flags1, flags1 + dp, d, dp, R, ldr, 0);
+  const int nT = dp / kTile;
+  hipLaunchKernelGGL(form_r_kernel<T>, dim3(nT * nT), dim3(64), 0, s, R2, R1, flags1, flags1 + dp, d, dp, R,
+                     ldr, 0);
   return hipGetLastError();
 }
 template hipError_t launch_form_l<float>(const double*, const double*, const int32_t*, int, int, float*, int64_t, hipStream_t);

@@ -28,6 +28,7 @@ struct GemmArgs {
   int nsplit;      // split-K count
   int kchunk;      // reduction length per split (multiple of 16)
   bool avec;       // A rows 16-byte aligned: vector loads
+  bool bvec;       // X rows padded to the tile width with zeros: vector loads
 };
 template <typename T> int gemm_block_rows();
 template <typename T> int gemm_block_cols(int N);
@@ -53,18 +54,25 @@ int gram_chunks(int64_t rows, int dp);
 // dp x dp, ld dp, identity beyond d; rows of dependent columns are e_j^T),
 // Rinv16 (inverses of the dp/16 diagonal 16x16 blocks of R, row-major
 // 16x16 each), flags[j] = 1 for dependent columns (j < dp).  Updates info.
+// fast_tol > 0: when ||G - I||_F < fast_tol, use R = I + F (first order)
+// and write the explicit inverse I - F to Xfull (dp x dp); *mode is set to
+// 1 in that case, 0 after a full factorization.
 hipError_t launch_chol(const double* G, int d, int dp, double* R, double* Rinv16, int32_t* flags,
-                       void* info, int pass_id, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+                       void* info, int pass_id, double fast_tol, int32_t* mode, double* Xfull,
+                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 
 // ---- triangular solve Q = Y R^-1 (k_apply.hip) ----
 // Y: rows x dp (ldy, type Tin); out1 (ld1, first `ncols1` columns, type
 // Tout) and optional out2 (ld2, first `ncols2` columns).  Dependent columns (flags) are replaced
 // by Gaussian columns of stream (seed, key1) divided by sqrt(rows).
+// mode (device, from launch_chol): 1 -> Q = Y Xfull (explicit inverse),
+// 0 -> blocked substitution with R and Rinv16.
 template <typename Tin, typename Tout>
 hipError_t launch_apply(const Tin* Y, int64_t ldy, int64_t rows, int d, int dp, const double* R,
-                        const double* Rinv16, const int32_t* flags, Tout* out1, int64_t ld1,
-                        int ncols1, Tout* out2, int64_t ld2, int ncols2, uint64_t seed,
-                        uint64_t key1, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+                        const double* Rinv16, const int32_t* flags, const int32_t* mode,
+                        const double* Xfull, Tout* out1, int64_t ld1, int ncols1, Tout* out2,
+                        int64_t ld2, int ncols2, uint64_t seed, uint64_t key1, hipStream_t s,
+                        hipEvent_t ev0, hipEvent_t ev1);
 
 // ---- small d x d helpers (k_small.hip) ----
 // L (d x d, ld ldl, type T) = (R2 * R1')^T where R1' is R1 with the rows of

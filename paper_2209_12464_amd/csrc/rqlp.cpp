@@ -14,7 +14,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/rqlp.h"
+#include "rqlp.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -103,15 +103,18 @@ GemmArgs<T> plan_gemm(int trans, const T* A, int64_t lda, const T* B, int64_t ld
   g.trans = trans;
   const int bm = gemm_block_rows<T>();
   g.mtiles = (int)ceil_div(M, bm);
+  // Resident workgroup slots: two 4-wave workgroups per CU (register
+  // limited), 256 CUs.  Split K so that all slabs x splits fit in one round.
   const int target = std::max(1, env_int("RQLP_GEMM_TARGET_WGS", 512));
   const int64_t kmin = std::max(16, env_int("RQLP_GEMM_MIN_KCHUNK", 256));
-  int64_t ns = ceil_div(target, g.mtiles);
+  int64_t ns = target / g.mtiles;
   ns = std::min<int64_t>(ns, std::max<int64_t>(1, ceil_div(K, kmin)));
   ns = std::max<int64_t>(1, ns);
   g.kchunk = (int)round_up(ceil_div(std::max(K, 1), ns), 16);
   g.nsplit = (int)ceil_div(std::max(K, 1), g.kchunk);
   const int vec = 16 / (int)sizeof(T);
   g.avec = (lda % vec == 0) && (((uintptr_t)A & 15) == 0);
+  g.bvec = false;
   return g;
 }
 
@@ -123,7 +126,7 @@ size_t gemm_partial_elems(int M, int K, int dp) {
 
 // Layout of the dense / CSR decomposition workspace.
 struct Layout {
-  size_t om, yb, qi, q1, part, gp, g, r1, r2, rinv, flags, csr_rt, csr_ct, csr_vt, csr_scr, total;
+  size_t om, yb, qi, q1, part, gp, g, r1, r2, rinv, flags, xf, csr_rt, csr_ct, csr_vt, csr_scr, total;
 };
 
 template <typename T>
@@ -146,7 +149,8 @@ Layout layout(int64_t m, int64_t n, int d, bool sparse, int64_t nnz) {
   L.r1 = put((size_t)dp * dp * sizeof(double));
   L.r2 = put((size_t)dp * dp * sizeof(double));
   L.rinv = put((size_t)dp * kTile * sizeof(double));
-  L.flags = put((size_t)2 * dp * sizeof(int32_t));
+  L.flags = put((size_t)(2 * dp + 2) * sizeof(int32_t));
+  L.xf = put((size_t)dp * dp * sizeof(double));
   if (sparse) {
     L.csr_rt = put((size_t)(n + 1) * sizeof(int32_t));
     L.csr_ct = put((size_t)nnz * sizeof(int32_t));
@@ -182,10 +186,14 @@ rqlp_status get_workspace(rqlp_ctx* c, void* ws, size_t ws_bytes, size_t need, c
 }
 
 struct Bufs {
-  double *q1, *gp, *g, *r1, *r2, *rinv;
-  int32_t* flags;
-  int gchunks;
+  double *q1, *gp, *g, *r1, *r2, *rinv, *xf;
+  int32_t* flags;  // 2 dp dependent-column flags, then the two pass modes
 };
+
+// Largest ||Q1^T Q1 - I||_F for which the first-order second-pass factor is
+// used: its orthogonality error ~||E||_F^2 / 4 stays below the output's
+// rounding (2^-52 for float64, far below 2^-24 for float32).
+double fast_tol_for(bool fp64) { return fp64 ? 0x1p-26 : 0x1p-18; }
 
 // Key of the completion stream of one CholeskyQR pass.
 uint64_t completion_key(int orth_index, int pass) {
@@ -201,30 +209,36 @@ rqlp_status cholqr2(rqlp_ctx* c, const T* Y, int64_t ldy, int64_t rows, int d, c
                     uint64_t seed, int orth_index, hipStream_t s) {
   const int dp = padded_d(d);
   const int gch = gram_chunks(rows, dp);
+  const double ftol = fast_tol_for(sizeof(T) == 8);
+  int32_t* mode = b.flags + 2 * dp;
   EvPair t;
   t = timer(c, RQLP_KT_GRAM);
   HIP_TRY(launch_gram<T>(Y, ldy, rows, d, dp, b.gp, gch, b.g, c->info, s, t.a, t.b));
   t = timer(c, RQLP_KT_CHOL);
-  HIP_TRY(launch_chol(b.g, d, dp, b.r1, b.rinv, b.flags, c->info, orth_index, s, t.a, t.b));
+  HIP_TRY(launch_chol(b.g, d, dp, b.r1, b.rinv, b.flags, c->info, orth_index, 0.0, mode, b.xf, s, t.a, t.b));
   t = timer(c, RQLP_KT_APPLY);
-  HIP_TRY((launch_apply<T, double>(Y, ldy, rows, d, dp, b.r1, b.rinv, b.flags, b.q1, dp, dp, nullptr, 0, 0,
-                                   seed, completion_key(orth_index, 0), s, t.a, t.b)));
+  HIP_TRY((launch_apply<T, double>(Y, ldy, rows, d, dp, b.r1, b.rinv, b.flags, mode, b.xf, b.q1, dp, dp, nullptr,
+                                   0, 0, seed, completion_key(orth_index, 0), s, t.a, t.b)));
   t = timer(c, RQLP_KT_GRAM);
   HIP_TRY(launch_gram<double>(b.q1, dp, rows, d, dp, b.gp, gch, b.g, c->info, s, t.a, t.b));
   t = timer(c, RQLP_KT_CHOL);
-  HIP_TRY(launch_chol(b.g, d, dp, b.r2, b.rinv, b.flags + dp, c->info, orth_index, s, t.a, t.b));
+  HIP_TRY(launch_chol(b.g, d, dp, b.r2, b.rinv, b.flags + dp, c->info, orth_index, ftol, mode + 1, b.xf, s, t.a,
+                      t.b));
   t = timer(c, RQLP_KT_APPLY);
-  HIP_TRY((launch_apply<double, T>(b.q1, dp, rows, d, dp, b.r2, b.rinv, b.flags + dp, out1, ld1, ncols1, out2,
-                                   ld2, ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b)));
+  HIP_TRY((launch_apply<double, T>(b.q1, dp, rows, d, dp, b.r2, b.rinv, b.flags + dp, mode + 1, b.xf, out1, ld1,
+                                   ncols1, out2, ld2, ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b)));
   return RQLP_OK;
 }
 
 template <typename T>
 rqlp_status gemm(rqlp_ctx* c, int trans, const T* A, int64_t lda, int64_t m, int64_t n, const T* X,
-                 int64_t ldx, int d, T* Y, int64_t ldy, int nst, T* P, hipStream_t s) {
+                 int64_t ldx, int d, T* Y, int64_t ldy, int nst, T* P, hipStream_t s, bool padded_x) {
   // trans = 0: Y (m x nst) = A X (K = n); trans = 1: Y (n x nst) = A^T X (K = m)
   const int M = (int)(trans ? n : m), K = (int)(trans ? m : n);
   GemmArgs<T> g = plan_gemm<T>(trans, A, lda, X, ldx, M, d, K);
+  // internal operands have ld = dp and zero padding columns: vector loads
+  const int vec = 16 / (int)sizeof(T);
+  g.bvec = padded_x && ldx == gemm_block_cols<T>(d) && ldx % vec == 0 && (((uintptr_t)X & 15) == 0);
   EvPair t = timer(c, trans ? RQLP_KT_GEMM_TN : RQLP_KT_GEMM_NN);
   HIP_TRY(launch_gemm<T>(g, Y, ldy, nst, P, s, t.a, t.b));
   return RQLP_OK;
@@ -258,6 +272,7 @@ rqlp_status run_method(rqlp_ctx* c, char* base, const Layout& Lo, int64_t m, int
   b.r2 = (double*)(base + Lo.r2);
   b.rinv = (double*)(base + Lo.rinv);
   b.flags = (int32_t*)(base + Lo.flags);
+  b.xf = (double*)(base + Lo.xf);
   rqlp_status st;
   HIP_TRY(launch_info_reset(c->info, s));
   // Omega (n x d, ld dp), then Y = A Omega and Q = orth(Y)
@@ -290,8 +305,8 @@ rqlp_status decompose_dense(rqlp_ctx* c, const T* A, int64_t m, int64_t n, int64
   rqlp_status st = get_workspace(c, ws, ws_bytes, Lo.total, &base);
   if (st != RQLP_OK) return st;
   T* part = (T*)(base + Lo.part);
-  auto mulA = [&](const T* X, T* Y) { return gemm<T>(c, 0, A, lda, m, n, X, dp, d, Y, dp, dp, part, s); };
-  auto mulAt = [&](const T* X, T* Y) { return gemm<T>(c, 1, A, lda, m, n, X, dp, d, Y, dp, dp, part, s); };
+  auto mulA = [&](const T* X, T* Y) { return gemm<T>(c, 0, A, lda, m, n, X, dp, d, Y, dp, dp, part, s, true); };
+  auto mulAt = [&](const T* X, T* Y) { return gemm<T>(c, 1, A, lda, m, n, X, dp, d, Y, dp, dp, part, s, true); };
   return run_method<T>(c, base, Lo, m, n, k, p, q, seed, Q, L, V, s, mulA, mulAt);
 }
 
@@ -329,7 +344,8 @@ size_t orth_ws_bytes(int64_t rows, int d, rqlp_precision prec) {
   put((size_t)gram_chunks(rows, dp) * dp * dp * sizeof(double));  // gp
   put((size_t)dp * dp * sizeof(double) * 3);                      // g, r1, r2
   put((size_t)dp * kTile * sizeof(double));                       // rinv
-  put((size_t)2 * dp * sizeof(int32_t));                          // flags
+  put((size_t)(2 * dp + 2) * sizeof(int32_t));                    // flags, modes
+  put((size_t)dp * dp * sizeof(double));                          // explicit inverse
   put((size_t)rows * dp * (prec == RQLP_FP64 ? 8 : 4));           // padded copy of the output
   (void)prec;
   return off + 256;
@@ -483,9 +499,9 @@ rqlp_status rqlp_gemm(rqlp_ctx* c, int trans, const void* A, int64_t m, int64_t 
   // the partial buffer is laid out with row length d here (nst = d)
   if (prec == RQLP_FP64)
     return gemm<double>(c, trans, (const double*)A, lda, m, n, (const double*)X, ldx, d, (double*)Y, ldy, d,
-                        (double*)base, s);
+                        (double*)base, s, false);
   return gemm<float>(c, trans, (const float*)A, lda, m, n, (const float*)X, ldx, d, (float*)Y, ldy, d,
-                     (float*)base, s);
+                     (float*)base, s, false);
 }
 
 size_t rqlp_orth_workspace_size(int64_t rows, int d, rqlp_precision prec) {
@@ -515,7 +531,8 @@ rqlp_status rqlp_orth(rqlp_ctx* c, const void* Y, int64_t rows, int d, int64_t l
   b.r1 = b.g + (size_t)dp * dp;
   b.r2 = b.r1 + (size_t)dp * dp;
   b.rinv = (double*)take((size_t)dp * kTile * sizeof(double));
-  b.flags = (int32_t*)take((size_t)2 * dp * sizeof(int32_t));
+  b.flags = (int32_t*)take((size_t)(2 * dp + 2) * sizeof(int32_t));
+  b.xf = (double*)take((size_t)dp * dp * sizeof(double));
   HIP_TRY(launch_info_reset(c->info, s));
   if (prec == RQLP_FP64) {
     st = cholqr2<double>(c, (const double*)Y, ldy, rows, d, b, (double*)Q, ldq, d, nullptr, 0, 0, seed, 1, s);
