@@ -113,6 +113,7 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
                                                     double* __restrict__ Rinv16,
                                                     int32_t* __restrict__ flags, DevInfo* info,
                                                     int pass_id, double tol, double fast_tol,
+                                                    const double* __restrict__ esq, int nesq,
                                                     int32_t* __restrict__ mode,
                                                     double* __restrict__ Xfull) {
   __shared__ double Pn[kDMax / kTile][kTile][kTile + 1];  // panel tiles L_ik
@@ -128,20 +129,19 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
   const int lr = lane >> 4, lc = lane & 15;  // MFMA accumulator layout: row lr + 4 r, col lc
 
   // ---------------- fast path: G close to the identity ----------------
+  // ||G - I||_F^2 comes as per-block partial sums from the Gram reduction;
+  // every workgroup adds them in the same fixed order.
   if (fast_tol > 0.0) {
     double ss = 0.0;
-    for (int e = tid; e < d * d; e += blockDim.x) {
-      const int i = e / d, j = e - (e / d) * d;
-      const double v = G[(int64_t)i * dp + j] - (i == j ? 1.0 : 0.0);
-      ss += v * v;
-    }
+    for (int e = tid; e < nesq; e += blockDim.x) ss += esq[e];
     for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
     if (lane == 0) red[wave] = ss;
     __syncthreads();
     double tot = 0.0;
     for (int w = 0; w < kCholWaves; ++w) tot += red[w];
     if (tot < fast_tol * fast_tol) {  // false for NaN
-      for (int e = tid; e < dp * dp; e += blockDim.x) {
+      // all workgroups write their share of R = I + F, R^-1 = I - F
+      for (int e = blockIdx.x * blockDim.x + tid; e < dp * dp; e += gridDim.x * blockDim.x) {
         const int i = e / dp, j = e - (e / dp) * dp;
         double f = 0.0;  // F[i][j]
         if (i < d && j < d && i <= j) {
@@ -154,12 +154,13 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
         if ((i >> 4) == (j >> 4))
           Rinv16[(int64_t)(i >> 4) * kTile * kTile + (i & 15) * kTile + (j & 15)] = id - f;
       }
-      for (int i = tid; i < dp; i += blockDim.x) flags[i] = 0;
-      if (tid == 0) *mode = 1;
+      for (int i = blockIdx.x * blockDim.x + tid; i < dp; i += gridDim.x * blockDim.x) flags[i] = 0;
+      if (blockIdx.x == 0 && tid == 0) *mode = 1;
       return;
     }
     __syncthreads();
   }
+  if (blockIdx.x != 0) return;  // the factorization runs in one workgroup
   if (tid == 0) *mode = 0;
 
   // ---------------- full factorization ----------------
@@ -268,23 +269,24 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
 }
 
 hipError_t launch_chol(const double* G, int d, int dp, double* R, double* Rinv16, int32_t* flags,
-                       void* info, int pass_id, double fast_tol, int32_t* mode, double* Xfull,
-                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                       void* info, int pass_id, double fast_tol, const double* esq, int nesq,
+                       int32_t* mode, double* Xfull, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const double tol = 64.0 * (double)d * 2.220446049250313e-16;
   if (ev0) (void)hipEventRecord(ev0, s);
   const int T = dp / kTile;
   // register slots per wave for the T (T + 1) / 2 lower tiles (waves x
   // slots chosen so that tiles and the diagonal-block code fit in registers)
   const int tiles = T * (T + 1) / 2;
+  const unsigned grid = fast_tol > 0.0 ? 16 : 1;  // extra workgroups only help the fast path
   if (tiles <= 8 * 7)
-    hipLaunchKernelGGL((chol_kernel<8, 7>), dim3(1), dim3(8 * kWave), 0, s, G, d, dp, R, Rinv16, flags,
-                       (DevInfo*)info, pass_id, tol, fast_tol, mode, Xfull);
+    hipLaunchKernelGGL((chol_kernel<8, 7>), dim3(grid), dim3(8 * kWave), 0, s, G, d, dp, R, Rinv16, flags,
+                       (DevInfo*)info, pass_id, tol, fast_tol, esq, nesq, mode, Xfull);
   else if (tiles <= 8 * 14)
-    hipLaunchKernelGGL((chol_kernel<8, 14>), dim3(1), dim3(8 * kWave), 0, s, G, d, dp, R, Rinv16, flags,
-                       (DevInfo*)info, pass_id, tol, fast_tol, mode, Xfull);
+    hipLaunchKernelGGL((chol_kernel<8, 14>), dim3(grid), dim3(8 * kWave), 0, s, G, d, dp, R, Rinv16, flags,
+                       (DevInfo*)info, pass_id, tol, fast_tol, esq, nesq, mode, Xfull);
   else
-    hipLaunchKernelGGL((chol_kernel<8, 17>), dim3(1), dim3(8 * kWave), 0, s, G, d, dp, R, Rinv16, flags,
-                       (DevInfo*)info, pass_id, tol, fast_tol, mode, Xfull);
+    hipLaunchKernelGGL((chol_kernel<8, 17>), dim3(grid), dim3(8 * kWave), 0, s, G, d, dp, R, Rinv16, flags,
+                       (DevInfo*)info, pass_id, tol, fast_tol, esq, nesq, mode, Xfull);
   if (ev1) (void)hipEventRecord(ev1, s);
   return hipGetLastError();
 }

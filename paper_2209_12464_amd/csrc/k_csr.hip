@@ -75,10 +75,10 @@ hipError_t launch_spmm(const int32_t* rowptr, const int32_t* colidx, const T* va
                        const T* X, int64_t ldx, int d, T* Y, int64_t ldy, int nst, hipStream_t s,
                        hipEvent_t ev0, hipEvent_t ev1) {
   if (rows <= 0) return hipSuccess;
-  if (ev0) hipEventRecord(ev0, s);
+  if (ev0) (void)hipEventRecord(ev0, s);
   hipLaunchKernelGGL(spmm_kernel<T>, dim3((unsigned)ceil_div(rows, kSpmmWaves)), dim3(kSpmmWaves * 64), 0, s,
                      rowptr, colidx, vals, rows, X, ldx, d, Y, ldy, nst);
-  if (ev1) hipEventRecord(ev1, s);
+  if (ev1) (void)hipEventRecord(ev1, s);
   return hipGetLastError();
 }
 template hipError_t launch_spmm<float>(const int32_t*, const int32_t*, const float*, int64_t, const float*,

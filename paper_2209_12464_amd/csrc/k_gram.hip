@@ -11,7 +11,7 @@
 namespace rqlp {
 
 constexpr int kGT = 64;   // output tile side
-constexpr int kGK = 16;   // rows of Y per LDS step
+constexpr int kGK = 32;   // rows of Y per LDS step
 
 __device__ inline void tile_pair(int p, int& I, int& J) {
   // p enumerates (I, J), I <= J, row by row of the upper triangle of a t x t grid
@@ -28,9 +28,10 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
                                                            int64_t rows, int d, int dp,
                                                            int64_t chunk_rows, int npairs,
                                                            double* __restrict__ P) {
-  __shared__ double YI[kGK][kGT + 1];
-  __shared__ double YJ[kGK][kGT + 1];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double YI[2][kGK][kGT + 1];
+  __shared__ double YJ[2][kGK][kGT + 1];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int pair = blockIdx.x % npairs;
   const int chunk = blockIdx.x / npairs;
   int I, J;
@@ -42,31 +43,55 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<double>::zero();
 
-  for (int64_t k0 = r0; k0 < r1; k0 += kGK) {
+  // The prefetch registers hold the raw inputs: widening to double happens
+  // at the LDS store, so the loads stay in flight across the MFMA loop.
+  constexpr int PER = kGK * kGT / 256;  // elements per thread per tile
+  T ri[PER], rj[PER];
+  auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int i = 0; i < kGK * kGT / 256; ++i) {
+    for (int i = 0; i < PER; ++i) {
       const int idx = tid + 256 * i;
       const int kr = idx / kGT, c = idx % kGT;
       const int64_t r = k0 + kr;
       const int ci = I * kGT + c, cj = J * kGT + c;
-      YI[kr][c] = (r < r1 && ci < d) ? (double)Y[r * ldy + ci] : 0.0;
-      YJ[kr][c] = (r < r1 && cj < d) ? (double)Y[r * ldy + cj] : 0.0;
+      ri[i] = (r < r1 && ci < d) ? Y[r * ldy + ci] : (T)0;
+      rj[i] = (r < r1 && cj < d) ? Y[r * ldy + cj] : (T)0;
     }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int idx = tid + 256 * i;
+      YI[buf][idx / kGT][idx % kGT] = (double)ri[i];
+      YJ[buf][idx / kGT][idx % kGT] = (double)rj[i];
+    }
+  };
+
+  if (r0 < r1) {
+    load(r0);
+    store(0);
     __syncthreads();
+    int buf = 0;
+    for (int64_t k0 = r0; k0 < r1; k0 += kGK) {
+      const bool more = k0 + kGK < r1;
+      if (more) load(k0 + kGK);
 #pragma unroll
-    for (int ks = 0; ks < kGK / 4; ++ks) {
-      double a[2], b[2];
+      for (int ks = 0; ks < kGK / 4; ++ks) {
+        double a[2], b[2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        a[t] = YI[ks * 4 + lane / 16][wi * 32 + t * 16 + (lane & 15)];
-        b[t] = YJ[ks * 4 + lane / 16][wj * 32 + t * 16 + (lane & 15)];
+        for (int t = 0; t < 2; ++t) {
+          a[t] = YI[buf][ks * 4 + lane / 16][wi * 32 + t * 16 + (lane & 15)];
+          b[t] = YJ[buf][ks * 4 + lane / 16][wj * 32 + t * 16 + (lane & 15)];
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<double>::mma(a[x], b[y], acc[x][y]);
       }
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<double>::mma(a[x], b[y], acc[x][y]);
+      if (more) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
     }
-    __syncthreads();
   }
   double* Pc = P + (int64_t)chunk * dp * dp;
 #pragma unroll
@@ -82,26 +107,52 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
 }
 
 // G[i][j] = G[j][i] = sum over chunks of P[c][i][j] for i <= j (fixed order).
+// Each block also writes esq[block] = its share of ||G - I||_F^2 over the
+// d x d part (fixed-order reduction; NaN propagates), which the Cholesky
+// sums in a fixed order to decide on its fast path.
 __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ P, int nchunks,
-                                                          int dp, double* __restrict__ G,
-                                                          DevInfo* info) {
+                                                          int d, int dp, double* __restrict__ G,
+                                                          double* __restrict__ esq, DevInfo* info) {
+  __shared__ double red[4];
   const int64_t total = (int64_t)dp * dp;
   bool bad = false;
+  double e2 = 0.0;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / dp), j = (int)(e % dp);
     if (i > j) continue;
     // (i, j) lies in tile (i/64, j/64) with i/64 <= j/64: written by every chunk
     double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += P[(int64_t)c * total + e];
+    const double* p = P + e;
+    int c = 0;
+    for (; c + 8 <= nchunks; c += 8) {  // loads first, then the ordered adds
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(c + u) * total];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < nchunks; ++c) s += p[(int64_t)c * total];
     if (!isfinite(s)) bad = true;
     G[(int64_t)i * dp + j] = s;
     G[(int64_t)j * dp + i] = s;
+    if (j < d) {
+      const double v = s - (i == j ? 1.0 : 0.0);
+      e2 += (i == j ? 1.0 : 2.0) * v * v;
+    }
   }
   if (bad) atomicOr(&info->nonfinite, 1);
+  for (int off = 32; off > 0; off >>= 1) e2 += __shfl_xor(e2, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e2;
+  __syncthreads();
+  if (threadIdx.x == 0) esq[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+int gram_reduce_blocks(int dp) { return (int)ceil_div((int64_t)dp * dp, 256); }
+
 int gram_chunks(int64_t rows, int dp) {
+  // about 512 workgroups in total, two per CU, so that one workgroup's
+  // MFMAs cover the other's load latency
   const int t = (int)ceil_div(dp, kGT);
   const int npairs = t * (t + 1) / 2;
   int64_t chunks = ceil_div(512, npairs);
@@ -114,23 +165,22 @@ int gram_chunks(int64_t rows, int dp) {
 
 template <typename T>
 hipError_t launch_gram(const T* Y, int64_t ldy, int64_t rows, int d, int dp, double* P,
-                       int nchunks, double* G, void* info, hipStream_t s, hipEvent_t ev0,
-                       hipEvent_t ev1) {
+                       int nchunks, double* G, double* esq, void* info, hipStream_t s,
+                       hipEvent_t ev0, hipEvent_t ev1) {
   const int t = (int)ceil_div(dp, kGT);
   const int npairs = t * (t + 1) / 2;
   const int64_t chunk_rows = round_up(ceil_div(rows, nchunks), kGK);
-  if (ev0) hipEventRecord(ev0, s);
+  if (ev0) (void)hipEventRecord(ev0, s);
   hipLaunchKernelGGL(gram_partial_kernel<T>, dim3(npairs * nchunks), dim3(256), 0, s, Y, ldy, rows, d,
                      dp, chunk_rows, npairs, P);
-  if (ev1) hipEventRecord(ev1, s);
-  const int64_t g = ceil_div((int64_t)dp * dp, 256);
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)g), dim3(256), 0, s, P, nchunks, dp, G,
-                     (DevInfo*)info);
+  if (ev1) (void)hipEventRecord(ev1, s);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)gram_reduce_blocks(dp)), dim3(256), 0, s, P, nchunks,
+                     d, dp, G, esq, (DevInfo*)info);
   return hipGetLastError();
 }
 template hipError_t launch_gram<float>(const float*, int64_t, int64_t, int, int, double*, int,
-                                       double*, void*, hipStream_t, hipEvent_t, hipEvent_t);
+                                       double*, double*, void*, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_gram<double>(const double*, int64_t, int64_t, int, int, double*, int,
-                                        double*, void*, hipStream_t, hipEvent_t, hipEvent_t);
+                                        double*, double*, void*, hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace rqlp

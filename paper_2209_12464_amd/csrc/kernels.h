@@ -42,24 +42,28 @@ hipError_t launch_gemm(GemmArgs<T> g, T* Y, int64_t ldy, int nst, T* P, hipStrea
 // ---- float64 Gram matrix (k_gram.hip) ----
 // G (dp x dp, ld dp, float64, full symmetric) = Y^T Y over rows [0, rows),
 // columns [0, d) of Y (ldy); entries outside d x d are zero.  Partials:
-// nchunks * dp * dp doubles in P.  Sets info->nonfinite on NaN/Inf.
+// nchunks * dp * dp doubles in P.  Sets info->nonfinite on NaN/Inf.  esq
+// (gram_reduce_blocks(dp) doubles) receives block partial sums of
+// ||G - I||_F^2 over the d x d part.
 template <typename T>
 hipError_t launch_gram(const T* Y, int64_t ldy, int64_t rows, int d, int dp, double* P,
-                       int nchunks, double* G, void* info, hipStream_t s, hipEvent_t ev0,
-                       hipEvent_t ev1);
+                       int nchunks, double* G, double* esq, void* info, hipStream_t s,
+                       hipEvent_t ev0, hipEvent_t ev1);
 int gram_chunks(int64_t rows, int dp);
+int gram_reduce_blocks(int dp);
 
 // ---- float64 Cholesky (k_chol.hip) ----
 // G = R^T R for the d x d leading block of G (ld dp).  Writes R (upper,
 // dp x dp, ld dp, identity beyond d; rows of dependent columns are e_j^T),
 // Rinv16 (inverses of the dp/16 diagonal 16x16 blocks of R, row-major
 // 16x16 each), flags[j] = 1 for dependent columns (j < dp).  Updates info.
-// fast_tol > 0: when ||G - I||_F < fast_tol, use R = I + F (first order)
+// fast_tol > 0: when ||G - I||_F < fast_tol (from the nesq partial sums in
+// esq written by launch_gram), use R = I + F (first order)
 // and write the explicit inverse I - F to Xfull (dp x dp); *mode is set to
 // 1 in that case, 0 after a full factorization.
 hipError_t launch_chol(const double* G, int d, int dp, double* R, double* Rinv16, int32_t* flags,
-                       void* info, int pass_id, double fast_tol, int32_t* mode, double* Xfull,
-                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+                       void* info, int pass_id, double fast_tol, const double* esq, int nesq,
+                       int32_t* mode, double* Xfull, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 
 // ---- triangular solve Q = Y R^-1 (k_apply.hip) ----
 // Y: rows x dp (ldy, type Tin); out1 (ld1, first `ncols1` columns, type

@@ -126,7 +126,7 @@ size_t gemm_partial_elems(int M, int K, int dp) {
 
 // Layout of the dense / CSR decomposition workspace.
 struct Layout {
-  size_t om, yb, qi, q1, part, gp, g, r1, r2, rinv, flags, xf, csr_rt, csr_ct, csr_vt, csr_scr, total;
+  size_t om, yb, qi, q1, part, gp, g, r1, r2, rinv, flags, xf, esq, csr_rt, csr_ct, csr_vt, csr_scr, total;
 };
 
 template <typename T>
@@ -151,6 +151,7 @@ Layout layout(int64_t m, int64_t n, int d, bool sparse, int64_t nnz) {
   L.rinv = put((size_t)dp * kTile * sizeof(double));
   L.flags = put((size_t)(2 * dp + 2) * sizeof(int32_t));
   L.xf = put((size_t)dp * dp * sizeof(double));
+  L.esq = put((size_t)gram_reduce_blocks(dp) * sizeof(double));
   if (sparse) {
     L.csr_rt = put((size_t)(n + 1) * sizeof(int32_t));
     L.csr_ct = put((size_t)nnz * sizeof(int32_t));
@@ -186,7 +187,7 @@ rqlp_status get_workspace(rqlp_ctx* c, void* ws, size_t ws_bytes, size_t need, c
 }
 
 struct Bufs {
-  double *q1, *gp, *g, *r1, *r2, *rinv, *xf;
+  double *q1, *gp, *g, *r1, *r2, *rinv, *xf, *esq;
   int32_t* flags;  // 2 dp dependent-column flags, then the two pass modes
 };
 
@@ -211,19 +212,21 @@ rqlp_status cholqr2(rqlp_ctx* c, const T* Y, int64_t ldy, int64_t rows, int d, c
   const int gch = gram_chunks(rows, dp);
   const double ftol = fast_tol_for(sizeof(T) == 8);
   int32_t* mode = b.flags + 2 * dp;
+  const int nesq = gram_reduce_blocks(dp);
   EvPair t;
   t = timer(c, RQLP_KT_GRAM);
-  HIP_TRY(launch_gram<T>(Y, ldy, rows, d, dp, b.gp, gch, b.g, c->info, s, t.a, t.b));
+  HIP_TRY(launch_gram<T>(Y, ldy, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
   t = timer(c, RQLP_KT_CHOL);
-  HIP_TRY(launch_chol(b.g, d, dp, b.r1, b.rinv, b.flags, c->info, orth_index, 0.0, mode, b.xf, s, t.a, t.b));
+  HIP_TRY(launch_chol(b.g, d, dp, b.r1, b.rinv, b.flags, c->info, orth_index, 0.0, b.esq, nesq, mode, b.xf, s, t.a,
+                      t.b));
   t = timer(c, RQLP_KT_APPLY);
   HIP_TRY((launch_apply<T, double>(Y, ldy, rows, d, dp, b.r1, b.rinv, b.flags, mode, b.xf, b.q1, dp, dp, nullptr,
                                    0, 0, seed, completion_key(orth_index, 0), s, t.a, t.b)));
   t = timer(c, RQLP_KT_GRAM);
-  HIP_TRY(launch_gram<double>(b.q1, dp, rows, d, dp, b.gp, gch, b.g, c->info, s, t.a, t.b));
+  HIP_TRY(launch_gram<double>(b.q1, dp, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
   t = timer(c, RQLP_KT_CHOL);
-  HIP_TRY(launch_chol(b.g, d, dp, b.r2, b.rinv, b.flags + dp, c->info, orth_index, ftol, mode + 1, b.xf, s, t.a,
-                      t.b));
+  HIP_TRY(launch_chol(b.g, d, dp, b.r2, b.rinv, b.flags + dp, c->info, orth_index, ftol, b.esq, nesq, mode + 1,
+                      b.xf, s, t.a, t.b));
   t = timer(c, RQLP_KT_APPLY);
   HIP_TRY((launch_apply<double, T>(b.q1, dp, rows, d, dp, b.r2, b.rinv, b.flags + dp, mode + 1, b.xf, out1, ld1,
                                    ncols1, out2, ld2, ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b)));
@@ -273,6 +276,7 @@ rqlp_status run_method(rqlp_ctx* c, char* base, const Layout& Lo, int64_t m, int
   b.rinv = (double*)(base + Lo.rinv);
   b.flags = (int32_t*)(base + Lo.flags);
   b.xf = (double*)(base + Lo.xf);
+  b.esq = (double*)(base + Lo.esq);
   rqlp_status st;
   HIP_TRY(launch_info_reset(c->info, s));
   // Omega (n x d, ld dp), then Y = A Omega and Q = orth(Y)
@@ -346,6 +350,7 @@ size_t orth_ws_bytes(int64_t rows, int d, rqlp_precision prec) {
   put((size_t)dp * kTile * sizeof(double));                       // rinv
   put((size_t)(2 * dp + 2) * sizeof(int32_t));                    // flags, modes
   put((size_t)dp * dp * sizeof(double));                          // explicit inverse
+  put((size_t)gram_reduce_blocks(dp) * sizeof(double));           // ||G - I||^2 partials
   put((size_t)rows * dp * (prec == RQLP_FP64 ? 8 : 4));           // padded copy of the output
   (void)prec;
   return off + 256;
@@ -533,6 +538,7 @@ rqlp_status rqlp_orth(rqlp_ctx* c, const void* Y, int64_t rows, int d, int64_t l
   b.rinv = (double*)take((size_t)dp * kTile * sizeof(double));
   b.flags = (int32_t*)take((size_t)(2 * dp + 2) * sizeof(int32_t));
   b.xf = (double*)take((size_t)dp * dp * sizeof(double));
+  b.esq = (double*)take((size_t)gram_reduce_blocks(dp) * sizeof(double));
   HIP_TRY(launch_info_reset(c->info, s));
   if (prec == RQLP_FP64) {
     st = cholqr2<double>(c, (const double*)Y, ldy, rows, d, b, (double*)Q, ldq, d, nullptr, 0, 0, seed, 1, s);
