@@ -1,74 +1,113 @@
 // Q = Y R^-1 for the upper-triangular Cholesky factor R (float64), the last
-// step of each CholeskyQR pass.  Rows are independent: one wave owns 16
-// rows and walks the 16-column blocks J in order,
-//     acc   = Y[:, J] - sum_{t < J} Q[:, t] R[t, J]      (float64 MFMA)
-//     Q[:,J] = acc * inv(R[J, J])                        (4 MFMAs)
-// keeping its finished Q blocks in LDS as the A operand of later blocks.
-// Arithmetic is float64 whatever the storage type of Y and Q.
-// Columns the Cholesky marked dependent are replaced by N(0,1)/sqrt(rows)
-// columns from a Philox stream of their own (completion of a rank-deficient
-// basis); their R rows are zero, so later columns do not depend on them.
-// When the Cholesky took its fast path it also wrote R^-1 explicitly; then
-// every 16 x 16 output block is an independent sum, Q[:,J] = sum_t Y[:,t]
-// X[t,J], and the grid's second dimension splits the column blocks into
-// groups of four so that four times as many waves share the work.
+// step of each CholeskyQR pass.  Arithmetic is float64 whatever the storage
+// type of Y and Q.  Normally R^-1 is available explicitly (the Cholesky's
+// fast path, or the inverse kernel after a full factorization), and every
+// 16 x 16 output block is an independent sum Q[:, J] = sum_{t <= J} Y[:, t]
+// X[t, J]: workgroups take 64 rows x 4 column blocks with LDS-staged tiles.
+// When the Cholesky marked a dependent column, a blocked substitution runs
+// instead, and those columns are replaced by N(0,1)/sqrt(rows) columns from
+// a Philox stream of their own (completion of a rank-deficient basis);
+// their R rows are zero, so later columns do not depend on them.
 #include "common.h"
 #include "kernels.h"
 
 namespace rqlp {
 
+constexpr int kApRows = 64;           // rows per workgroup (16 per wave)
+constexpr int kApCols = 4 * kTile;    // columns per workgroup (4 blocks)
+constexpr int kApXS = kApCols + 2;    // LDS row stride of the X tile (doubles)
+constexpr int kApYS = kTile + 1;      // LDS row stride of the Y tile (doubles)
+
+__host__ __device__ inline size_t apply_lds_doubles(int dp) {
+  const size_t expl = 2 * (size_t)(kTile * kApXS + kApRows * kApYS);
+  const size_t subst = (size_t)kTile * (dp + 1);
+  return expl > subst ? expl : subst;
+}
+
 template <typename Tin, typename Tout>
-__global__ __launch_bounds__(64) void apply_kernel(const Tin* __restrict__ Y, int64_t ldy, int64_t rows,
-                                                   int d, int dp, const double* __restrict__ R,
-                                                   const double* __restrict__ Rinv16,
-                                                   const int32_t* __restrict__ flags,
-                                                   const int32_t* __restrict__ mode,
-                                                   const double* __restrict__ Xfull,
-                                                   Tout* __restrict__ out1, int64_t ld1, int ncols1,
-                                                   Tout* __restrict__ out2, int64_t ld2, int ncols2,
-                                                   uint64_t seed, uint64_t key1, double inv_sqrt_rows) {
-  extern __shared__ double Qs[];  // [16][dp + 1]
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(256) void apply_kernel(const Tin* __restrict__ Y, int64_t ldy, int64_t rows,
+                                                    int d, int dp, const double* __restrict__ R,
+                                                    const double* __restrict__ Rinv16,
+                                                    const int32_t* __restrict__ flags,
+                                                    const int32_t* __restrict__ mode,
+                                                    const double* __restrict__ Xfull,
+                                                    Tout* __restrict__ out1, int64_t ld1, int ncols1,
+                                                    Tout* __restrict__ out2, int64_t ld2, int ncols2,
+                                                    uint64_t seed, uint64_t key1, double inv_sqrt_rows) {
+  extern __shared__ double smem[];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane >> 4, lc = lane & 15;
-  const int S = dp + 1;
-  const int64_t r0 = (int64_t)blockIdx.x * kTile;
+  const int64_t r0 = (int64_t)blockIdx.x * kApRows;
   const int T = dp / kTile;
 
-  if (*mode == 1) {
-    // explicit inverse: column blocks J in [4 g, 4 g + 4)
-    const int g = blockIdx.y;
-    const int J0 = 4 * g;
+  if (*mode != 0) {
+    // ---- explicit inverse: out[:, J] = sum_{t <= J} Y[:, t] X[t, J] ----
+    // Column blocks J0..J1-1; per block row t the X tile (16 x 64) and the
+    // Y tile (64 x 16, widened to double) are staged in LDS, double
+    // buffered, with the next t held in registers meanwhile.
+    const int J0 = 4 * blockIdx.y;
     if (J0 >= T) return;
     const int J1 = min(T, J0 + 4);
+    double* Xs = smem;                           // [2][16][kApXS]
+    double* Ys = smem + 2 * kTile * kApXS;       // [2][64][kApYS]
+    double xr[4];
+    Tin yr[4];
+    auto load = [&](int t) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + 256 * q;
+        const int kr = e >> 6, c = e & 63;       // X[t*16 + kr][J0*16 + c]
+        const int col = J0 * kTile + c;
+        xr[q] = (col < J1 * kTile) ? Xfull[(int64_t)(t * kTile + kr) * dp + col] : 0.0;
+        const int rr = e >> 4, cc = e & 15;      // Y[r0 + rr][t*16 + cc]
+        const int64_t row = r0 + rr;
+        const int ycol = t * kTile + cc;
+        yr[q] = (row < rows && ycol < d) ? Y[row * ldy + ycol] : (Tin)0;
+      }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + 256 * q;
+        Xs[buf * kTile * kApXS + (e >> 6) * kApXS + (e & 63)] = xr[q];
+        Ys[buf * kApRows * kApYS + (e >> 4) * kApYS + (e & 15)] = (double)yr[q];
+      }
+    };
     doublex4 acc[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[u] = Mfma<double>::zero();
-    const int64_t arow = r0 + lc;
+    load(0);
+    store(0);
+    __syncthreads();
+    int buf = 0;
     for (int t = 0; t < J1; ++t) {
+      const bool more = t + 1 < J1;
+      if (more) load(t + 1);
+      const double* xs = Xs + buf * kTile * kApXS;
+      const double* ys = Ys + buf * kApRows * kApYS + (wave * kTile + lc) * kApYS;
       double a[4];
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const int col = t * kTile + ks * 4 + lr;
-        a[ks] = (arow < rows && col < d) ? (double)Y[arow * ldy + col] : 0.0;
-      }
+      for (int ks = 0; ks < 4; ++ks) a[ks] = ys[ks * 4 + lr];  // A[m][k] = Y[16 w + m][t*16 + k]
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int J = J0 + u;
-        if (J < J1 && t <= J) {
+        if (J0 + u >= t && J0 + u < J1) {
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks)
-            acc[u] = Mfma<double>::mma(a[ks], Xfull[(int64_t)(t * kTile + ks * 4 + lr) * dp + J * kTile + lc],
-                                       acc[u]);
+            acc[u] = Mfma<double>::mma(a[ks], xs[(ks * 4 + lr) * kApXS + u * kTile + lc], acc[u]);
         }
       }
+      if (more) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int col = (J0 + u) * kTile + lc;
       if (J0 + u >= J1) break;
+      const int col = (J0 + u) * kTile + lc;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + lr + 4 * r;
+        const int64_t row = r0 + wave * kTile + lr + 4 * r;
         if (row < rows) {
           if (col < ncols1) out1[row * ld1 + col] = (Tout)acc[u][r];
           if (out2 && col < ncols2) out2[row * ld2 + col] = (Tout)acc[u][r];
@@ -77,67 +116,69 @@ __global__ __launch_bounds__(64) void apply_kernel(const Tin* __restrict__ Y, in
     }
     return;
   }
-  if (blockIdx.y != 0) return;
 
-  for (int J = 0; J < T; ++J) {
-    doublex4 acc;
+  // ---- blocked substitution (a dependent column was found) ----
+  // Wave 0 of the first column group walks the workgroup's four 16-row
+  // slabs one after another (this path is taken only for rank-deficient
+  // inputs); per slab it goes through the 16-column blocks J in order,
+  //     acc    = Y[:, J] - sum_{t < J} Q[:, t] R[t, J]      (float64 MFMA)
+  //     Q[:,J] = acc * inv(R[J, J])                         (4 MFMAs)
+  // keeping the finished Q blocks in LDS as the A operand of later blocks.
+  if (blockIdx.y != 0 || wave != 0) return;
+  double* Qs = smem;  // [16][dp + 1]
+  const int S = dp + 1;
+  for (int slab = 0; slab < kApRows / kTile; ++slab) {
+    const int64_t q0 = r0 + slab * kTile;
+    if (q0 >= rows) break;
+    for (int J = 0; J < T; ++J) {
+      doublex4 acc;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + lr + 4 * r;
-      const int col = J * kTile + lc;
-      acc[r] = (row < rows && col < d) ? (double)Y[row * ldy + col] : 0.0;
-    }
-    // acc -= Q[:, t-block] R[t-block, J-block]: all R fragments of column
-    // block J are requested first (one memory latency per block), and the
-    // sum is split over two accumulators to shorten the dependent chain.
-    double b[kDMax / kTile][4];
-#pragma unroll
-    for (int t = 0; t < kDMax / kTile; ++t)
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
-        b[t][ks] = (t < J) ? R[(int64_t)(t * kTile + ks * 4 + lr) * dp + J * kTile + lc] : 0.0;
-    doublex4 acc2 = Mfma<double>::zero();
-#pragma unroll
-    for (int t = 0; t < kDMax / kTile; ++t) {
-      if (t < J) {
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = q0 + lr + 4 * r;
+        const int col = J * kTile + lc;
+        acc[r] = (row < rows && col < d) ? (double)Y[row * ldy + col] : 0.0;
+      }
+      doublex4 acc2 = Mfma<double>::zero();
+      for (int t = 0; t < J; ++t) {
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
           const double a = -Qs[lc * S + t * kTile + ks * 4 + lr];
-          if (t & 1) acc2 = Mfma<double>::mma(a, b[t][ks], acc2);
-          else acc = Mfma<double>::mma(a, b[t][ks], acc);
+          const double b = R[(int64_t)(t * kTile + ks * 4 + lr) * dp + J * kTile + lc];
+          if (t & 1) acc2 = Mfma<double>::mma(a, b, acc2);
+          else acc = Mfma<double>::mma(a, b, acc);
         }
       }
-    }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] += acc2[r];
-    // stage acc as an A operand, then multiply by inv(R[J, J])
+      for (int r = 0; r < 4; ++r) acc[r] += acc2[r];
+      // stage acc as an A operand, then multiply by inv(R[J, J])
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Qs[(lr + 4 * r) * S + J * kTile + lc] = acc[r];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    doublex4 q = Mfma<double>::zero();
+      for (int r = 0; r < 4; ++r) Qs[(lr + 4 * r) * S + J * kTile + lc] = acc[r];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      doublex4 q = Mfma<double>::zero();
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const double a = Qs[lc * S + J * kTile + ks * 4 + lr];
-      const double b = Rinv16[(int64_t)J * kTile * kTile + (ks * 4 + lr) * kTile + lc];
-      q = Mfma<double>::mma(a, b, q);
-    }
-    const int col = J * kTile + lc;
-    const bool dep = (col < d) && flags[col] != 0;
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + lr + 4 * r;
-      double v = q[r];
-      if (dep) v = (row < rows) ? gaussian_at(seed, key1, (uint64_t)col * rows + row) * inv_sqrt_rows : 0.0;
-      Qs[(lr + 4 * r) * S + col] = v;
-      if (row < rows) {
-        if (col < ncols1) out1[row * ld1 + col] = (Tout)v;
-        if (out2 && col < ncols2) out2[row * ld2 + col] = (Tout)v;
+      for (int ks = 0; ks < 4; ++ks) {
+        const double a = Qs[lc * S + J * kTile + ks * 4 + lr];
+        const double b = Rinv16[(int64_t)J * kTile * kTile + (ks * 4 + lr) * kTile + lc];
+        q = Mfma<double>::mma(a, b, q);
       }
+      const int col = J * kTile + lc;
+      const bool dep = (col < d) && flags[col] != 0;
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = q0 + lr + 4 * r;
+        double v = q[r];
+        if (dep) v = (row < rows) ? gaussian_at(seed, key1, (uint64_t)col * rows + row) * inv_sqrt_rows : 0.0;
+        Qs[(lr + 4 * r) * S + col] = v;
+        if (row < rows) {
+          if (col < ncols1) out1[row * ld1 + col] = (Tout)v;
+          if (out2 && col < ncols2) out2[row * ld2 + col] = (Tout)v;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -148,12 +189,12 @@ hipError_t launch_apply(const Tin* Y, int64_t ldy, int64_t rows, int d, int dp, 
                         int64_t ld2, int ncols2, uint64_t seed, uint64_t key1, hipStream_t s,
                         hipEvent_t ev0, hipEvent_t ev1) {
   if (rows <= 0) return hipSuccess;
-  const size_t shmem = (size_t)kTile * (dp + 1) * sizeof(double);
+  const size_t shmem = apply_lds_doubles(dp) * sizeof(double);
   const double isr = 1.0 / sqrt((double)rows);
   const unsigned groups = (unsigned)ceil_div(dp / kTile, 4);
   if (ev0) (void)hipEventRecord(ev0, s);
-  hipLaunchKernelGGL((apply_kernel<Tin, Tout>), dim3((unsigned)ceil_div(rows, kTile), groups), dim3(64), shmem, s,
-                     Y, ldy, rows, d, dp, R, Rinv16, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2,
+  hipLaunchKernelGGL((apply_kernel<Tin, Tout>), dim3((unsigned)ceil_div(rows, kApRows), groups), dim3(256), shmem,
+                     s, Y, ldy, rows, d, dp, R, Rinv16, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2,
                      seed, key1, isr);
   if (ev1) (void)hipEventRecord(ev1, s);
   return hipGetLastError();

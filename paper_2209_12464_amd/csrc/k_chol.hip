@@ -6,12 +6,9 @@
 // lower triangle of G is cut into 16 x 16 tiles held in registers (MFMA
 // 16x16x4 accumulator layout: lane l holds rows l/16 + 4 s, column l % 16),
 // dealt round-robin to the waves.  Per block column k:
-//   A. the owner of tile (k,k) factors it in registers and, in the same
-//      sweep, forms the inverse of the 16 x 16 factor.  The trailing part
-//      is kept symmetric so that each lane finds the multiplier of its own
-//      column in row j; per pivot the lanes exchange data by one readlane
-//      (the pivot), one cross-lane shuffle (row j) and DPP row broadcasts
-//      (column j), and 1/sqrt is a hardware estimate plus Newton steps;
+//   A. the owner of tile (k,k) moves it to one column per lane and factors
+//      it there, forming the inverse of the 16 x 16 factor in the same
+//      sweep (every cross-lane value is a readlane broadcast);
 //   B. owners of tiles (i,k), i > k, form L_ik = G_ik L_kk^-T (4 MFMAs) and
 //      publish them in an LDS panel;
 //   C. owners of tiles (i,j), k < j <= i, update G_ij -= L_ik L_jk^T (MFMA).
@@ -61,50 +58,62 @@ __device__ inline double rsqrt_f64(double x) {
   return y;
 }
 
-// Value of x in lane N of this lane's 16-lane row (DPP row_newbcast).
-template <int N>
-__device__ inline double row_bcast(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x150 + N, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x150 + N, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
-// One pivot step of the 16 x 16 diagonal-tile factorization.  The tile is in
-// the MFMA accumulator layout (lane (g, c) = (l / 16, l % 16) holds rows
-// g + 4 r of column c) and is kept symmetric, so S[J][c] = S[c][J] gives
-// every lane the multiplier of its own column.  x accumulates L^-1 by rows.
-template <int J>
-__device__ inline void pivot_step(doublex4& a, doublex4& x, int lr, int lc, const double* gd, double tol,
-                                  int& depmask) {
-  constexpr int kSlot = J >> 2;
-  const double piv = bcast(a[kSlot], J + 16 * (J & 3));  // S[J][J]
-  const int src = lc + 16 * (J & 3);
-  const double sjc = __shfl(a[kSlot], src);             // S[J][c]
-  const double xj = __shfl(x[kSlot], src);              // running X[J][c]
-  const double orig = gd[J];
-  const bool dep = !(piv > tol * orig);
-  const double inv = dep ? 1.0 : rsqrt_f64(piv);
-  const double ljj = dep ? 1.0 : piv * inv;
-  const double lcj = dep ? 0.0 : sjc * inv;              // L[c][J]
-  const double xjc = xj * inv;                           // X[J][c]
+// 1/x to float64 accuracy: hardware estimate and two Newton steps.
+__device__ inline double rcp_f64(double x) {
+  double y = __builtin_amdgcn_rcp(x);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const double colj = row_bcast<J>(a[r]);              // S[g + 4 r][J]
-    const int row = lr + 4 * r;
-    const double lrj = dep ? 0.0 : colj * inv;           // L[g + 4 r][J]
-    if (lc > J) a[r] -= lrj * lcj;
-    else if (lc == J) a[r] = (row > J) ? lrj : (row == J ? ljj : 0.0);
-    if (row == J) x[r] = xjc;
-    else if (row > J) x[r] -= lrj * xjc;
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
   }
-  depmask |= dep ? (1 << J) : 0;
+  return y;
 }
 
-template <int J>
-__device__ inline void factor_tile(doublex4& a, doublex4& x, int lr, int lc, const double* gd, double tol,
-                                   int& depmask) {
-  pivot_step<J>(a, x, lr, lc, gd, tol, depmask);
-  if constexpr (J + 1 < kTile) factor_tile<J + 1>(a, x, lr, lc, gd, tol, depmask);
+// Factor the 16 x 16 diagonal tile S = L L^T in column-per-lane form and
+// form X = L^-1 in the same sweep.  Lane c < 16 holds column c of S in v[]
+// (both triangles, S symmetric); lane 16 + c holds column c of X (starting
+// as the identity).  Per pivot J every value another lane needs is column J
+// of S, read from lane J as wave-uniform scalars, and both halves apply the
+// same update v[r] -= S[r][J] * coef for r > J, with coef = S[J][c] / S[J][J]
+// (lanes c > J of S) or X[J][c] / S[J][J] (X), before row J is scaled by
+// 1 / sqrt(S[J][J]).  The chain from one pivot to the next is a reciprocal
+// and one FMA; 1/sqrt runs beside it.  On return lane c holds row c of L
+// (column c of R = L^T, zero below the diagonal) and lane 16 + c column c of
+// X; depmask has bit J set for each dependent pivot.  Lanes 32..63 repeat
+// lanes 0..31.
+__device__ inline void factor_diag_tile(double (&v)[kTile], int lane, double gdl, double tol,
+                                        int& depmask) {
+  // gdl: lane c holds the original squared norm of column c (the pivot test)
+  int c = lane & 15;
+  // opaque to the optimizer: keeps the per-step lane masks from being
+  // hoisted out of the block loop, where they would pin scalar registers
+  asm volatile("" : "+v"(c));
+  const bool xs = (lane & 16) != 0;  // this lane holds a column of X
+#pragma unroll
+  for (int J = 0; J < kTile; ++J) {
+    const double piv = bcast(v[J], J);  // S[J][J]
+    const bool dep = !(piv > tol * bcast(gdl, J));
+    // both chains are computed unconditionally (no branch) and selected
+    const double rp = dep ? 0.0 : rcp_f64(piv);
+    const double inv = dep ? 1.0 : rsqrt_f64(piv);
+    const bool upd = xs || c > J;
+    const double vj = v[J];  // S[J][c] or X[J][c]
+    const double coef = upd ? vj * rp : 0.0;
+#pragma unroll
+    for (int r = J + 1; r < kTile; ++r) v[r] = fma(-bcast(v[r], J), coef, v[r]);
+    double nv = upd ? vj * inv : vj;       // X[J][c], or L[c][J] for c > J
+    if (!xs && c > J && dep) nv = 0.0;
+    if (!xs && c == J) nv = dep ? 1.0 : piv * inv;  // L[J][J]
+    v[J] = nv;
+    depmask |= dep ? (1 << J) : 0;
+    __builtin_amdgcn_sched_barrier(0);  // keep the steps apart: bounds the live scalars
+  }
+  // lane c of S: entries below the diagonal of R = L^T are zero
+  if (!xs) {
+#pragma unroll
+    for (int r = 0; r < kTile; ++r)
+      if (r > c) v[r] = 0.0;
+  }
 }
 
 template <int NW, int SLOTS>
@@ -116,12 +125,11 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
                                                     const double* __restrict__ esq, int nesq,
                                                     int32_t* __restrict__ mode,
                                                     double* __restrict__ Xfull) {
-  __shared__ double Pn[kDMax / kTile][kTile][kTile + 1];  // panel tiles L_ik
+  __shared__ double Pn[kDMax / kTile][kTile][kTile + 1];  // panel tiles L_ik of column k
   __shared__ double Di[kTile][kTile + 1];                  // inverse of the diagonal factor
   __shared__ double Gdiag[kDMax];
   __shared__ int defl[kDMax];
-  constexpr int kCholWaves = NW;
-  __shared__ double red[kCholWaves];
+  __shared__ double red[NW];
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -138,7 +146,7 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
     if (lane == 0) red[wave] = ss;
     __syncthreads();
     double tot = 0.0;
-    for (int w = 0; w < kCholWaves; ++w) tot += red[w];
+    for (int w = 0; w < NW; ++w) tot += red[w];
     if (tot < fast_tol * fast_tol) {  // false for NaN
       // all workgroups write their share of R = I + F, R^-1 = I - F
       for (int e = blockIdx.x * blockDim.x + tid; e < dp * dp; e += gridDim.x * blockDim.x) {
@@ -155,13 +163,12 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
           Rinv16[(int64_t)(i >> 4) * kTile * kTile + (i & 15) * kTile + (j & 15)] = id - f;
       }
       for (int i = blockIdx.x * blockDim.x + tid; i < dp; i += gridDim.x * blockDim.x) flags[i] = 0;
-      if (blockIdx.x == 0 && tid == 0) *mode = 1;
+      if (blockIdx.x == 0 && tid == 0) *mode = 2;  // explicit inverse already written
       return;
     }
     __syncthreads();
   }
   if (blockIdx.x != 0) return;  // the factorization runs in one workgroup
-  if (tid == 0) *mode = 0;
 
   // ---------------- full factorization ----------------
   for (int i = tid; i < dp; i += blockDim.x) {
@@ -169,19 +176,21 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
     defl[i] = 0;
   }
   const int ntiles = T * (T + 1) / 2;
+  // slot sl of this wave holds tile t = wave + NW sl of the lower triangle,
+  // (i, j) packed as i + 256 (j + 1) (a free slot has j = -1)
   doublex4 tile[SLOTS];
-  int ti[SLOTS], tj[SLOTS];
+  int tij[SLOTS];
 #pragma unroll
   for (int sl = 0; sl < SLOTS; ++sl) {
-    const int t = wave + kCholWaves * sl;
-    ti[sl] = -1;
-    tj[sl] = -1;
-    if (t < ntiles) tile_of(t, ti[sl], tj[sl]);
+    const int t = wave + NW * sl;
+    int i0 = 0, j0 = -1;
+    if (t < ntiles) tile_of(t, i0, j0);
+    tij[sl] = __builtin_amdgcn_readfirstlane(i0 + 256 * (j0 + 1));
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       double v = 0.0;
       if (t < ntiles) {
-        const int row = ti[sl] * kTile + lr + 4 * r, col = tj[sl] * kTile + lc;
+        const int row = i0 * kTile + lr + 4 * r, col = j0 * kTile + lc;
         v = (row < d && col < d) ? G[(int64_t)row * dp + col] : (row == col ? 1.0 : 0.0);
       }
       tile[sl][r] = v;
@@ -190,42 +199,66 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
   int ndep_total = 0;
   __syncthreads();
 
-  for (int k = 0; k < T; ++k) {
-    const int tkk = k * (k + 1) / 2 + k;
-    // ---------------- A: factor the diagonal tile ----------------
-    if (wave == tkk % kCholWaves) {
-      const int sk = tkk / kCholWaves;
-      doublex4 a = tile[0];
+  // A: the owner of tile (k,k) factors it (column per lane) and publishes
+  // Di = L_kk^-1, the R block L_kk^T, its inverse and the dependent-column
+  // flags.
+  auto factor_diag = [&](int k, int sk) {
 #pragma unroll
-      for (int sl = 1; sl < SLOTS; ++sl)
-        if (sl == sk) a = tile[sl];
-      doublex4 x;  // running inverse, starts as I
+    for (int sl = 0; sl < SLOTS; ++sl)
+      if (sl == sk) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) x[r] = (lr + 4 * r == lc) ? 1.0 : 0.0;
-      int depmask = 0;
-      factor_tile<0>(a, x, lr, lc, &Gdiag[k * kTile], tol, depmask);
-      // a = L_kk (lower; rows lr + 4 r of column lc), x = L_kk^-1
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = lr + 4 * r;
-        Di[row][lc] = x[r];
-        // R block = L_kk^T, inverse of the R block = (L_kk^-1)^T
-        R[(int64_t)(k * kTile + lc) * dp + k * kTile + row] = a[r];
-        Rinv16[(int64_t)k * kTile * kTile + lc * kTile + row] = x[r];
+        for (int r = 0; r < 4; ++r) Di[lr + 4 * r][lc] = tile[sl][r];
       }
-      if (lane < kTile) {
-        const int dep_c = (depmask >> lane) & 1;
-        defl[k * kTile + lane] = dep_c;
-        flags[k * kTile + lane] = dep_c;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const bool xs = (lane & 16) != 0;
+    double v[kTile];
+#pragma unroll
+    for (int r = 0; r < kTile; ++r) v[r] = xs ? (r == lc ? 1.0 : 0.0) : Di[r][lc];
+    const double gdl = Gdiag[k * kTile + lc];
+    __builtin_amdgcn_wave_barrier();
+    int depmask = 0;
+    factor_diag_tile(v, lane, gdl, tol, depmask);
+    if (lane < kTile) {
+#pragma unroll
+      for (int r = 0; r < kTile; ++r) R[(int64_t)(k * kTile + r) * dp + k * kTile + lc] = v[r];  // R[r][c]
+      const int dep_c = (depmask >> lc) & 1;
+      defl[k * kTile + lc] = dep_c;
+      flags[k * kTile + lc] = dep_c;
+    } else if (lane < 2 * kTile) {
+#pragma unroll
+      for (int r = 0; r < kTile; ++r) {
+        Di[r][lc] = v[r];                                            // X[r][c]
+        Rinv16[(int64_t)k * kTile * kTile + lc * kTile + r] = v[r];  // (L^-1)^T
       }
-      ndep_total += __popc(depmask);
     }
+    ndep_total += __popc(depmask);
+  };
+
+  // G_ij -= L_ik L_jk^T for a tile of the trailing matrix (k < j <= i)
+  auto update_g = [&](doublex4& t, int i, int j) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kk = ks * 4 + lr;
+      t = Mfma<double>::mma(-Pn[i][lc][kk], Pn[j][lc][kk], t);  // B[kk][n] = L_jk[n][kk]
+    }
+  };
+
+  {  // A for k = 0
+    const int t0 = 0;
+    if (wave == t0 % NW) factor_diag(0, t0 / NW);
+  }
+  for (int k = 0; k < T; ++k) {
+    // Opaque to the optimizer: otherwise the LDS addresses of every slot are
+    // hoisted out of this loop and held in vector registers the tiles need.
+#pragma unroll
+    for (int sl = 0; sl < SLOTS; ++sl) asm volatile("" : "+s"(tij[sl]));
     __syncthreads();
     // ---------------- B: panel L_ik = G_ik L_kk^-T ----------------
 #pragma unroll
     for (int sl = 0; sl < SLOTS; ++sl) {
-      if (tj[sl] == k && ti[sl] > k) {
-        const int i = ti[sl];
+      const int i = tij[sl] & 255, j = (tij[sl] >> 8) - 1;
+      if (j == k && i > k) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) Pn[i][lr + 4 * r][lc] = tile[sl][r];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -243,25 +276,42 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
       }
     }
     __syncthreads();
-    // publish the panel: R = L^T above the diagonal block row k, zero below
-    for (int e = tid; e < (T - 1 - k) * kTile * kTile; e += blockDim.x) {
-      const int i = k + 1 + e / (kTile * kTile), row = (e / kTile) % kTile, col = e % kTile;
-      R[(int64_t)(k * kTile + col) * dp + i * kTile + row] = Pn[i][row][col];
-      R[(int64_t)(i * kTile + row) * dp + k * kTile + col] = 0.0;
-    }
-    // ---------------- C: trailing update ----------------
+    // ---------------- C: trailing update, with the next A looked ahead ----------------
+    // The owner of tile (k+1, k+1) updates it first and factors it at once;
+    // the other waves publish the panel (R = L^T above the diagonal block
+    // row k, zero below) and go on with their updates meanwhile.
+    const int kn = k + 1;
+    const int tn = kn * (kn + 1) / 2 + kn;
+    const int own = tn % NW;
+    const bool ahead = kn < T && wave == own;
+    const int sn = tn / NW;
+    if (ahead) {
 #pragma unroll
-    for (int sl = 0; sl < SLOTS; ++sl) {
-      if (tj[sl] > k) {
-        const int i = ti[sl], j = tj[sl];
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int kk = ks * 4 + lr;
-          tile[sl] = Mfma<double>::mma(-Pn[i][lc][kk], Pn[j][lc][kk], tile[sl]);  // B[kk][n] = L_jk[n][kk]
-        }
+      for (int sl = 0; sl < SLOTS; ++sl)
+        if (sl == sn) update_g(tile[sl], kn, kn);
+      factor_diag(kn, sn);
+    } else {
+      const int nt = (kn < T) ? NW - 1 : NW;                 // publishing waves
+      const int pw = (kn < T && wave > own) ? wave - 1 : wave;  // rank among them
+      for (int e = pw * kWave + lane; e < (T - 1 - k) * kTile * kTile; e += nt * kWave) {
+        const int i = k + 1 + e / (kTile * kTile), row = (e / kTile) % kTile, col = e % kTile;
+        R[(int64_t)(k * kTile + col) * dp + i * kTile + row] = Pn[i][row][col];
+        R[(int64_t)(i * kTile + row) * dp + k * kTile + col] = 0.0;
       }
     }
+#pragma unroll
+    for (int sl = 0; sl < SLOTS; ++sl) {
+      if (ahead && sl == sn) continue;
+      const int i = tij[sl] & 255, j = (tij[sl] >> 8) - 1;
+      if (j > k) update_g(tile[sl], i, j);
+    }
   }
+  // the explicit R^-1 (formed next by the inverse kernel) serves the solve
+  // unless a column was dependent
+  int anydep = 0;
+  for (int i = tid; i < dp; i += blockDim.x) anydep |= defl[i];
+  anydep = __syncthreads_or(anydep);
+  if (tid == 0) *mode = anydep ? 0 : 1;
   if (lane == 0 && ndep_total > 0) {
     atomicAdd(&info->completed_cols, ndep_total);
     atomicCAS(&info->breakdown_pass, 0, pass_id);

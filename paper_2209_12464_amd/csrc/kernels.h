@@ -50,6 +50,13 @@ hipError_t launch_gram(const T* Y, int64_t ldy, int64_t rows, int d, int dp, dou
                        int nchunks, double* G, double* esq, void* info, hipStream_t s,
                        hipEvent_t ev0, hipEvent_t ev1);
 int gram_chunks(int64_t rows, int dp);
+
+// X = R^-1 (dp x dp, row-major; the blocks on and above the diagonal are
+// written) from the upper Cholesky factor R and its diagonal-block
+// inverses; does nothing unless *mode == 1 (full factorization, no
+// dependent column).
+hipError_t launch_trinv(const double* R, const double* Rinv16, int dp, const int32_t* mode, double* X,
+                        hipStream_t s);
 int gram_reduce_blocks(int dp);
 
 // ---- float64 Cholesky (k_chol.hip) ----
@@ -60,7 +67,8 @@ int gram_reduce_blocks(int dp);
 // fast_tol > 0: when ||G - I||_F < fast_tol (from the nesq partial sums in
 // esq written by launch_gram), use R = I + F (first order)
 // and write the explicit inverse I - F to Xfull (dp x dp); *mode is set to
-// 1 in that case, 0 after a full factorization.
+// 2 in that case.  After a full factorization *mode is 1 (launch_trinv then
+// forms Xfull = R^-1), or 0 when a column was dependent.
 hipError_t launch_chol(const double* G, int d, int dp, double* R, double* Rinv16, int32_t* flags,
                        void* info, int pass_id, double fast_tol, const double* esq, int nesq,
                        int32_t* mode, double* Xfull, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
@@ -69,8 +77,8 @@ hipError_t launch_chol(const double* G, int d, int dp, double* R, double* Rinv16
 // Y: rows x dp (ldy, type Tin); out1 (ld1, first `ncols1` columns, type
 // Tout) and optional out2 (ld2, first `ncols2` columns).  Dependent columns (flags) are replaced
 // by Gaussian columns of stream (seed, key1) divided by sqrt(rows).
-// mode (device, from launch_chol): 1 -> Q = Y Xfull (explicit inverse),
-// 0 -> blocked substitution with R and Rinv16.
+// mode (device, from launch_chol): nonzero -> Q = Y Xfull (explicit
+// inverse), 0 -> blocked substitution with R and Rinv16.
 template <typename Tin, typename Tout>
 hipError_t launch_apply(const Tin* Y, int64_t ldy, int64_t rows, int d, int dp, const double* R,
                         const double* Rinv16, const int32_t* flags, const int32_t* mode,

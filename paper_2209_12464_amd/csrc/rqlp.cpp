@@ -219,6 +219,7 @@ rqlp_status cholqr2(rqlp_ctx* c, const T* Y, int64_t ldy, int64_t rows, int d, c
   t = timer(c, RQLP_KT_CHOL);
   HIP_TRY(launch_chol(b.g, d, dp, b.r1, b.rinv, b.flags, c->info, orth_index, 0.0, b.esq, nesq, mode, b.xf, s, t.a,
                       t.b));
+  HIP_TRY(launch_trinv(b.r1, b.rinv, dp, mode, b.xf, s));
   t = timer(c, RQLP_KT_APPLY);
   HIP_TRY((launch_apply<T, double>(Y, ldy, rows, d, dp, b.r1, b.rinv, b.flags, mode, b.xf, b.q1, dp, dp, nullptr,
                                    0, 0, seed, completion_key(orth_index, 0), s, t.a, t.b)));
@@ -227,6 +228,7 @@ rqlp_status cholqr2(rqlp_ctx* c, const T* Y, int64_t ldy, int64_t rows, int d, c
   t = timer(c, RQLP_KT_CHOL);
   HIP_TRY(launch_chol(b.g, d, dp, b.r2, b.rinv, b.flags + dp, c->info, orth_index, ftol, b.esq, nesq, mode + 1,
                       b.xf, s, t.a, t.b));
+  HIP_TRY(launch_trinv(b.r2, b.rinv, dp, mode + 1, b.xf, s));
   t = timer(c, RQLP_KT_APPLY);
   HIP_TRY((launch_apply<double, T>(b.q1, dp, rows, d, dp, b.r2, b.rinv, b.flags + dp, mode + 1, b.xf, out1, ld1,
                                    ncols1, out2, ld2, ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b)));
