@@ -6,9 +6,10 @@
 // lower triangle of G is cut into 16 x 16 tiles held in registers (MFMA
 // 16x16x4 accumulator layout: lane l holds rows l/16 + 4 s, column l % 16),
 // dealt round-robin to the waves.  Per block column k:
-//   A. the owner of tile (k,k) moves it to one column per lane and factors
-//      it there, forming the inverse of the 16 x 16 factor in the same
-//      sweep (every cross-lane value is a readlane broadcast);
+//   A. the owner of tile (k,k) factors it in four steps of 4 pivots: a
+//      4 x 4 factorization on wave-uniform scalars, then MFMAs for the
+//      panel, the rank-4 trailing update and the running inverse of the
+//      16 x 16 factor;
 //   B. owners of tiles (i,k), i > k, form L_ik = G_ik L_kk^-T (4 MFMAs) and
 //      publish them in an LDS panel;
 //   C. owners of tiles (i,j), k < j <= i, update G_ij -= L_ik L_jk^T (MFMA).
@@ -28,8 +29,6 @@
 
 namespace rqlp {
 
-constexpr double kFastPathTol = 0x1p-30;
-
 __device__ inline double bcast(double x, int lane) {
   // value of x in lane `lane` (wave-uniform index), as a scalar broadcast
   const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
@@ -46,7 +45,6 @@ __device__ inline void tile_of(int t, int& i, int& j) {
   j = t - ii * (ii + 1) / 2;
 }
 
-
 // 1/sqrt(x) to float64 accuracy: hardware estimate and two Newton steps.
 __device__ inline double rsqrt_f64(double x) {
   double y = __builtin_amdgcn_rsq(x);
@@ -58,62 +56,86 @@ __device__ inline double rsqrt_f64(double x) {
   return y;
 }
 
-// 1/x to float64 accuracy: hardware estimate and two Newton steps.
-__device__ inline double rcp_f64(double x) {
-  double y = __builtin_amdgcn_rcp(x);
+// One 4-pivot step of the 16 x 16 diagonal-tile factorization S = L L^T,
+// pivots j0..j0+3 (j0 = 4 B), with the tile in the MFMA accumulator layout
+// (lane (g, c) = (l / 16, l % 16) holds rows g + 4 r of column c, so
+// register B of lane (g, c) is S[j0 + g][c]) and X = L^-1 carried along in
+// the same layout:
+//   1. the 4 x 4 block D = S[j0.., j0..] is read as wave-uniform scalars and
+//      factored, D = L_D L_D^T, with M = L_D^-1 (dependent pivots get a unit
+//      column in L_D); the pivots' Schur updates use the L_D entries, so the
+//      chain from one pivot to the next is one 1/sqrt and one FMA;
+//   2. C = M S[j0..j0+3, :] (one MFMA; the B operand is register B as it
+//      stands) holds L^T's rows j0..j0+3: the panel L_P^T right of the block
+//      and, by symmetry, L_D^T inside it;
+//   3. S -= L_P L_P^T on the trailing block and X[j0.., :] = M X[j0.., :],
+//      X[below, :] -= L_P X[j0.., :] (three MFMAs; A and B of the rank-4
+//      update are the same register, zero outside the trailing part).
+// R = L^T's rows j0..j0+3 of the tile are written to Rt (row stride dp).
+template <int B>
+__device__ inline void diag_step4(doublex4& a, doublex4& x, int lane, int lr, int lc, double gdl, double tol,
+                                  int& depmask, double* __restrict__ Rt, int dp, double* Mb) {
+  constexpr int j0 = 4 * B;
+  double W[4][4];
 #pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) W[i][j] = bcast(a[B], 16 * i + j0 + j);  // S[j0 + i][j0 + j]
+  double Ld[4][4], inv[4];
+  int dm = 0;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const double piv = W[p][p];
+    const bool dep = !(piv > tol * bcast(gdl, j0 + p));
+    inv[p] = dep ? 1.0 : rsqrt_f64(piv);
+    Ld[p][p] = dep ? 1.0 : piv * inv[p];
+#pragma unroll
+    for (int i = p + 1; i < 4; ++i) Ld[i][p] = dep ? 0.0 : W[i][p] * inv[p];
+#pragma unroll
+    for (int i = p + 1; i < 4; ++i)
+#pragma unroll
+      for (int j = p + 1; j <= i; ++j) W[i][j] = fma(-Ld[i][p], Ld[j][p], W[i][j]);
+    dm |= dep ? (1 << p) : 0;
   }
-  return y;
-}
-
-// Factor the 16 x 16 diagonal tile S = L L^T in column-per-lane form and
-// form X = L^-1 in the same sweep.  Lane c < 16 holds column c of S in v[]
-// (both triangles, S symmetric); lane 16 + c holds column c of X (starting
-// as the identity).  Per pivot J every value another lane needs is column J
-// of S, read from lane J as wave-uniform scalars, and both halves apply the
-// same update v[r] -= S[r][J] * coef for r > J, with coef = S[J][c] / S[J][J]
-// (lanes c > J of S) or X[J][c] / S[J][J] (X), before row J is scaled by
-// 1 / sqrt(S[J][J]).  The chain from one pivot to the next is a reciprocal
-// and one FMA; 1/sqrt runs beside it.  On return lane c holds row c of L
-// (column c of R = L^T, zero below the diagonal) and lane 16 + c column c of
-// X; depmask has bit J set for each dependent pivot.  Lanes 32..63 repeat
-// lanes 0..31.
-__device__ inline void factor_diag_tile(double (&v)[kTile], int lane, double gdl, double tol,
-                                        int& depmask) {
-  // gdl: lane c holds the original squared norm of column c (the pivot test)
-  int c = lane & 15;
-  // opaque to the optimizer: keeps the per-step lane masks from being
-  // hoisted out of the block loop, where they would pin scalar registers
-  asm volatile("" : "+v"(c));
-  const bool xs = (lane & 16) != 0;  // this lane holds a column of X
+  // M = L_D^-1 (lower), M[i][i] = 1 / L_D[i][i]
+  double M[4][4];
 #pragma unroll
-  for (int J = 0; J < kTile; ++J) {
-    const double piv = bcast(v[J], J);  // S[J][J]
-    const bool dep = !(piv > tol * bcast(gdl, J));
-    // both chains are computed unconditionally (no branch) and selected
-    const double rp = dep ? 0.0 : rcp_f64(piv);
-    const double inv = dep ? 1.0 : rsqrt_f64(piv);
-    const bool upd = xs || c > J;
-    const double vj = v[J];  // S[J][c] or X[J][c]
-    const double coef = upd ? vj * rp : 0.0;
+  for (int i = 0; i < 4; ++i) {
+    M[i][i] = inv[i];
 #pragma unroll
-    for (int r = J + 1; r < kTile; ++r) v[r] = fma(-bcast(v[r], J), coef, v[r]);
-    double nv = upd ? vj * inv : vj;       // X[J][c], or L[c][J] for c > J
-    if (!xs && c > J && dep) nv = 0.0;
-    if (!xs && c == J) nv = dep ? 1.0 : piv * inv;  // L[J][J]
-    v[J] = nv;
-    depmask |= dep ? (1 << J) : 0;
-    __builtin_amdgcn_sched_barrier(0);  // keep the steps apart: bounds the live scalars
+    for (int j = 0; j < i; ++j) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = j; q < i; ++q) t = fma(Ld[i][q], M[q][j], t);
+      M[i][j] = -t * inv[i];
+    }
   }
-  // lane c of S: entries below the diagonal of R = L^T are zero
-  if (!xs) {
+  // A operand: lane (k, m) supplies M[m][k] (rows m >= 4 are zero), handed
+  // out through LDS from lane 0's copy of the uniform values
+  if (lane == 0) {
 #pragma unroll
-    for (int r = 0; r < kTile; ++r)
-      if (r > c) v[r] = 0.0;
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Mb[4 * m + k] = (k <= m) ? M[m][k] : 0.0;
   }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const double am = (lc < 4) ? Mb[4 * lc + lr] : 0.0;
+  __builtin_amdgcn_wave_barrier();
+  const doublex4 z = Mfma<double>::zero();
+  const doublex4 c = Mfma<double>::mma(am, a[B], z);   // c[0] = (M S[j0.., :])[lr][lc]
+  const doublex4 xn = Mfma<double>::mma(am, x[B], z);  // xn[0] = new X[j0 + lr][lc]
+  const bool depg = (dm >> lr) & 1;
+  // L_P^T[lr][lc] = L[lc][j0 + lr] right of the block (zero for a dependent pivot)
+  const double lp = (lc > j0 + 3 && !depg) ? c[0] : 0.0;
+  double rv = lp;  // R[j0 + lr][lc]
+  if (lc < j0 + lr) rv = 0.0;
+  else if (lc <= j0 + 3) rv = depg ? (lc == j0 + lr ? 1.0 : 0.0) : c[0];
+  Rt[(int64_t)(j0 + lr) * dp + lc] = rv;
+  x[B] = xn[0];
+  a = Mfma<double>::mma(-lp, lp, a);     // S[m][n] -= sum_k L_P[m][k] L_P[n][k]
+  x = Mfma<double>::mma(-lp, x[B], x);   // X[m][:] -= sum_k L_P[m][k] X[j0 + k][:]
+  depmask |= dm << j0;
 }
 
 template <int NW, int SLOTS>
@@ -130,6 +152,7 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
   __shared__ double Gdiag[kDMax];
   __shared__ int defl[kDMax];
   __shared__ double red[NW];
+  __shared__ double Mb[16];  // 4 x 4 inverse of the current diagonal block step
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -199,38 +222,34 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
   int ndep_total = 0;
   __syncthreads();
 
-  // A: the owner of tile (k,k) factors it (column per lane) and publishes
-  // Di = L_kk^-1, the R block L_kk^T, its inverse and the dependent-column
-  // flags.
+  // A: the owner of tile (k,k) factors it in four 4-pivot steps and
+  // publishes Di = L_kk^-1, the R block L_kk^T, its inverse and the
+  // dependent-column flags.
   auto factor_diag = [&](int k, int sk) {
+    doublex4 t = Mfma<double>::zero();
 #pragma unroll
     for (int sl = 0; sl < SLOTS; ++sl)
-      if (sl == sk) {
+      if (sl == sk) t = tile[sl];
+    doublex4 x;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Di[lr + 4 * r][lc] = tile[sl][r];
-      }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const bool xs = (lane & 16) != 0;
-    double v[kTile];
-#pragma unroll
-    for (int r = 0; r < kTile; ++r) v[r] = xs ? (r == lc ? 1.0 : 0.0) : Di[r][lc];
+    for (int r = 0; r < 4; ++r) x[r] = (lr + 4 * r == lc) ? 1.0 : 0.0;
     const double gdl = Gdiag[k * kTile + lc];
-    __builtin_amdgcn_wave_barrier();
     int depmask = 0;
-    factor_diag_tile(v, lane, gdl, tol, depmask);
+    double* Rt = R + (int64_t)k * kTile * dp + k * kTile;
+    diag_step4<0>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
+    diag_step4<1>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
+    diag_step4<2>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
+    diag_step4<3>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = lr + 4 * r;
+      Di[row][lc] = x[r];                                              // X[row][c]
+      Rinv16[(int64_t)k * kTile * kTile + lc * kTile + row] = x[r];    // (L^-1)^T
+    }
     if (lane < kTile) {
-#pragma unroll
-      for (int r = 0; r < kTile; ++r) R[(int64_t)(k * kTile + r) * dp + k * kTile + lc] = v[r];  // R[r][c]
-      const int dep_c = (depmask >> lc) & 1;
-      defl[k * kTile + lc] = dep_c;
-      flags[k * kTile + lc] = dep_c;
-    } else if (lane < 2 * kTile) {
-#pragma unroll
-      for (int r = 0; r < kTile; ++r) {
-        Di[r][lc] = v[r];                                            // X[r][c]
-        Rinv16[(int64_t)k * kTile * kTile + lc * kTile + r] = v[r];  // (L^-1)^T
-      }
+      const int dep_c = (depmask >> lane) & 1;
+      defl[k * kTile + lane] = dep_c;
+      flags[k * kTile + lane] = dep_c;
     }
     ndep_total += __popc(depmask);
   };
