@@ -7,16 +7,22 @@
 // I' <= I adds R_{I',I+1} X_{I+1,J} to its accumulator (float64 MFMA), and the
 // owner of row I finishes it with R_II^-1.  Rows are dealt to the 8 waves
 // round-robin; X_{I+1,J} is passed through LDS (double buffered, one
-// workgroup barrier per block row).  The diagonal-block inverses come from
+// workgroup barrier per block row).  The step loop is unrolled so that the
+// R tiles of each step can be loaded into a register ring several steps
+// before they are used.  The diagonal-block inverses come from
 // the Cholesky.  Nothing is done when the Cholesky marked a dependent column
 // (the solve then substitutes instead).
 #include "common.h"
 #include "kernels.h"
 
+#include <utility>
+
 namespace rqlp {
 
 constexpr int kInvWaves = 8;
 constexpr int kInvRows = kDMax / kTile / kInvWaves;  // block rows per wave
+constexpr int kInvT = kDMax / kTile;                 // largest number of block rows
+constexpr int kInvAhead = 4;                         // R tiles are loaded this many steps early
 
 __global__ __launch_bounds__(kInvWaves * 64) void trinv_kernel(const double* __restrict__ R,
                                                                const double* __restrict__ Rinv16, int dp,
@@ -28,6 +34,35 @@ __global__ __launch_bounds__(kInvWaves * 64) void trinv_kernel(const double* __r
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane >> 4, lc = lane & 15;
+
+  // A operands of R_{I', t} for this wave's rows I' = wave + 8 s, step I = t - 1:
+  // ring[I % kInvAhead][s][ks] (float64 MFMA A layout: A[m][kk] = R_I't[m][kk])
+  double ring[kInvAhead][kInvRows][4];
+  auto load_step = [&](auto Ic) {
+    constexpr int I = decltype(Ic)::value;
+    constexpr int t = I + 1;
+#pragma unroll
+    for (int s = 0; s < kInvRows; ++s) {
+      const int Ip = wave + kInvWaves * s;
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+        ring[I % kInvAhead][s][ks] =
+            (Ip <= I) ? R[(int64_t)(Ip * kTile + lc) * dp + t * kTile + ks * 4 + lr] : 0.0;
+    }
+  };
+  // -R_I'I'^-1 as A operands for the rows this wave finishes
+  double rinv[kInvRows][4];
+#pragma unroll
+  for (int s = 0; s < kInvRows; ++s) {
+    const int Ip = wave + kInvWaves * s;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+      rinv[s][ks] = (Ip < J) ? -Rinv16[(int64_t)Ip * kTile * kTile + lc * kTile + ks * 4 + lr] : 0.0;
+  }
+  // the first kInvAhead steps (I = J-1 down to J-kInvAhead)
+  [&]<int... Is>(std::integer_sequence<int, Is...>) {
+    ((Is < J && Is >= J - kInvAhead ? load_step(std::integral_constant<int, Is>{}) : void()), ...);
+  }(std::make_integer_sequence<int, kInvT>{});
 
   // X_JJ = R_JJ^-1 (row-major 16 x 16 block of Rinv16)
   for (int e = tid; e < kTile * kTile; e += blockDim.x) {
@@ -41,33 +76,30 @@ __global__ __launch_bounds__(kInvWaves * 64) void trinv_kernel(const double* __r
   for (int s = 0; s < kInvRows; ++s) S[s] = Mfma<double>::zero();
   __syncthreads();
 
-  int buf = 0;
-  for (int I = J - 1; I >= 0; --I) {
-    const int t = I + 1;  // X_tJ is in Zs[buf]
-    // S_I' += R_I't X_tJ for the pending rows I' <= I of this wave
+  // steps I = J-1 down to 0, unrolled so that the ring slots are fixed
+  auto step = [&](auto Ic) {
+    constexpr int I = decltype(Ic)::value;
+    if (I >= J) return;
+    const int buf = (J - 1 - I) & 1;  // X_{I+1,J} is in Zs[buf]
+    // S_I' += R_{I',I+1} X_{I+1,J} for the pending rows I' <= I of this wave
 #pragma unroll
     for (int s = 0; s < kInvRows; ++s) {
       const int Ip = wave + kInvWaves * s;
       if (Ip <= I) {
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int kk = ks * 4 + lr;
-          const double a = R[(int64_t)(Ip * kTile + lc) * dp + t * kTile + kk];  // A[m][kk] = R_I't[m][kk]
-          S[s] = Mfma<double>::mma(a, Zs[buf][kk][lc], S[s]);                  // B[kk][n] = X_tJ[kk][n]
-        }
+        for (int ks = 0; ks < 4; ++ks)
+          S[s] = Mfma<double>::mma(ring[I % kInvAhead][s][ks], Zs[buf][ks * 4 + lr][lc], S[s]);
       }
     }
+    // this step's ring slot is free again: fetch the tiles of step I - kInvAhead
+    if constexpr (I >= kInvAhead) load_step(std::integral_constant<int, I - kInvAhead>{});
     // the owner of row I finishes X_IJ = -R_II^-1 S_I
     if (wave == I % kInvWaves) {
-      const int so = I / kInvWaves;
+      constexpr int so = I / kInvWaves;
       doublex4 z = Mfma<double>::zero();
 #pragma unroll
-      for (int s = 0; s < kInvRows; ++s)
-        if (s == so) {
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks)  // the accumulator layout is the B operand layout
-            z = Mfma<double>::mma(-Rinv16[(int64_t)I * kTile * kTile + lc * kTile + ks * 4 + lr], S[s][ks], z);
-        }
+      for (int ks = 0; ks < 4; ++ks)  // the accumulator layout is the B operand layout
+        z = Mfma<double>::mma(rinv[so][ks], S[so][ks], z);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = lr + 4 * r;
@@ -76,8 +108,10 @@ __global__ __launch_bounds__(kInvWaves * 64) void trinv_kernel(const double* __r
       }
     }
     __syncthreads();
-    buf ^= 1;
-  }
+  };
+  [&]<int... Is>(std::integer_sequence<int, Is...>) {
+    (step(std::integral_constant<int, kInvT - 1 - Is>{}), ...);
+  }(std::make_integer_sequence<int, kInvT>{});
 }
 
 hipError_t launch_trinv(const double* R, const double* Rinv16, int dp, const int32_t* mode, double* X,
