@@ -54,9 +54,17 @@ def f_alg_csr(nnz, m, n, k, p, q):
     return 2.0 * nnz * d * (2 * q + 2) + qr(m) * (q + 1) + qr(n) * (q + 1)
 
 
-def kernel_source_hash():
+# source files that define each timed kernel class (for the traffic record)
+KERNEL_SOURCES = {
+    "gemm_nn": ["k_gemm.hip", "common.h", "kernels.h"],
+    "gemm_tn": ["k_gemm.hip", "common.h", "kernels.h"],
+    "spmm": ["k_csr.hip", "common.h", "kernels.h"],
+}
+
+
+def kernel_source_hash(kernel):
     h = hashlib.sha256()
-    for name in sorted(os.listdir(os.path.join(ROOT, "paper_2209_12464_amd", "csrc"))):
+    for name in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2209_12464_amd", "csrc", name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -64,8 +72,9 @@ def kernel_source_hash():
 
 
 def load_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` measured by rocprofv3 PMC runs and
-    committed under profiles/, if taken on the current kernel sources."""
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE and
+    WRITE_SIZE runs recorded in profiles/traffic.json, if they were taken on
+    the kernel's current sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -73,7 +82,7 @@ def load_traffic(workload, kernel):
     except (OSError, ValueError):
         return None
     ent = rec.get(workload, {}).get(kernel)
-    if not ent or ent.get("source_hash") != kernel_source_hash():
+    if not ent or ent.get("source_hash") != kernel_source_hash(kernel):
         return None
     return ent.get("bytes_per_launch")
 
@@ -127,6 +136,61 @@ def copy_calibration(nbytes=1 << 30, reps=5):
     print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def kernel_class(name):
+    """Timed kernel class of a profiled kernel name (None if untimed)."""
+    if name.startswith("void rqlp::gemm_kernel<"):
+        trans = name.split("<", 1)[1].split(",")[2].strip()
+        return "gemm_tn" if trans == "true" else "gemm_nn"
+    if "rqlp::spmm_kernel" in name:
+        return "spmm"
+    return None
+
+
+def read_counter(csv_path, counter):
+    """{kernel name: [per-dispatch values]} of one counter from a rocprofv3
+    counter_collection.csv."""
+    import csv
+    out = {}
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def record_traffic(workload, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, cal_bytes):
+    """Scale the FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the timed
+    kernels by what the same counters read for a plain copy of cal_bytes per
+    dispatch, and store bytes per launch in profiles/traffic.json."""
+    def scale(csv_path, counter):
+        vals = [v for name, vs in read_counter(csv_path, counter).items() if "copyBuffer" in name for v in vs]
+        return cal_bytes / (1024.0 * float(np.median(vals)))
+    f_fetch = scale(cal_fetch_csv, "FETCH_SIZE")
+    f_write = scale(cal_write_csv, "WRITE_SIZE")
+    fetch = read_counter(fetch_csv, "FETCH_SIZE")
+    write = read_counter(write_csv, "WRITE_SIZE")
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        rec = {}
+    out = {}
+    for name in fetch:
+        cls = kernel_class(name)
+        if cls is None or name not in write:
+            continue
+        fb = float(np.mean(fetch[name])) * 1024.0 * f_fetch
+        wb = float(np.mean(write[name])) * 1024.0 * f_write
+        out[cls] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
+                    "fetch_scale": f_fetch, "write_scale": f_write, "dispatches": len(fetch[name]),
+                    "source_hash": kernel_source_hash(cls)}
+    rec[workload] = out
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    print(json.dumps({workload: out}, indent=1), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,8 +199,15 @@ def main():
     ap.add_argument("--workload", default="dense8000", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (x5), to scale FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV"),
+                    help="write profiles/traffic.json for --workload from rocprofv3 counter CSVs (no GPU use)")
     args = ap.parse_args()
+
+    if args.record_traffic:
+        record_traffic(args.workload, *args.record_traffic, cal_bytes=float(1 << 30))
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}), flush=True)
