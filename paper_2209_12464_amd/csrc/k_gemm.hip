@@ -227,18 +227,36 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(
     for (int k0 = kbeg; k0 < kend; k0 += kBK) {
       const bool more = k0 + kBK < kend;
       if (more) load_tile(k0 + kBK);
+      __builtin_amdgcn_s_setprio(1);
+      // The operands of step ks + 1 are read from LDS while the MFMAs of
+      // step ks issue, and the wave's priority is raised for the MFMA loop
+      // so that the co-resident workgroup's loads and stores fill its gaps.
+      T a0[2], a1[2], bb[2][NBW];
+      {
+        const int kr = (lane >> 4);
+        a0[0] = As[buf][kr][arow];
+        a1[0] = As[buf][kr][arow + 16];
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) bb[0][nb] = Bs[buf][kr][bcol + nb * 16];
+      }
 #pragma unroll
       for (int ks = 0; ks < kBK / 4; ++ks) {
-        const int kr = ks * 4 + (lane >> 4);
-        const T a0 = As[buf][kr][arow];
-        const T a1 = As[buf][kr][arow + 16];
+        const int cur = ks & 1, nxt = cur ^ 1;
+        if (ks + 1 < kBK / 4) {
+          const int kr = (ks + 1) * 4 + (lane >> 4);
+          a0[nxt] = As[buf][kr][arow];
+          a1[nxt] = As[buf][kr][arow + 16];
+#pragma unroll
+          for (int nb = 0; nb < NBW; ++nb) bb[nxt][nb] = Bs[buf][kr][bcol + nb * 16];
+        }
 #pragma unroll
         for (int nb = 0; nb < NBW; ++nb) {
-          const T b = Bs[buf][kr][bcol + nb * 16];
-          acc[0][nb] = MF::mma(a0, b, acc[0][nb]);
-          acc[1][nb] = MF::mma(a1, b, acc[1][nb]);
+          acc[0][nb] = MF::mma(a0[cur], bb[cur][nb], acc[0][nb]);
+          acc[1][nb] = MF::mma(a1[cur], bb[cur][nb], acc[1][nb]);
         }
+        __builtin_amdgcn_sched_barrier(0);
       }
+      __builtin_amdgcn_s_setprio(0);
       if (more) store_tile(buf ^ 1);
       __syncthreads();
       buf ^= 1;
