@@ -56,11 +56,17 @@ typedef enum {
 
 /* Working precision.  A, Q, L, V (and X, Y of the step entry points) are
  * double for RQLP_FP64 and float otherwise.  Gram matrices, Cholesky
- * factors and the first CholeskyQR pass are always float64. */
+ * factors and the first CholeskyQR pass are always float64.
+ * RQLP_BF16_REFINED (dense rqlp_decompose only; UNSUPPORTED elsewhere): A
+ * is float; every product with A rounds A and its right-hand factor to
+ * bfloat16 (round to nearest even) and accumulates in float32 on the matrix
+ * cores; the orthonormalizations are the same float64-Gram CholeskyQR2 as
+ * for RQLP_FP32, whose second pass restores orthogonality.  Results are
+ * float.  Its workspace also holds bfloat16 copies of A and A^T. */
 typedef enum {
   RQLP_FP64 = 0,
   RQLP_FP32 = 1,
-  RQLP_BF16_REFINED = 2 /* reserved: bfloat16 products; returns UNSUPPORTED */
+  RQLP_BF16_REFINED = 2
 } rqlp_precision;
 
 typedef struct rqlp_ctx rqlp_ctx;
@@ -140,7 +146,9 @@ rqlp_status rqlp_gaussian(rqlp_ctx* ctx, uint64_t seed, uint32_t stream_id, int6
  * A^T Q; Algorithm 2: the power steps).
  *  trans = 0: Y (m x d) = A X,   X is n x d;   trans = 1: Y (n x d) = A^T X,
  *  X is m x d.  A is m x n row-major (lda).  X, Y leading dims ldx, ldy
- *  >= d.  Working precision only (float or double); d <= 256. */
+ *  >= d; d <= 256.  A, X, Y are double for RQLP_FP64, float otherwise; with
+ *  RQLP_BF16_REFINED, A and X are rounded to bfloat16 (into the workspace)
+ *  and the products accumulated in float32. */
 size_t rqlp_gemm_workspace_size(int trans, int64_t m, int64_t n, int d, rqlp_precision prec);
 rqlp_status rqlp_gemm(rqlp_ctx* ctx, int trans, const void* A, int64_t m, int64_t n, int64_t lda,
                       const void* X, int64_t ldx, int d, void* Y, int64_t ldy,

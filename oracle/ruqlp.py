@@ -67,17 +67,24 @@ def _ruqlp_core(mul_A, mul_At, n, k, p, q, seed, omega_dtype):
     return Q, L, V
 
 
-def ruqlp(A, k, p, q, seed, omega_dtype="f64"):
+def ruqlp(A, k, p, q, seed, omega_dtype="f64", operand_dtype="f64"):
     """RU-QLP of dense A (m x n, any float dtype; used in float64).
 
     Returns (Q, L, V): Q m x d, L d x d lower triangular, V n x d, d = k + p.
+
+    operand_dtype="bf16" models products taken in bfloat16: every product
+    with A uses A and its right-hand factor rounded to bfloat16 (round_to)
+    and is then formed exactly in float64.  The orthonormalizations are
+    unchanged, so Q L V^T = Q round(Q)^T round(A) holds exactly.
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     d = k + p
     if not (1 <= k and d <= min(m, n)):
         raise ValueError("need 1 <= k and k + p <= min(m, n)")
-    return _ruqlp_core(lambda X: A @ X, lambda X: A.T @ X, n, k, p, q, seed, omega_dtype)
+    Ar = round_to(A, operand_dtype)
+    return _ruqlp_core(lambda X: Ar @ round_to(X, operand_dtype), lambda X: Ar.T @ round_to(X, operand_dtype),
+                       n, k, p, q, seed, omega_dtype)
 
 
 def ruqlp_csr(rowptr, colidx, vals, m, n, k, p, q, seed, omega_dtype="f64"):

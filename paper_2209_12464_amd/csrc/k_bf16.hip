@@ -1,0 +1,255 @@
+// BFloat16 products with float32 accumulation (the reduced-precision form of
+// the sketch, power-step and projection products of Algorithms 1 and 2):
+// A is rounded to bfloat16 once per decomposition, each right-hand factor
+// (Omega, Q, W) once per product, and the matrix cores accumulate the exact
+// bfloat16 products in float32.  Everything after the product (Gram matrix,
+// Cholesky factor, inverse, solve) stays as in the float32 form.
+//
+// The 16x16x32 bf16 MFMA takes 8 consecutive reduction indices per lane, so
+// both operands are kept k-contiguous: A as stored (row-major m x n) for
+// A X, a transposed copy of A for A^T X (both made by one conversion pass),
+// and the right-hand factor transposed (d x K) by a small conversion kernel.
+// The product kernel is then a single "NT" form, Y = A_op X^T_op, tiled like
+// the float32 kernel: 8 waves as 4 x 2, 128-row slabs with all columns per
+// workgroup (A read once), split-K with the ordered float32 reduction.
+#include <algorithm>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace rqlp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest with ties to even (NaN stays NaN)
+__device__ inline uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// conversions: 64 x 64 tiles through LDS
+
+constexpr int kCvT = 64;
+
+// A (m x n float, lda) -> Ab (m x ldb, bf16) and, if At != null, At (n x
+// ldt, bf16) = A^T.  Columns [n, ldb) of Ab and [m, ldt) of At are zero.
+__global__ __launch_bounds__(256) void cvt_bf16_kernel(const float* __restrict__ A, int64_t lda, int64_t m,
+                                                       int64_t n, uint16_t* __restrict__ Ab, int64_t ldb,
+                                                       uint16_t* __restrict__ At, int64_t ldt) {
+  __shared__ uint16_t tile[kCvT][kCvT + 2];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.y * kCvT, c0 = (int64_t)blockIdx.x * kCvT;
+  const int cl = (tid & 15) * 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rl = (tid >> 4) + 16 * i;
+    const int64_t r = r0 + rl;
+    u16x4 v;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t c = c0 + cl + j;
+      v[j] = (r < m && c < n) ? f2bf(A[r * lda + c]) : (uint16_t)0;
+      tile[rl][cl + j] = v[j];
+    }
+    if (r < m && c0 + cl < ldb) {
+      if (c0 + cl + 4 <= ldb) {
+        *reinterpret_cast<u16x4*>(Ab + r * ldb + c0 + cl) = v;
+      } else {
+        for (int j = 0; j < 4 && c0 + cl + j < ldb; ++j) Ab[r * ldb + c0 + cl + j] = v[j];
+      }
+    }
+  }
+  if (!At) return;
+  __syncthreads();
+  // At[c][r] for the tile: thread writes 4 consecutive r of one c
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int ccl = (tid >> 4) + 16 * i;
+    const int rl = (tid & 15) * 4;
+    const int64_t c = c0 + ccl;
+    if (c >= n) continue;
+    u16x4 v;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = tile[rl + j][ccl];
+    const int64_t r = r0 + rl;
+    if (r < ldt) {
+      if (r + 4 <= ldt) {
+        *reinterpret_cast<u16x4*>(At + c * ldt + r) = v;
+      } else {
+        for (int j = 0; j < 4 && r + j < ldt; ++j) At[c * ldt + r + j] = v[j];
+      }
+    }
+  }
+}
+
+hipError_t launch_cvt_bf16(const float* A, int64_t lda, int64_t m, int64_t n, uint16_t* Ab, int64_t ldb,
+                           uint16_t* At, int64_t ldt, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  // the grid covers the padded extents so that the zero padding is written
+  const int64_t cols = std::max<int64_t>(ldb, n), rows = At ? std::max<int64_t>(ldt, m) : m;
+  dim3 grid((unsigned)ceil_div(cols, kCvT), (unsigned)ceil_div(rows, kCvT));
+  hipLaunchKernelGGL(cvt_bf16_kernel, grid, dim3(256), 0, s, A, lda, m, n, Ab, ldb, At, ldt);
+  return hipGetLastError();
+}
+
+// X (K x N float, ldx) -> Xt (N x ldt bf16) = X^T, columns [K, ldt) zero.
+hipError_t launch_cvt_bf16_t(const float* X, int64_t ldx, int64_t K, int64_t N, uint16_t* Xt, int64_t ldt,
+                             hipStream_t s) {
+  if (K <= 0 || N <= 0) return hipSuccess;
+  // only the transposed copy is wanted: Ab is written to a null-sized target
+  dim3 grid((unsigned)ceil_div(N, kCvT), (unsigned)ceil_div(std::max<int64_t>(ldt, K), kCvT));
+  hipLaunchKernelGGL(cvt_bf16_kernel, grid, dim3(256), 0, s, X, ldx, K, N, (uint16_t*)nullptr, (int64_t)0, Xt,
+                     ldt);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// the product: C (M x nst slab of split `split`) = A[M x K] Xt[N x K]^T
+
+constexpr int kBfThreads = 512;
+constexpr int kBfBK = 32;                 // one bf16 MFMA step
+constexpr int kBfStride = kBfBK + 8;      // LDS row stride (bf16): 80 bytes, conflict-free 16-byte reads
+
+template <int NBW>
+__global__ __launch_bounds__(kBfThreads) void gemm_bf16_kernel(const uint16_t* __restrict__ A, int64_t lda,
+                                                               const uint16_t* __restrict__ Xt, int64_t ldx,
+                                                               float* __restrict__ C, int64_t ldc, int64_t cslice,
+                                                               int M, int N, int K, int kchunk, int mtiles,
+                                                               int nst) {
+  constexpr int BM = 128, BN = 32 * NBW;
+  constexpr int B_VECS = (BN * kBfBK / 8 + kBfThreads - 1) / kBfThreads;
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][BM][kBfStride];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN][kBfStride];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave & 3, wn = wave >> 2;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int split = logical / mtiles;
+  const int mt = logical - split * mtiles;
+  const int m0 = mt * BM;
+  const int kbeg = split * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+
+  u16x8 areg, breg[B_VECS];
+  auto load_tile = [&](int k0) {
+    {
+      const int r = tid >> 2, kv = tid & 3;
+      const int gr = m0 + r, gk = k0 + kv * 8;
+      areg = (u16x8)0;
+      if (gr < M && gk < kend) areg = *reinterpret_cast<const u16x8*>(A + (int64_t)gr * lda + gk);
+    }
+#pragma unroll
+    for (int v = 0; v < B_VECS; ++v) {
+      const int idx = tid + kBfThreads * v;
+      const int n = idx >> 2, kv = idx & 3;
+      const int gk = k0 + kv * 8;
+      breg[v] = (u16x8)0;
+      if (n < BN && n < N && gk < kend) breg[v] = *reinterpret_cast<const u16x8*>(Xt + (int64_t)n * ldx + gk);
+    }
+  };
+  auto store_tile = [&](int buf) {
+    *reinterpret_cast<u16x8*>(&As[buf][tid >> 2][(tid & 3) * 8]) = areg;
+#pragma unroll
+    for (int v = 0; v < B_VECS; ++v) {
+      const int idx = tid + kBfThreads * v;
+      if ((idx >> 2) < BN) *reinterpret_cast<u16x8*>(&Bs[buf][idx >> 2][(idx & 3) * 8]) = breg[v];
+    }
+  };
+
+  floatx4 acc[2][NBW];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = (floatx4)0.0f;
+  const int arow = wm * 32 + (lane & 15);
+  const int bcol = wn * (BN / 2) + (lane & 15);
+  const int kq = (lane >> 4) * 8;
+  if (kbeg < kend) {
+    load_tile(kbeg);
+    store_tile(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += kBfBK) {
+      const bool more = k0 + kBfBK < kend;
+      if (more) load_tile(k0 + kBfBK);
+      __builtin_amdgcn_s_setprio(1);
+      const bf16x8 a0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&As[buf][arow][kq]));
+      const bf16x8 a1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&As[buf][arow + 16][kq]));
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) {
+        const bf16x8 b = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&Bs[buf][bcol + nb * 16][kq]));
+        acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc[0][nb], 0, 0, 0);
+        acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc[1][nb], 0, 0, 0);
+      }
+      __builtin_amdgcn_s_setprio(0);
+      if (more) store_tile(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+  float* Cs = C + (int64_t)split * cslice;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NBW; ++nb) {
+      const int col = wn * (BN / 2) + nb * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 32 + mb * 16 + 4 * (lane >> 4) + r;
+        if (row < M && col < nst) Cs[(int64_t)row * ldc + col] = acc[mb][nb][r];
+      }
+    }
+}
+
+// Same split-K plan as the float32 product (a 128-row slab per workgroup,
+// about 512 workgroups in one round).
+void plan_gemm_bf16(int M, int K, int* mtiles, int* nsplit, int* kchunk) {
+  *mtiles = (int)ceil_div(M, 128);
+  int64_t ns = std::max(1, 512 / *mtiles);
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, ceil_div(K, 256)));
+  *kchunk = (int)round_up(ceil_div(std::max(K, 1), ns), kBfBK);
+  *nsplit = (int)ceil_div(std::max(K, 1), *kchunk);
+}
+
+size_t gemm_bf16_partial_elems(int M, int K, int dp) {
+  int mt, ns, kc;
+  plan_gemm_bf16(M, K, &mt, &ns, &kc);
+  return ns > 1 ? (size_t)ns * M * dp : 0;
+}
+
+hipError_t launch_gemm_bf16(const uint16_t* A, int64_t lda, const uint16_t* Xt, int64_t ldx, int M, int N, int K,
+                            float* Y, int64_t ldy, int nst, float* P, hipStream_t s, hipEvent_t ev0,
+                            hipEvent_t ev1) {
+  if (M <= 0 || nst <= 0) return hipSuccess;
+  int mtiles, nsplit, kchunk;
+  plan_gemm_bf16(M, K, &mtiles, &nsplit, &kchunk);
+  const int grid = mtiles * nsplit;
+  float* C = nsplit == 1 ? Y : P;
+  const int64_t ldc = nsplit == 1 ? ldy : nst;
+  const int64_t cslice = nsplit == 1 ? 0 : (int64_t)M * nst;
+  if (ev0) (void)hipEventRecord(ev0, s);
+#define RQLP_BF_LAUNCH(NB)                                                                                   \
+  hipLaunchKernelGGL(gemm_bf16_kernel<NB>, dim3(grid), dim3(kBfThreads), 0, s, A, lda, Xt, ldx, C, ldc, cslice, M, \
+                     N, K, kchunk, mtiles, nst)
+  switch ((int)round_up(N, 32) / 32) {
+    case 1: RQLP_BF_LAUNCH(1); break;
+    case 2: RQLP_BF_LAUNCH(2); break;
+    case 3: RQLP_BF_LAUNCH(3); break;
+    case 4: RQLP_BF_LAUNCH(4); break;
+    case 5: RQLP_BF_LAUNCH(5); break;
+    case 6: RQLP_BF_LAUNCH(6); break;
+    case 7: RQLP_BF_LAUNCH(7); break;
+    default: RQLP_BF_LAUNCH(8); break;
+  }
+#undef RQLP_BF_LAUNCH
+  if (ev1) (void)hipEventRecord(ev1, s);
+  if (nsplit > 1) return launch_splitk_reduce_f32(P, nsplit, M, nst, Y, ldy, s);
+  return hipGetLastError();
+}
+
+}  // namespace rqlp

@@ -357,6 +357,15 @@ hipError_t launch_gemm(GemmArgs<T> g, T* Y, int64_t ldy, int nst, T* P, hipStrea
   }
   return hipGetLastError();
 }
+hipError_t launch_splitk_reduce_f32(const float* P, int nsplit, int M, int nst, float* Y, int64_t ldy,
+                                    hipStream_t s) {
+  const int64_t total = (int64_t)M * nst;
+  const int64_t gr = ceil_div(total, 256);
+  hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3((unsigned)(gr < 8192 ? gr : 8192)), dim3(256), 0, s, P,
+                     (int64_t)nst, (int64_t)M * nst, nsplit, Y, ldy, M, nst);
+  return hipGetLastError();
+}
+
 template hipError_t launch_gemm<float>(GemmArgs<float>, float*, int64_t, int, float*, hipStream_t,
                                        hipEvent_t, hipEvent_t);
 template hipError_t launch_gemm<double>(GemmArgs<double>, double*, int64_t, int, double*,

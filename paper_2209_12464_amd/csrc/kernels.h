@@ -39,6 +39,26 @@ template <typename T>
 hipError_t launch_gemm(GemmArgs<T> g, T* Y, int64_t ldy, int nst, T* P, hipStream_t s,
                        hipEvent_t ev0, hipEvent_t ev1);
 
+// Y (M x nst, ldy) = sum over s of P[s] (M x nst slabs, ld nst), fixed order.
+hipError_t launch_splitk_reduce_f32(const float* P, int nsplit, int M, int nst, float* Y, int64_t ldy,
+                                    hipStream_t s);
+
+// ---- bfloat16 products, float32 accumulation (k_bf16.hip) ----
+// Ab (m x ldb) = bf16(A) and, if At is not null, At (n x ldt) = bf16(A)^T,
+// for A (m x n float, lda); padding columns are written as zero.
+hipError_t launch_cvt_bf16(const float* A, int64_t lda, int64_t m, int64_t n, uint16_t* Ab, int64_t ldb,
+                           uint16_t* At, int64_t ldt, hipStream_t s);
+// Xt (N x ldt) = bf16(X)^T for X (K x N float, ldx); columns [K, ldt) zero.
+hipError_t launch_cvt_bf16_t(const float* X, int64_t ldx, int64_t K, int64_t N, uint16_t* Xt, int64_t ldt,
+                             hipStream_t s);
+// Y (M x nst, ldy) = A Xt^T with A (M x K bf16, lda) and Xt (N x K bf16,
+// ldx), both k-contiguous, K a multiple of 8 with zero padding, lda and ldx
+// multiples of 8, N <= 256.  P: split-K partials (gemm_bf16_partial_elems).
+hipError_t launch_gemm_bf16(const uint16_t* A, int64_t lda, const uint16_t* Xt, int64_t ldx, int M, int N, int K,
+                            float* Y, int64_t ldy, int nst, float* P, hipStream_t s, hipEvent_t ev0,
+                            hipEvent_t ev1);
+size_t gemm_bf16_partial_elems(int M, int K, int dp);
+
 // ---- float64 Gram matrix (k_gram.hip) ----
 // G (dp x dp, ld dp, float64, full symmetric) = Y^T Y over rows [0, rows),
 // columns [0, d) of Y (ldy); entries outside d x d are zero.  Partials:

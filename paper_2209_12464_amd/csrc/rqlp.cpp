@@ -126,11 +126,16 @@ size_t gemm_partial_elems(int M, int K, int dp) {
 
 // Layout of the dense / CSR decomposition workspace.
 struct Layout {
-  size_t om, yb, qi, q1, part, gp, g, r1, r2, rinv, flags, xf, esq, csr_rt, csr_ct, csr_vt, csr_scr, total;
+  size_t om, yb, qi, q1, part, gp, g, r1, r2, rinv, flags, xf, esq, csr_rt, csr_ct, csr_vt, csr_scr;
+  size_t ab, at, xt;  // bfloat16 products: A, A^T and the transposed right-hand factor
+  size_t total;
 };
 
+// leading dimension of a k-contiguous bfloat16 operand of reduction length K
+int64_t bf16_ld(int64_t K) { return round_up(K, 8); }
+
 template <typename T>
-Layout layout(int64_t m, int64_t n, int d, bool sparse, int64_t nnz) {
+Layout layout(int64_t m, int64_t n, int d, bool sparse, int64_t nnz, bool bf16 = false) {
   const int dp = padded_d(d);
   const int64_t mx = std::max(m, n);
   Layout L;
@@ -142,6 +147,8 @@ Layout layout(int64_t m, int64_t n, int d, bool sparse, int64_t nnz) {
   L.q1 = put((size_t)mx * dp * sizeof(double));
   size_t pe = 0;
   if (!sparse) pe = std::max(gemm_partial_elems<T>((int)m, (int)n, dp), gemm_partial_elems<T>((int)n, (int)m, dp));
+  if (bf16) pe = std::max(gemm_bf16_partial_elems((int)m, (int)bf16_ld(n), dp),
+                          gemm_bf16_partial_elems((int)n, (int)bf16_ld(m), dp));
   L.part = put(pe * sizeof(T));
   const int gc = std::max(gram_chunks(m, dp), gram_chunks(n, dp));
   L.gp = put((size_t)gc * dp * dp * sizeof(double));
@@ -159,6 +166,13 @@ Layout layout(int64_t m, int64_t n, int d, bool sparse, int64_t nnz) {
     L.csr_scr = put(csr_transpose_scratch_bytes(m, n, nnz));
   } else {
     L.csr_rt = L.csr_ct = L.csr_vt = L.csr_scr = 0;
+  }
+  if (bf16) {
+    L.ab = put((size_t)m * bf16_ld(n) * 2);
+    L.at = put((size_t)n * bf16_ld(m) * 2);
+    L.xt = put((size_t)dp * bf16_ld(mx) * 2);
+  } else {
+    L.ab = L.at = L.xt = 0;
   }
   L.total = off + 256;
   return L;
@@ -257,7 +271,6 @@ rqlp_status check_common(int64_t m, int64_t n, int k, int p, int q, rqlp_precisi
   if (d > std::min(m, n)) return RQLP_ERR_INVALID_ARG;
   if (m > INT32_MAX || n > INT32_MAX) return RQLP_ERR_UNSUPPORTED;
   if (d > kDMax) return RQLP_ERR_UNSUPPORTED;
-  if (prec == RQLP_BF16_REFINED) return RQLP_ERR_UNSUPPORTED;
   return RQLP_OK;
 }
 
@@ -314,6 +327,38 @@ rqlp_status decompose_dense(rqlp_ctx* c, const T* A, int64_t m, int64_t n, int64
   auto mulA = [&](const T* X, T* Y) { return gemm<T>(c, 0, A, lda, m, n, X, dp, d, Y, dp, dp, part, s, true); };
   auto mulAt = [&](const T* X, T* Y) { return gemm<T>(c, 1, A, lda, m, n, X, dp, d, Y, dp, dp, part, s, true); };
   return run_method<T>(c, base, Lo, m, n, k, p, q, seed, Q, L, V, s, mulA, mulAt);
+}
+
+// RQLP_BF16_REFINED: A (float) is rounded to bfloat16 once, in both layouts;
+// every product rounds its right-hand factor to bfloat16 and accumulates in
+// float32; the rest of the method is the float32 form.
+rqlp_status decompose_dense_bf16(rqlp_ctx* c, const float* A, int64_t m, int64_t n, int64_t lda, int k, int p,
+                                 int q, uint64_t seed, float* Q, float* L, float* V, void* ws, size_t ws_bytes,
+                                 hipStream_t s) {
+  const int d = k + p, dp = padded_d(d);
+  const Layout Lo = layout<float>(m, n, d, false, 0, true);
+  char* base = nullptr;
+  rqlp_status st = get_workspace(c, ws, ws_bytes, Lo.total, &base);
+  if (st != RQLP_OK) return st;
+  float* part = (float*)(base + Lo.part);
+  uint16_t* ab = (uint16_t*)(base + Lo.ab);
+  uint16_t* at = (uint16_t*)(base + Lo.at);
+  uint16_t* xt = (uint16_t*)(base + Lo.xt);
+  const int64_t ldn = bf16_ld(n), ldm = bf16_ld(m);
+  HIP_TRY(launch_cvt_bf16(A, lda, m, n, ab, ldn, at, ldm, s));
+  auto mulA = [&](const float* X, float* Y) -> rqlp_status {  // Y (m x dp) = A X, X n x dp
+    HIP_TRY(launch_cvt_bf16_t(X, dp, n, dp, xt, ldn, s));
+    EvPair t = timer(c, RQLP_KT_GEMM_NN);
+    HIP_TRY(launch_gemm_bf16(ab, ldn, xt, ldn, (int)m, dp, (int)ldn, Y, dp, dp, part, s, t.a, t.b));
+    return RQLP_OK;
+  };
+  auto mulAt = [&](const float* X, float* Y) -> rqlp_status {  // Y (n x dp) = A^T X, X m x dp
+    HIP_TRY(launch_cvt_bf16_t(X, dp, m, dp, xt, ldm, s));
+    EvPair t = timer(c, RQLP_KT_GEMM_TN);
+    HIP_TRY(launch_gemm_bf16(at, ldm, xt, ldm, (int)n, dp, (int)ldm, Y, dp, dp, part, s, t.a, t.b));
+    return RQLP_OK;
+  };
+  return run_method<float>(c, base, Lo, m, n, k, p, q, seed, Q, L, V, s, mulA, mulAt);
 }
 
 template <typename T>
@@ -401,11 +446,12 @@ rqlp_status rqlp_destroy(rqlp_ctx* c) {
 size_t rqlp_workspace_size(int64_t m, int64_t n, int k, int p, int q, rqlp_precision prec) {
   if (check_common(m, n, k, p, q, prec) != RQLP_OK) return 0;
   return prec == RQLP_FP64 ? layout<double>(m, n, k + p, false, 0).total
-                           : layout<float>(m, n, k + p, false, 0).total;
+                           : layout<float>(m, n, k + p, false, 0, prec == RQLP_BF16_REFINED).total;
 }
 
 size_t rqlp_workspace_size_csr(int64_t m, int64_t n, int64_t nnz, int k, int p, int q, rqlp_precision prec) {
   if (check_common(m, n, k, p, q, prec) != RQLP_OK || nnz < 0 || nnz > INT32_MAX) return 0;
+  if (prec == RQLP_BF16_REFINED) return 0;
   return prec == RQLP_FP64 ? layout<double>(m, n, k + p, true, nnz).total
                            : layout<float>(m, n, k + p, true, nnz).total;
 }
@@ -422,6 +468,9 @@ rqlp_status rqlp_decompose(rqlp_ctx* c, const void* A, int64_t m, int64_t n, int
   if (prec == RQLP_FP64)
     return decompose_dense<double>(c, (const double*)A, m, n, lda, k, p, q, seed, (double*)Q, (double*)L,
                                    (double*)V, ws, ws_bytes, s);
+  if (prec == RQLP_BF16_REFINED)
+    return decompose_dense_bf16(c, (const float*)A, m, n, lda, k, p, q, seed, (float*)Q, (float*)L, (float*)V, ws,
+                                ws_bytes, s);
   return decompose_dense<float>(c, (const float*)A, m, n, lda, k, p, q, seed, (float*)Q, (float*)L, (float*)V,
                                 ws, ws_bytes, s);
 }
@@ -435,6 +484,7 @@ rqlp_status rqlp_decompose_csr(rqlp_ctx* c, const int32_t* rowptr, const int32_t
   if (nnz > 0 && (!colidx || !vals)) return RQLP_ERR_INVALID_ARG;
   rqlp_status st = check_common(m, n, k, p, q, prec);
   if (st != RQLP_OK) return st;
+  if (prec == RQLP_BF16_REFINED) return RQLP_ERR_UNSUPPORTED;
   if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
   hipStream_t s = (hipStream_t)stream;
   if (prec == RQLP_FP64)
@@ -483,9 +533,15 @@ rqlp_status rqlp_gaussian(rqlp_ctx* c, uint64_t seed, uint32_t stream_id, int64_
 }
 
 size_t rqlp_gemm_workspace_size(int trans, int64_t m, int64_t n, int d, rqlp_precision prec) {
-  if (m < 1 || n < 1 || d < 1 || d > kDMax || m > INT32_MAX || n > INT32_MAX) return 0;
+  if (m < 1 || n < 1 || d < 1 || d > kDMax || m > INT32_MAX || n > INT32_MAX || !valid_prec(prec)) return 0;
   const int dp = padded_d(d);
   const int M = (int)(trans ? n : m), K = (int)(trans ? m : n);
+  if (prec == RQLP_BF16_REFINED) {
+    // bf16 copy of op(A) (M x K, k-contiguous), of X^T (d x K), partial slabs
+    const int64_t kp = bf16_ld(K);
+    return align256((size_t)M * kp * 2) + align256((size_t)d * kp * 2) +
+           align256(gemm_bf16_partial_elems(M, (int)kp, d) * 4) + 512;
+  }
   const size_t e = prec == RQLP_FP64 ? gemm_partial_elems<double>(M, K, dp) * 8 : gemm_partial_elems<float>(M, K, dp) * 4;
   return e + 512;
 }
@@ -496,13 +552,26 @@ rqlp_status rqlp_gemm(rqlp_ctx* c, int trans, const void* A, int64_t m, int64_t 
   if (!c || !A || !X || !Y || m < 1 || n < 1 || d < 1 || lda < n || ldx < d || ldy < d || !valid_prec(prec) ||
       (trans != 0 && trans != 1))
     return RQLP_ERR_INVALID_ARG;
-  if (d > kDMax || m > INT32_MAX || n > INT32_MAX || prec == RQLP_BF16_REFINED) return RQLP_ERR_UNSUPPORTED;
+  if (d > kDMax || m > INT32_MAX || n > INT32_MAX) return RQLP_ERR_UNSUPPORTED;
   if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
   const size_t need = rqlp_gemm_workspace_size(trans, m, n, d, prec);
   char* base = nullptr;
   rqlp_status st = get_workspace(c, ws, ws_bytes, need, &base);
   if (st != RQLP_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  if (prec == RQLP_BF16_REFINED) {
+    const int M = (int)(trans ? n : m), K = (int)(trans ? m : n);
+    const int64_t kp = bf16_ld(K);
+    uint16_t* ab = (uint16_t*)base;
+    uint16_t* xt = (uint16_t*)(base + align256((size_t)M * kp * 2));
+    float* part = (float*)((char*)xt + align256((size_t)d * kp * 2));
+    if (trans) HIP_TRY(launch_cvt_bf16((const float*)A, lda, m, n, ab, 0, ab, kp, s));  // A^T only
+    else HIP_TRY(launch_cvt_bf16((const float*)A, lda, m, n, ab, kp, nullptr, 0, s));
+    HIP_TRY(launch_cvt_bf16_t((const float*)X, ldx, K, d, xt, kp, s));
+    EvPair t = timer(c, trans ? RQLP_KT_GEMM_TN : RQLP_KT_GEMM_NN);
+    HIP_TRY(launch_gemm_bf16(ab, kp, xt, kp, M, d, (int)kp, (float*)Y, ldy, d, part, s, t.a, t.b));
+    return RQLP_OK;
+  }
   // the partial buffer is laid out with row length d here (nst = d)
   if (prec == RQLP_FP64)
     return gemm<double>(c, trans, (const double*)A, lda, m, n, (const double*)X, ldx, d, (double*)Y, ldy, d,

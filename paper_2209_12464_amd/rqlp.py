@@ -93,7 +93,11 @@ def _check(status, where):
         raise RqlpError(status, where)
 
 
-def _prec(dtype):
+def _prec(dtype, bf16=False):
+    if bf16:
+        if dtype != torch.float32:
+            raise TypeError("bfloat16 products take a float32 A")
+        return RQLP_BF16_REFINED
     if dtype == torch.float64:
         return RQLP_FP64
     if dtype == torch.float32:
@@ -159,8 +163,8 @@ def default_context(device=0):
     return _DEFAULT[device]
 
 
-def workspace_size(m, n, k, p, q, dtype):
-    return int(_lib().rqlp_workspace_size(m, n, k, p, q, _prec(dtype)))
+def workspace_size(m, n, k, p, q, dtype, bf16=False):
+    return int(_lib().rqlp_workspace_size(m, n, k, p, q, _prec(dtype, bf16)))
 
 
 def workspace_size_csr(m, n, nnz, k, p, q, dtype):
@@ -171,16 +175,17 @@ def alloc_workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
-def decompose(A, k, p, q=0, seed=0, ctx=None, workspace=None, out=None):
+def decompose(A, k, p, q=0, seed=0, ctx=None, workspace=None, out=None, bf16=False):
     """RU-QLP of a dense device matrix A (m x n, float32 or float64, row
     stride >= n).  Returns (Q, L, V) on A's device; enqueued on the current
-    stream (not synchronized)."""
+    stream (not synchronized).  bf16=True (float32 A) takes the products
+    with A in bfloat16 with float32 accumulation (RQLP_BF16_REFINED)."""
     if A.dim() != 2 or A.stride(1) != 1:
         raise ValueError("A must be a 2-D row-major tensor")
     ctx = ctx or default_context(A.device.index or 0)
     m, n = A.shape
     d = k + p
-    prec = _prec(A.dtype)
+    prec = _prec(A.dtype, bf16)
     if out is None:
         Q = torch.empty((m, d), dtype=A.dtype, device=A.device)
         L = torch.empty((d, d), dtype=A.dtype, device=A.device)
@@ -188,7 +193,7 @@ def decompose(A, k, p, q=0, seed=0, ctx=None, workspace=None, out=None):
     else:
         Q, L, V = out
     if workspace is None:
-        ws_bytes = workspace_size(m, n, k, p, q, A.dtype)
+        ws_bytes = workspace_size(m, n, k, p, q, A.dtype, bf16)
         workspace = alloc_workspace(ws_bytes, A.device) if ws_bytes else None
     ws_ptr = _ptr(workspace)
     ws_bytes = workspace.numel() if workspace is not None else 0
@@ -231,16 +236,19 @@ def gaussian(rows, cols, seed, dtype=torch.float64, stream_id=0, ld=None, device
     return out
 
 
-def gemm(A, X, trans=False, ctx=None):
-    """Y = A X (trans=False) or A^T X (trans=True) on the matrix cores."""
+def gemm(A, X, trans=False, ctx=None, bf16=False):
+    """Y = A X (trans=False) or A^T X (trans=True) on the matrix cores;
+    bf16=True (float32 A, X) rounds both to bfloat16 and accumulates in
+    float32."""
     ctx = ctx or default_context(A.device.index or 0)
     m, n = A.shape
     d = X.shape[1]
     rows_out = n if trans else m
+    prec = _prec(A.dtype, bf16)
     Y = torch.empty((rows_out, d), dtype=A.dtype, device=A.device)
-    ws = alloc_workspace(_lib().rqlp_gemm_workspace_size(int(trans), m, n, d, _prec(A.dtype)), A.device)
+    ws = alloc_workspace(_lib().rqlp_gemm_workspace_size(int(trans), m, n, d, prec), A.device)
     _check(_lib().rqlp_gemm(ctx.handle, int(trans), _ptr(A), m, n, A.stride(0), _ptr(X), X.stride(0), d,
-                            _ptr(Y), Y.stride(0), _prec(A.dtype), _ptr(ws), ws.numel(), _stream(A.device)),
+                            _ptr(Y), Y.stride(0), prec, _ptr(ws), ws.numel(), _stream(A.device)),
            "rqlp_gemm")
     return Y
 

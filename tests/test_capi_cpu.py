@@ -49,7 +49,11 @@ def test_workspace_size_argument_checks(lib):
     assert lib.rqlp_workspace_size(1000, 1000, 250, 10, 0, 1) == 0      # d > 256
     assert lib.rqlp_workspace_size(100, 50, 5, 1, -1, 1) == 0           # q < 0
     assert lib.rqlp_workspace_size(100, 50, 5, 1, 0, 7) == 0            # bad precision
-    assert lib.rqlp_workspace_size(100, 50, 5, 1, 0, 2) == 0            # bf16 reserved
+    # bfloat16 products: dense only, and the workspace adds the bf16 copies of A and A^T
+    bf = lib.rqlp_workspace_size(1000, 800, 20, 5, 0, 2)
+    f32 = lib.rqlp_workspace_size(1000, 800, 20, 5, 0, 1)
+    assert bf >= f32 + 2 * 1000 * 800 * 2
+    assert lib.rqlp_workspace_size_csr(1000, 800, 5000, 20, 5, 0, 2) == 0
     small = lib.rqlp_workspace_size(1000, 800, 20, 5, 0, 0)
     big = lib.rqlp_workspace_size(2000, 800, 20, 5, 0, 0)
     assert 0 < small < big

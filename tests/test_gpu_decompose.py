@@ -136,6 +136,49 @@ def test_full_size_gapped_fp32(gpu_lib):
     _check_against_oracle(c["A"], Qg, Lg, Vg, 200, 10, 1, 2024, torch.float32, factors=False)
 
 
+# ---------------------------------------------------------------- bfloat16 products
+# Stated tolerances of the bfloat16 form (RQLP_BF16_REFINED):
+#  - against the oracle with the same bfloat16 rounding of the product
+#    operands (operand_dtype="bf16"): Delta <= 5e-4.  The GPU accumulates in
+#    float32 and rounds its float32 Q to bfloat16, so an operand within
+#    float32 noise (~1e-7) of a rounding boundary (spacing 2^-8) can round
+#    to the neighbour: about 2.5e-5 of the operands move by one bfloat16
+#    ulp, a ~2e-5 relative change of each product, which the power steps
+#    carry into the basis (measured: 5e-5 to 1.3e-4).
+#  - against the plain float64 oracle: Delta <= 2e-2, and the error
+#    ||A - Q L V^T||_F / ||A||_F within 5 % of the float64 method's when the
+#    rounding noise of A projected on d of n directions, ~2^-9 sqrt(d / n),
+#    is small beside that error (d / n <= 0.1 here, as at 20000 x 15000,
+#    k = 500, p = 20).
+TOL_BF16_EMUL = 5e-4
+TOL_BF16_F64 = 2e-2
+
+
+@pytest.mark.parametrize("m,n,k,p,q", [(2000, 1500, 100, 20, 1), (1200, 1500, 60, 10, 0), (1000, 3000, 150, 20, 1)])
+def test_bf16_products(gpu_lib, m, n, k, p, q):
+    announce("decompose bf16", m, n, k, p, q)
+    sigma = workloads.spectrum("polynomial", min(m, n), power=1.5)
+    A, _, _, _ = workloads.dense_from_spectrum(m, n, sigma, seed=m + 2 * n, dtype=np.float32, trunc=0.0)
+    seed = 11
+    Q, L, V = gpu_lib.decompose(to_dev(A), k, p, q, seed=seed, bf16=True)
+    Qg, Lg, Vg = to_np(Q), to_np(L), to_np(V)
+    A64 = A.astype(np.float64)
+    nA = np.linalg.norm(A64)
+    Qe, Le, Ve = oracle.ruqlp(A64, k, p, q, seed, omega_dtype="bf16", operand_dtype="bf16")
+    Qd, Ld, Vd = oracle.ruqlp(A64, k, p, q, seed, omega_dtype="f64")
+    d_emul = recon_diff(Qg, Lg, Vg, Qe, Le, Ve) / nA
+    d_f64 = recon_diff(Qg, Lg, Vg, Qd, Ld, Vd) / nA
+    e_gpu = recon_error(A64, Qg, Lg, Vg)
+    e_f64 = recon_error(A64, Qd, Ld, Vd)
+    print(f"bf16 {m}x{n} k={k} p={p} q={q}: Delta(emulated)={d_emul:.3e} Delta(f64)={d_f64:.3e} "
+          f"e={e_gpu:.4e} e_f64={e_f64:.4e}", flush=True)
+    assert d_emul <= TOL_BF16_EMUL
+    assert d_f64 <= TOL_BF16_F64
+    assert e_gpu <= 1.05 * e_f64
+    assert orth_error(Qg) <= 1e-4 and orth_error(Vg) <= 1e-4
+    assert np.all(np.triu(Lg, 1) == 0.0)
+
+
 # ---------------------------------------------------------------- CSR
 @pytest.mark.parametrize("m,n,density,k,p,q", [(3000, 2000, 0.01, 30, 10, 1), (2000, 3000, 0.005, 20, 5, 0)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])

@@ -85,6 +85,32 @@ def test_gemm_unaligned_leading_dimension(gpu_lib):
         assert np.allclose(Y, ref, rtol=1e-4, atol=1e-4)
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("m,n,d", [(1000, 777, 37), (300, 2000, 210), (8000, 8000, 210), (129, 67, 256),
+                                   (5, 3, 1)])
+def test_gemm_bf16_matches_rounded_product(gpu_lib, trans, m, n, d):
+    """bfloat16 products: the kernel multiplies round_bf16(A) and
+    round_bf16(X) exactly and accumulates in float32, so it must match the
+    float64 product of the rounded operands to float32 accumulation error."""
+    from oracle.bf16 import round_bf16
+    announce("gemm bf16", trans, m, n, d)
+    rng = np.random.default_rng(m + 3 * n + d)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    X = rng.standard_normal((m if trans else n, d)).astype(np.float32)
+    Y = to_np(gpu_lib.gemm(to_dev(A), to_dev(X), trans=trans, bf16=True))
+    Ab, Xb = round_bf16(A), round_bf16(X)
+    ref = (Ab.T @ Xb) if trans else (Ab @ Xb)
+    bound = (np.abs(Ab).T @ np.abs(Xb)) if trans else (np.abs(Ab) @ np.abs(Xb))
+    K = m if trans else n
+    # products of bfloat16 values are exact in float32; only the sums round
+    assert np.all(np.abs(Y - ref) <= 2 * K * 2.0 ** -24 * bound + 1e-30)
+    # and the rounding of the operands is really applied
+    ref32 = (A.astype(np.float64).T @ X) if trans else (A.astype(np.float64) @ X)
+    if K > 8:
+        assert np.abs(Y - ref32).max() > 1e-4 * np.abs(ref32).max()
+
+
 # ---------------------------------------------------------------- orth (CholeskyQR2)
 def _conditioned(m, d, cond, seed):
     rng = np.random.default_rng(seed)

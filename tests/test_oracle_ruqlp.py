@@ -102,3 +102,28 @@ def test_omega_rounding_modes():
     Q32, _, _ = oracle.ruqlp(A, 5, 2, 0, seed=2, omega_dtype="f32")
     # float32 rounding of Omega moves Q by ~1e-8, not more
     assert 0 < np.linalg.norm(Q64 - Q32) < 1e-5
+
+
+@pytest.mark.parametrize("q", [0, 1])
+def test_bf16_operand_model(q):
+    """operand_dtype='bf16': the products see A and the right-hand factor
+    rounded to bfloat16.  Pins: the exact identity Q L V^T = Q round(Q)^T
+    round(A) of the projection step; orthonormal Q, V and triangular L still
+    hold; and the result moves away from the float64 result by about the
+    bfloat16 unit roundoff, no more and no less."""
+    from oracle.bf16 import round_bf16
+    A, s, _, _ = _small("polynomial", m=300, n=200, seed=3, power=1.5)
+    k, p = 10, 5
+    Qb, Lb, Vb = oracle.ruqlp(A, k, p, q, seed=4, omega_dtype="bf16", operand_dtype="bf16")
+    Qd, Ld, Vd = oracle.ruqlp(A, k, p, q, seed=4, omega_dtype="bf16")
+    d = k + p
+    assert np.linalg.norm(Qb.T @ Qb - np.eye(d)) < 1e-13
+    assert np.linalg.norm(Vb.T @ Vb - np.eye(d)) < 1e-13
+    assert np.allclose(np.triu(Lb, 1), 0.0)
+    lhs = Qb @ Lb @ Vb.T
+    rhs = Qb @ (round_bf16(Qb).T @ round_bf16(A))
+    assert np.linalg.norm(lhs - rhs) < 1e-13 * np.linalg.norm(rhs)
+    # the unrounded projection would not satisfy it
+    assert np.linalg.norm(lhs - Qb @ (Qb.T @ A)) > 1e-6 * np.linalg.norm(rhs)
+    diff = np.linalg.norm(Qb @ Lb @ Vb.T - Qd @ Ld @ Vd.T) / np.linalg.norm(A)
+    assert 1e-6 < diff < 3e-2
