@@ -98,7 +98,8 @@ size_t rqlp_workspace_size_csr(int64_t m, int64_t n, int64_t nnz, int k, int p, 
 /* RU-QLP of a dense A (Algorithms 1 and 2; see the top of this file).
  *  A    : m x n, row-major, leading dimension lda >= n.
  *  k, p : target rank (k >= 1) and oversampling (p >= 0); d = k + p must
- *         satisfy d <= min(m, n) and d <= 256 in this build.
+ *         satisfy d <= min(m, n) and d <= 544 in this build (d <= 256 for
+ *         the CSR form).
  *  q    : number of power iterations (q >= 0), each two more passes over A.
  *  seed : key of the Gaussian test matrix (Philox4x64-10, see rqlp_gaussian).
  *  Q    : m x d output, leading dimension d.
@@ -146,7 +147,7 @@ rqlp_status rqlp_gaussian(rqlp_ctx* ctx, uint64_t seed, uint32_t stream_id, int6
  * A^T Q; Algorithm 2: the power steps).
  *  trans = 0: Y (m x d) = A X,   X is n x d;   trans = 1: Y (n x d) = A^T X,
  *  X is m x d.  A is m x n row-major (lda).  X, Y leading dims ldx, ldy
- *  >= d; d <= 256.  A, X, Y are double for RQLP_FP64, float otherwise; with
+ *  >= d; d <= 544.  A, X, Y are double for RQLP_FP64, float otherwise; with
  *  RQLP_BF16_REFINED, A and X are rounded to bfloat16 (into the workspace)
  *  and the products accumulated in float32. */
 size_t rqlp_gemm_workspace_size(int trans, int64_t m, int64_t n, int d, rqlp_precision prec);
@@ -159,8 +160,9 @@ rqlp_status rqlp_gemm(rqlp_ctx* ctx, int trans, const void* A, int64_t m, int64_
  *  Y: rows x d (ldy), not modified.  Q: rows x d output (ldq).  R: optional
  *  d x d output (row-major, leading dimension d, working precision), NULL to
  *  skip.  Columns found linearly dependent (relative residual below about
- *  sqrt(64 d eps64)) are replaced by random unit columns; their R row is
- *  zero.  Requires d <= rows and d <= 256. */
+ *  sqrt(64 d eps64)) are replaced by random unit columns; their diagonal
+ *  entry of R is zero (and their whole R row when no independent column
+ *  follows them).  Requires d <= rows and d <= 544. */
 size_t rqlp_orth_workspace_size(int64_t rows, int d, rqlp_precision prec);
 rqlp_status rqlp_orth(rqlp_ctx* ctx, const void* Y, int64_t rows, int d, int64_t ldy, void* Q,
                       int64_t ldq, void* R, rqlp_precision prec, uint64_t seed, void* workspace,

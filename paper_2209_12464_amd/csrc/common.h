@@ -13,7 +13,9 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;
 constexpr int kXcds = 8;       // MI355X: 8 accelerator complex dies, 32 CUs each
-constexpr int kDMax = 256;     // largest d = k + p this build supports
+constexpr int kDMax = 544;        // largest d = k + p (dense inputs)
+constexpr int kDMaxCsr = 256;     // largest d = k + p for sparse (CSR) inputs
+constexpr int kCholRegMax = 256;  // up to this d the Cholesky holds G in registers
 constexpr int kTile = 16;      // side of the float64 Cholesky / solve tiles
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

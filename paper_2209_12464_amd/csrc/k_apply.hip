@@ -192,6 +192,11 @@ hipError_t launch_apply(const Tin* Y, int64_t ldy, int64_t rows, int d, int dp, 
   const size_t shmem = apply_lds_doubles(dp) * sizeof(double);
   const double isr = 1.0 / sqrt((double)rows);
   const unsigned groups = (unsigned)ceil_div(dp / kTile, 4);
+  if (shmem > 65536) {  // the substitution rows of a wide R take more than 64 KB
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(apply_kernel<Tin, Tout>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+  }
   if (ev0) (void)hipEventRecord(ev0, s);
   hipLaunchKernelGGL((apply_kernel<Tin, Tout>), dim3((unsigned)ceil_div(rows, kApRows), groups), dim3(256), shmem,
                      s, Y, ldy, rows, d, dp, R, Rinv16, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2,

@@ -232,19 +232,26 @@ hipError_t launch_gemm_bf16(const uint16_t* A, int64_t lda, const uint16_t* Xt, 
   float* C = nsplit == 1 ? Y : P;
   const int64_t ldc = nsplit == 1 ? ldy : nst;
   const int64_t cslice = nsplit == 1 ? 0 : (int64_t)M * nst;
+  // outputs wider than 256 columns take equal column passes (A is streamed once per pass)
+  const int npass = (int)ceil_div(round_up(N, 32), 256);
+  const int cw = (int)round_up(ceil_div(N, npass), 32);
   if (ev0) (void)hipEventRecord(ev0, s);
 #define RQLP_BF_LAUNCH(NB)                                                                                   \
-  hipLaunchKernelGGL(gemm_bf16_kernel<NB>, dim3(grid), dim3(kBfThreads), 0, s, A, lda, Xt, ldx, C, ldc, cslice, M, \
-                     N, K, kchunk, mtiles, nst)
-  switch ((int)round_up(N, 32) / 32) {
-    case 1: RQLP_BF_LAUNCH(1); break;
-    case 2: RQLP_BF_LAUNCH(2); break;
-    case 3: RQLP_BF_LAUNCH(3); break;
-    case 4: RQLP_BF_LAUNCH(4); break;
-    case 5: RQLP_BF_LAUNCH(5); break;
-    case 6: RQLP_BF_LAUNCH(6); break;
-    case 7: RQLP_BF_LAUNCH(7); break;
-    default: RQLP_BF_LAUNCH(8); break;
+  hipLaunchKernelGGL(gemm_bf16_kernel<NB>, dim3(grid), dim3(kBfThreads), 0, s, A, lda, Xt + (int64_t)c0 * ldx, ldx, \
+                     C + c0, ldc, cslice, M, nc, K, kchunk, mtiles, nst_c)
+  for (int c0 = 0; c0 < N; c0 += cw) {
+    const int nc = std::min(cw, N - c0);
+    const int nst_c = (c0 + cw >= N) ? nst - c0 : cw;  // the last pass also writes the zero columns
+    switch ((int)round_up(nc, 32) / 32) {
+      case 1: RQLP_BF_LAUNCH(1); break;
+      case 2: RQLP_BF_LAUNCH(2); break;
+      case 3: RQLP_BF_LAUNCH(3); break;
+      case 4: RQLP_BF_LAUNCH(4); break;
+      case 5: RQLP_BF_LAUNCH(5); break;
+      case 6: RQLP_BF_LAUNCH(6); break;
+      case 7: RQLP_BF_LAUNCH(7); break;
+      default: RQLP_BF_LAUNCH(8); break;
+    }
   }
 #undef RQLP_BF_LAUNCH
   if (ev1) (void)hipEventRecord(ev1, s);

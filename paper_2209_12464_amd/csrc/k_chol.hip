@@ -1,8 +1,8 @@
-// Cholesky factor of the float64 Gram matrix, G = R^T R (R upper), for
-// d <= 256: the middle step of each CholeskyQR pass (orth() and qr() of the
-// paper, computed as an unpivoted QR with a positive diagonal in R).
+// Cholesky factor of the float64 Gram matrix, G = R^T R (R upper): the
+// middle step of each CholeskyQR pass (orth() and qr() of the paper,
+// computed as an unpivoted QR with a positive diagonal in R).
 //
-// One workgroup of 8 waves, right-looking over 16-column blocks k.  The
+// For d <= 256, one workgroup of 8 waves, right-looking over 16-column blocks k.  The
 // lower triangle of G is cut into 16 x 16 tiles held in registers (MFMA
 // 16x16x4 accumulator layout: lane l holds rows l/16 + 4 s, column l % 16),
 // dealt round-robin to the waves.  Per block column k:
@@ -138,6 +138,45 @@ __device__ inline void diag_step4(doublex4& a, doublex4& x, int lane, int lr, in
   depmask |= dm << j0;
 }
 
+// Fast path of the second CholeskyQR pass: when ||G - I||_F < fast_tol
+// (from the nesq partial sums the Gram reduction wrote; every workgroup adds
+// them in the same fixed order), all workgroups write their share of
+// R = I + F and R^-1 = I - F, and the call returns true.
+__device__ inline bool chol_fast_path(const double* __restrict__ G, int d, int dp, double* __restrict__ R,
+                                      double* __restrict__ Rinv16, int32_t* __restrict__ flags, double fast_tol,
+                                      const double* __restrict__ esq, int nesq, int32_t* __restrict__ mode,
+                                      double* __restrict__ Xfull, double* red, int nw) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double ss = 0.0;
+  for (int e = tid; e < nesq; e += blockDim.x) ss += esq[e];
+  for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
+  if (lane == 0) red[wave] = ss;
+  __syncthreads();
+  double tot = 0.0;
+  for (int w = 0; w < nw; ++w) tot += red[w];
+  if (tot < fast_tol * fast_tol) {  // false for NaN
+    for (int e = blockIdx.x * blockDim.x + tid; e < dp * dp; e += gridDim.x * blockDim.x) {
+      const int i = e / dp, j = e - (e / dp) * dp;
+      double f = 0.0;  // F[i][j]
+      if (i < d && j < d && i <= j) {
+        const double g = G[(int64_t)i * dp + j];
+        f = (i < j) ? g : 0.5 * (g - 1.0);
+      }
+      const double id = (i == j) ? 1.0 : 0.0;
+      R[(int64_t)i * dp + j] = id + f;
+      Xfull[(int64_t)i * dp + j] = id - f;
+      if ((i >> 4) == (j >> 4))
+        Rinv16[(int64_t)(i >> 4) * kTile * kTile + (i & 15) * kTile + (j & 15)] = id - f;
+    }
+    for (int i = blockIdx.x * blockDim.x + tid; i < dp; i += gridDim.x * blockDim.x) flags[i] = 0;
+    if (blockIdx.x == 0 && tid == 0) *mode = 2;  // explicit inverse already written
+    return true;
+  }
+  __syncthreads();
+  return false;
+}
+
 template <int NW, int SLOTS>
 __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict__ G, int d, int dp,
                                                     double* __restrict__ R,
@@ -147,10 +186,10 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
                                                     const double* __restrict__ esq, int nesq,
                                                     int32_t* __restrict__ mode,
                                                     double* __restrict__ Xfull) {
-  __shared__ double Pn[kDMax / kTile][kTile][kTile + 1];  // panel tiles L_ik of column k
-  __shared__ double Di[kTile][kTile + 1];                  // inverse of the diagonal factor
-  __shared__ double Gdiag[kDMax];
-  __shared__ int defl[kDMax];
+  __shared__ double Pn[kCholRegMax / kTile][kTile][kTile + 1];  // panel tiles L_ik of column k
+  __shared__ double Di[kTile][kTile + 1];                        // inverse of the diagonal factor
+  __shared__ double Gdiag[kCholRegMax];
+  __shared__ int defl[kCholRegMax];
   __shared__ double red[NW];
   __shared__ double Mb[16];  // 4 x 4 inverse of the current diagonal block step
 
@@ -159,38 +198,8 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
   const int T = dp / kTile;
   const int lr = lane >> 4, lc = lane & 15;  // MFMA accumulator layout: row lr + 4 r, col lc
 
-  // ---------------- fast path: G close to the identity ----------------
-  // ||G - I||_F^2 comes as per-block partial sums from the Gram reduction;
-  // every workgroup adds them in the same fixed order.
-  if (fast_tol > 0.0) {
-    double ss = 0.0;
-    for (int e = tid; e < nesq; e += blockDim.x) ss += esq[e];
-    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
-    if (lane == 0) red[wave] = ss;
-    __syncthreads();
-    double tot = 0.0;
-    for (int w = 0; w < NW; ++w) tot += red[w];
-    if (tot < fast_tol * fast_tol) {  // false for NaN
-      // all workgroups write their share of R = I + F, R^-1 = I - F
-      for (int e = blockIdx.x * blockDim.x + tid; e < dp * dp; e += gridDim.x * blockDim.x) {
-        const int i = e / dp, j = e - (e / dp) * dp;
-        double f = 0.0;  // F[i][j]
-        if (i < d && j < d && i <= j) {
-          const double g = G[(int64_t)i * dp + j];
-          f = (i < j) ? g : 0.5 * (g - 1.0);
-        }
-        const double id = (i == j) ? 1.0 : 0.0;
-        R[(int64_t)i * dp + j] = id + f;
-        Xfull[(int64_t)i * dp + j] = id - f;
-        if ((i >> 4) == (j >> 4))
-          Rinv16[(int64_t)(i >> 4) * kTile * kTile + (i & 15) * kTile + (j & 15)] = id - f;
-      }
-      for (int i = blockIdx.x * blockDim.x + tid; i < dp; i += gridDim.x * blockDim.x) flags[i] = 0;
-      if (blockIdx.x == 0 && tid == 0) *mode = 2;  // explicit inverse already written
-      return;
-    }
-    __syncthreads();
-  }
+  if (fast_tol > 0.0 && chol_fast_path(G, d, dp, R, Rinv16, flags, fast_tol, esq, nesq, mode, Xfull, red, NW))
+    return;
   if (blockIdx.x != 0) return;  // the factorization runs in one workgroup
 
   // ---------------- full factorization ----------------
@@ -337,7 +346,196 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
   }
 }
 
-hipError_t launch_chol(const double* G, int d, int dp, double* R, double* Rinv16, int32_t* flags,
+// Cholesky for dp > kCholRegMax: the same right-looking algorithm, with the
+// lower tiles of the trailing matrix kept in G itself (updated in place,
+// 2.4 MB at d = 544, resident in L2) instead of registers, and 16 waves.
+// A tile is only ever read and written by its owner wave (tile t =
+// i (i + 1) / 2 + j belongs to wave t % NW), and by the same lane for the
+// same element, so no synchronisation beyond the per-step barriers is
+// needed.  Rows and columns in [d, dp) are read as the identity.
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void chol_big_kernel(double* __restrict__ G, int d, int dp,
+                                                        double* __restrict__ R, double* __restrict__ Rinv16,
+                                                        int32_t* __restrict__ flags, DevInfo* info, int pass_id,
+                                                        double tol, double fast_tol, const double* __restrict__ esq,
+                                                        int nesq, int32_t* __restrict__ mode,
+                                                        double* __restrict__ Xfull) {
+  __shared__ double Pn[kDMax / kTile][kTile][kTile + 1];  // panel tiles L_ik of column k
+  __shared__ double Di[kTile][kTile + 1];                  // inverse of the diagonal factor
+  __shared__ double Gdiag[kDMax];
+  __shared__ int defl[kDMax];
+  __shared__ double red[NW];
+  __shared__ double Mb[16];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int T = dp / kTile;
+  const int lr = lane >> 4, lc = lane & 15;
+
+  if (fast_tol > 0.0 && chol_fast_path(G, d, dp, R, Rinv16, flags, fast_tol, esq, nesq, mode, Xfull, red, NW))
+    return;
+  if (blockIdx.x != 0) return;
+
+  for (int i = tid; i < dp; i += blockDim.x) {
+    Gdiag[i] = (i < d) ? G[(int64_t)i * dp + i] : 1.0;
+    defl[i] = 0;
+  }
+  int ndep_total = 0;
+  __syncthreads();
+
+  auto load_tile = [&](int i, int j) {
+    doublex4 v;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = i * kTile + lr + 4 * r, col = j * kTile + lc;
+      const double g = G[(int64_t)row * dp + col];
+      v[r] = (row < d && col < d) ? g : (row == col ? 1.0 : 0.0);
+    }
+    return v;
+  };
+  auto store_tile = [&](int i, int j, const doublex4& v) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) G[(int64_t)(i * kTile + lr + 4 * r) * dp + j * kTile + lc] = v[r];
+  };
+  auto factor_diag = [&](int k, doublex4 t) {
+    doublex4 x;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = (lr + 4 * r == lc) ? 1.0 : 0.0;
+    const double gdl = Gdiag[k * kTile + lc];
+    int depmask = 0;
+    double* Rt = R + (int64_t)k * kTile * dp + k * kTile;
+    diag_step4<0>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
+    diag_step4<1>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
+    diag_step4<2>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
+    diag_step4<3>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = lr + 4 * r;
+      Di[row][lc] = x[r];
+      Rinv16[(int64_t)k * kTile * kTile + lc * kTile + row] = x[r];
+    }
+    if (lane < kTile) {
+      const int dep_c = (depmask >> lane) & 1;
+      defl[k * kTile + lane] = dep_c;
+      flags[k * kTile + lane] = dep_c;
+    }
+    ndep_total += __popc(depmask);
+  };
+  auto update_g = [&](doublex4& t, int i, int j) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kk = ks * 4 + lr;
+      t = Mfma<double>::mma(-Pn[i][lc][kk], Pn[j][lc][kk], t);
+    }
+  };
+  // first column j >= j0 of row i whose tile this wave owns
+  auto first_owned = [&](int i, int j0) {
+    const int base = i * (i + 1) / 2;
+    return j0 + ((wave - (base + j0)) % NW + NW) % NW;
+  };
+
+  if (wave == 0) factor_diag(0, load_tile(0, 0));
+  for (int k = 0; k < T; ++k) {
+    __syncthreads();
+    // ---------------- B: panel L_ik = G_ik L_kk^-T, two tiles at a time ----------------
+    {
+      int i = k + 1;
+      while (i < T && (i * (i + 1) / 2 + k) % NW != wave) ++i;
+      while (i < T) {
+        int i2 = i + 1;
+        while (i2 < T && (i2 * (i2 + 1) / 2 + k) % NW != wave) ++i2;
+        const doublex4 t1 = load_tile(i, k);
+        const doublex4 t2 = (i2 < T) ? load_tile(i2, k) : Mfma<double>::zero();
+        const int ni = (i2 < T) ? 2 : 1;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          if (u >= ni) break;
+          const int ii = u ? i2 : i;
+          const doublex4& tt = u ? t2 : t1;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Pn[ii][lr + 4 * r][lc] = tt[r];
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          doublex4 acc = Mfma<double>::zero();
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            const int kk = ks * 4 + lr;
+            acc = Mfma<double>::mma(Pn[ii][lc][kk], Di[lc][kk], acc);
+          }
+          const bool zc = defl[k * kTile + lc] != 0;
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Pn[ii][lr + 4 * r][lc] = zc ? 0.0 : acc[r];
+        }
+        i = i2 + 1;
+        while (i < T && (i * (i + 1) / 2 + k) % NW != wave) ++i;
+      }
+    }
+    __syncthreads();
+    // ---------------- C: trailing update, with the next A looked ahead ----------------
+    const int kn = k + 1;
+    const int own = (kn * (kn + 1) / 2 + kn) % NW;
+    const bool ahead = kn < T && wave == own;
+    if (ahead) {
+      doublex4 t = load_tile(kn, kn);
+      update_g(t, kn, kn);
+      factor_diag(kn, t);
+    } else {
+      const int nt = (kn < T) ? NW - 1 : NW;
+      const int pw = (kn < T && wave > own) ? wave - 1 : wave;
+      for (int e = pw * kWave + lane; e < (T - 1 - k) * kTile * kTile; e += nt * kWave) {
+        const int i = k + 1 + e / (kTile * kTile), row = (e / kTile) % kTile, col = e % kTile;
+        R[(int64_t)(k * kTile + col) * dp + i * kTile + row] = Pn[i][row][col];
+        R[(int64_t)(i * kTile + row) * dp + k * kTile + col] = 0.0;
+      }
+    }
+    // owned tiles (i, j), kn <= j <= i, row by row, four loads in flight
+    int ci = kn, cj = (kn < T) ? first_owned(kn, kn) : 0;
+    auto advance = [&]() {
+      cj += NW;
+      while (ci < T && cj > ci) {
+        ++ci;
+        if (ci < T) cj = first_owned(ci, kn);
+      }
+    };
+    while (ci < T && cj > ci) {  // the first row may hold no owned tile
+      ++ci;
+      if (ci < T) cj = first_owned(ci, kn);
+    }
+    while (ci < T) {
+      int bi[4], bj[4], nb = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        bi[u] = ci;
+        bj[u] = cj;
+        if (ci < T) {
+          ++nb;
+          advance();
+        }
+      }
+      doublex4 tb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) tb[u] = (u < nb) ? load_tile(bi[u], bj[u]) : Mfma<double>::zero();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (u < nb && !(ahead && bi[u] == kn && bj[u] == kn)) {
+          update_g(tb[u], bi[u], bj[u]);
+          store_tile(bi[u], bj[u], tb[u]);
+        }
+      }
+    }
+  }
+  int anydep = 0;
+  for (int i = tid; i < dp; i += blockDim.x) anydep |= defl[i];
+  anydep = __syncthreads_or(anydep);
+  if (tid == 0) *mode = anydep ? 0 : 1;
+  if (lane == 0 && ndep_total > 0) {
+    atomicAdd(&info->completed_cols, ndep_total);
+    atomicCAS(&info->breakdown_pass, 0, pass_id);
+  }
+}
+
+hipError_t launch_chol(double* G, int d, int dp, double* R, double* Rinv16, int32_t* flags,
                        void* info, int pass_id, double fast_tol, const double* esq, int nesq,
                        int32_t* mode, double* Xfull, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const double tol = 64.0 * (double)d * 2.220446049250313e-16;
@@ -347,7 +545,10 @@ hipError_t launch_chol(const double* G, int d, int dp, double* R, double* Rinv16
   // slots chosen so that tiles and the diagonal-block code fit in registers)
   const int tiles = T * (T + 1) / 2;
   const unsigned grid = fast_tol > 0.0 ? 16 : 1;  // extra workgroups only help the fast path
-  if (tiles <= 8 * 7)
+  if (dp > kCholRegMax)
+    hipLaunchKernelGGL((chol_big_kernel<16>), dim3(grid), dim3(16 * kWave), 0, s, G, d, dp, R, Rinv16, flags,
+                       (DevInfo*)info, pass_id, tol, fast_tol, esq, nesq, mode, Xfull);
+  else if (tiles <= 8 * 7)
     hipLaunchKernelGGL((chol_kernel<8, 7>), dim3(grid), dim3(8 * kWave), 0, s, G, d, dp, R, Rinv16, flags,
                        (DevInfo*)info, pass_id, tol, fast_tol, esq, nesq, mode, Xfull);
   else if (tiles <= 8 * 14)

@@ -1,9 +1,9 @@
 // Dense products with A on the matrix cores: Y = A X (NN) and Y = A^T X (TN),
 // the sketch, power-step and projection products of Algorithms 1 and 2.
 //
-// The output is tall and skinny (d <= 256 columns), so one workgroup owns a
-// BM-row slab of Y and ALL of its columns: A is streamed from HBM exactly
-// once per product.  To fill 256 CUs the reduction dimension is split
+// The output is tall and skinny (d columns), so one workgroup owns a BM-row
+// slab of Y and all of its columns up to 256 (wider outputs take equal
+// column passes): A is streamed from HBM once per product and pass.  To fill 256 CUs the reduction dimension is split
 // (split-K); each split writes a partial slab and a second kernel sums the
 // partials in a fixed order, so results are bitwise reproducible.
 // Workgroup ids are remapped so that an XCD works on a contiguous range of
@@ -16,6 +16,8 @@
 // prefetch, one barrier per K step.
 #include "common.h"
 #include "kernels.h"
+
+#include <algorithm>
 
 namespace rqlp {
 
@@ -331,22 +333,36 @@ int gemm_block_cols(int N) { return (int)round_up(N, 32); }
 template int gemm_block_cols<float>(int);
 template int gemm_block_cols<double>(int);
 
+// Widest column tile of one pass; wider outputs are cut into equal passes
+// of at most this many columns (A is then streamed once per pass).
+constexpr int kGemmMaxCols = 256;
+
 // Launch the main kernel (into C directly when nsplit == 1, else into the
-// partial buffer P) and, for nsplit > 1, the ordered reduction.
+// partial buffer P) once per column pass and, for nsplit > 1, the ordered
+// reduction over the full width.
 template <typename T>
 hipError_t launch_gemm(GemmArgs<T> g, T* Y, int64_t ldy, int nst, T* P, hipStream_t s,
                        hipEvent_t ev0, hipEvent_t ev1) {
   if (g.M <= 0 || nst <= 0) return hipSuccess;
   const int grid = g.mtiles * g.nsplit;
+  const int npass = (int)ceil_div(round_up(g.N, 32), kGemmMaxCols);
+  const int cw = (int)round_up(ceil_div(g.N, npass), 32);
   if (ev0) (void)hipEventRecord(ev0, s);
-  if (g.nsplit == 1) {
-    if (g.trans) dispatch_nb<T, true>(g, s, grid, Y, ldy, 0, nst);
-    else dispatch_nb<T, false>(g, s, grid, Y, ldy, 0, nst);
-  } else {
-    const int64_t ldp = nst;
-    const int64_t pslice = (int64_t)g.M * ldp;
-    if (g.trans) dispatch_nb<T, true>(g, s, grid, P, ldp, pslice, nst);
-    else dispatch_nb<T, false>(g, s, grid, P, ldp, pslice, nst);
+  for (int c0 = 0; c0 < g.N; c0 += cw) {
+    GemmArgs<T> gc = g;
+    gc.B = g.B + c0;
+    gc.N = std::min(cw, g.N - c0);
+    // the last pass also writes the zero columns [N, nst)
+    const int nst_c = (c0 + cw >= g.N) ? nst - c0 : cw;
+    if (g.nsplit == 1) {
+      if (g.trans) dispatch_nb<T, true>(gc, s, grid, Y + c0, ldy, 0, nst_c);
+      else dispatch_nb<T, false>(gc, s, grid, Y + c0, ldy, 0, nst_c);
+    } else {
+      const int64_t ldp = nst;
+      const int64_t pslice = (int64_t)g.M * ldp;
+      if (g.trans) dispatch_nb<T, true>(gc, s, grid, P + c0, ldp, pslice, nst_c);
+      else dispatch_nb<T, false>(gc, s, grid, P + c0, ldp, pslice, nst_c);
+    }
   }
   if (ev1) (void)hipEventRecord(ev1, s);
   if (g.nsplit > 1) {

@@ -5,7 +5,7 @@
 //     X_JJ = R_JJ^-1,   X_IJ = -R_II^-1 sum_{t = I+1..J} R_It X_tJ   (I < J),
 // right-looking: as soon as X_{I+1,J} is known every pending block row
 // I' <= I adds R_{I',I+1} X_{I+1,J} to its accumulator (float64 MFMA), and the
-// owner of row I finishes it with R_II^-1.  Rows are dealt to the 8 waves
+// owner of row I finishes it with R_II^-1.  Rows are dealt to the waves
 // round-robin; X_{I+1,J} is passed through LDS (double buffered, one
 // workgroup barrier per block row).  The step loop is unrolled so that the
 // R tiles of each step can be loaded into a register ring several steps
@@ -19,15 +19,14 @@
 
 namespace rqlp {
 
-constexpr int kInvWaves = 8;
-constexpr int kInvRows = kDMax / kTile / kInvWaves;  // block rows per wave
-constexpr int kInvT = kDMax / kTile;                 // largest number of block rows
-constexpr int kInvAhead = 4;                         // R tiles are loaded this many steps early
-
+// kInvWaves waves; up to kInvT block rows (dp <= 16 kInvT); R tiles are
+// loaded kInvAhead steps before they are used.
+template <int kInvWaves, int kInvT, int kInvAhead>
 __global__ __launch_bounds__(kInvWaves * 64) void trinv_kernel(const double* __restrict__ R,
                                                                const double* __restrict__ Rinv16, int dp,
                                                                const int32_t* __restrict__ mode,
                                                                double* __restrict__ X) {
+  constexpr int kInvRows = (kInvT + kInvWaves - 1) / kInvWaves;  // block rows per wave
   __shared__ double Zs[2][kTile][kTile + 1];
   if (*mode != 1) return;
   const int J = blockIdx.x;
@@ -71,7 +70,7 @@ __global__ __launch_bounds__(kInvWaves * 64) void trinv_kernel(const double* __r
     Zs[0][r][c] = v;
     X[(int64_t)(J * kTile + r) * dp + J * kTile + c] = v;
   }
-  doublex4 S[kInvRows];  // accumulators of block rows wave + 8 s
+  doublex4 S[kInvRows];  // accumulators of block rows wave + kInvWaves s
 #pragma unroll
   for (int s = 0; s < kInvRows; ++s) S[s] = Mfma<double>::zero();
   __syncthreads();
@@ -116,8 +115,12 @@ __global__ __launch_bounds__(kInvWaves * 64) void trinv_kernel(const double* __r
 
 hipError_t launch_trinv(const double* R, const double* Rinv16, int dp, const int32_t* mode, double* X,
                         hipStream_t s) {
-  hipLaunchKernelGGL(trinv_kernel, dim3((unsigned)(dp / kTile)), dim3(kInvWaves * kWave), 0, s, R, Rinv16, dp,
-                     mode, X);
+  if (dp <= kCholRegMax)
+    hipLaunchKernelGGL((trinv_kernel<8, kCholRegMax / kTile, 4>), dim3((unsigned)(dp / kTile)), dim3(8 * kWave), 0,
+                       s, R, Rinv16, dp, mode, X);
+  else
+    hipLaunchKernelGGL((trinv_kernel<16, kDMax / kTile, 2>), dim3((unsigned)(dp / kTile)), dim3(16 * kWave), 0,
+                       s, R, Rinv16, dp, mode, X);
   return hipGetLastError();
 }
 

@@ -53,7 +53,7 @@ hipError_t launch_cvt_bf16_t(const float* X, int64_t ldx, int64_t K, int64_t N, 
                              hipStream_t s);
 // Y (M x nst, ldy) = A Xt^T with A (M x K bf16, lda) and Xt (N x K bf16,
 // ldx), both k-contiguous, K a multiple of 8 with zero padding, lda and ldx
-// multiples of 8, N <= 256.  P: split-K partials (gemm_bf16_partial_elems).
+// multiples of 8.  P: split-K partials (gemm_bf16_partial_elems).
 hipError_t launch_gemm_bf16(const uint16_t* A, int64_t lda, const uint16_t* Xt, int64_t ldx, int M, int N, int K,
                             float* Y, int64_t ldy, int nst, float* P, hipStream_t s, hipEvent_t ev0,
                             hipEvent_t ev1);
@@ -88,8 +88,9 @@ int gram_reduce_blocks(int dp);
 // esq written by launch_gram), use R = I + F (first order)
 // and write the explicit inverse I - F to Xfull (dp x dp); *mode is set to
 // 2 in that case.  After a full factorization *mode is 1 (launch_trinv then
-// forms Xfull = R^-1), or 0 when a column was dependent.
-hipError_t launch_chol(const double* G, int d, int dp, double* R, double* Rinv16, int32_t* flags,
+// forms Xfull = R^-1), or 0 when a column was dependent.  For dp > 256 the
+// factorization overwrites the lower triangle of G (its trailing updates).
+hipError_t launch_chol(double* G, int d, int dp, double* R, double* Rinv16, int32_t* flags,
                        void* info, int pass_id, double fast_tol, const double* esq, int nesq,
                        int32_t* mode, double* Xfull, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 

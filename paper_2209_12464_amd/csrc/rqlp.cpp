@@ -451,7 +451,7 @@ size_t rqlp_workspace_size(int64_t m, int64_t n, int k, int p, int q, rqlp_preci
 
 size_t rqlp_workspace_size_csr(int64_t m, int64_t n, int64_t nnz, int k, int p, int q, rqlp_precision prec) {
   if (check_common(m, n, k, p, q, prec) != RQLP_OK || nnz < 0 || nnz > INT32_MAX) return 0;
-  if (prec == RQLP_BF16_REFINED) return 0;
+  if (prec == RQLP_BF16_REFINED || k + p > kDMaxCsr) return 0;
   return prec == RQLP_FP64 ? layout<double>(m, n, k + p, true, nnz).total
                            : layout<float>(m, n, k + p, true, nnz).total;
 }
@@ -484,7 +484,7 @@ rqlp_status rqlp_decompose_csr(rqlp_ctx* c, const int32_t* rowptr, const int32_t
   if (nnz > 0 && (!colidx || !vals)) return RQLP_ERR_INVALID_ARG;
   rqlp_status st = check_common(m, n, k, p, q, prec);
   if (st != RQLP_OK) return st;
-  if (prec == RQLP_BF16_REFINED) return RQLP_ERR_UNSUPPORTED;
+  if (prec == RQLP_BF16_REFINED || k + p > kDMaxCsr) return RQLP_ERR_UNSUPPORTED;
   if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
   hipStream_t s = (hipStream_t)stream;
   if (prec == RQLP_FP64)
@@ -627,7 +627,7 @@ rqlp_status rqlp_spmm(rqlp_ctx* c, const int32_t* rowptr, const int32_t* colidx,
   if (!c || !rowptr || !X || !Y || rows < 0 || cols < 1 || nnz < 0 || d < 1 || ldx < d || ldy < d ||
       !valid_prec(prec) || (nnz > 0 && (!colidx || !vals)))
     return RQLP_ERR_INVALID_ARG;
-  if (d > kDMax || prec == RQLP_BF16_REFINED || nnz > INT32_MAX) return RQLP_ERR_UNSUPPORTED;
+  if (d > kDMaxCsr || prec == RQLP_BF16_REFINED || nnz > INT32_MAX) return RQLP_ERR_UNSUPPORTED;
   if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
   hipStream_t s = (hipStream_t)stream;
   EvPair t = timer(c, RQLP_KT_SPMM);

@@ -46,7 +46,9 @@ def test_workspace_size_argument_checks(lib):
     assert lib.rqlp_workspace_size(8000, 8000, 200, 10, 1, 1) > 0
     assert lib.rqlp_workspace_size(8000, 8000, 0, 10, 1, 1) == 0        # k < 1
     assert lib.rqlp_workspace_size(100, 50, 45, 10, 0, 1) == 0          # d > min(m, n)
-    assert lib.rqlp_workspace_size(1000, 1000, 250, 10, 0, 1) == 0      # d > 256
+    assert lib.rqlp_workspace_size(1000, 1000, 250, 10, 0, 1) > 0       # d = 260: wide tiles
+    assert lib.rqlp_workspace_size(2000, 2000, 540, 5, 0, 1) == 0       # d > 544
+    assert lib.rqlp_workspace_size_csr(1000, 1000, 5000, 250, 10, 0, 1) == 0  # CSR: d > 256
     assert lib.rqlp_workspace_size(100, 50, 5, 1, -1, 1) == 0           # q < 0
     assert lib.rqlp_workspace_size(100, 50, 5, 1, 0, 7) == 0            # bad precision
     # bfloat16 products: dense only, and the workspace adds the bf16 copies of A and A^T

@@ -54,11 +54,17 @@ def test_small_fp64_config(gpu_lib):
 
 
 @pytest.mark.parametrize("m,n,k,p,q", [(600, 450, 30, 10, 0), (600, 450, 30, 10, 2), (450, 600, 20, 5, 1),
-                                       (300, 300, 250, 6, 1), (97, 61, 60, 1, 1), (200, 40, 1, 0, 0)])
+                                       (300, 300, 250, 6, 1), (97, 61, 60, 1, 1), (200, 40, 1, 0, 0),
+                                       # d > 256 (wide Cholesky, column passes), up to the largest d = 544
+                                       (1500, 1200, 300, 20, 1), (1100, 900, 520, 24, 0), (700, 900, 260, 1, 1)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_shapes_and_edges(gpu_lib, m, n, k, p, q, dtype):
     announce("decompose shapes", m, n, k, p, q, dtype)
-    sigma = workloads.spectrum("geometric", min(m, n), rho=0.97)
+    # CholeskyQR2 needs cond(A Omega) well below 1 / sqrt(u64) ~ 7e7; with
+    # rho = 0.97 the sketch of width 544 would reach ~1e8, so wide sketches
+    # take a slower decay
+    rho = 0.97 if k + p <= 256 else 0.99
+    sigma = workloads.spectrum("geometric", min(m, n), rho=rho)
     A, _, _, _ = workloads.dense_from_spectrum(m, n, sigma, seed=m + n, trunc=0.0)
     A = A.astype(np.float32) if dtype == torch.float32 else A
     Qg, Lg, Vg = _run(gpu_lib, A, k, p, q, 3, dtype)
@@ -146,15 +152,14 @@ def test_full_size_gapped_fp32(gpu_lib):
 #    ulp, a ~2e-5 relative change of each product, which the power steps
 #    carry into the basis (measured: 5e-5 to 1.3e-4).
 #  - against the plain float64 oracle: Delta <= 2e-2, and the error
-#    ||A - Q L V^T||_F / ||A||_F within 5 % of the float64 method's when the
-#    rounding noise of A projected on d of n directions, ~2^-9 sqrt(d / n),
-#    is small beside that error (d / n <= 0.1 here, as at 20000 x 15000,
-#    k = 500, p = 20).
+#    e = ||A - Q L V^T||_F / ||A||_F at most the float64 method's plus the
+#    rounding noise that survives the projections (below).
 TOL_BF16_EMUL = 5e-4
 TOL_BF16_F64 = 2e-2
 
 
-@pytest.mark.parametrize("m,n,k,p,q", [(2000, 1500, 100, 20, 1), (1200, 1500, 60, 10, 0), (1000, 3000, 150, 20, 1)])
+@pytest.mark.parametrize("m,n,k,p,q", [(2000, 1500, 100, 20, 1), (1200, 1500, 60, 10, 0), (1000, 3000, 150, 20, 1),
+                                       (4000, 3000, 280, 20, 1)])
 def test_bf16_products(gpu_lib, m, n, k, p, q):
     announce("decompose bf16", m, n, k, p, q)
     sigma = workloads.spectrum("polynomial", min(m, n), power=1.5)
@@ -174,7 +179,11 @@ def test_bf16_products(gpu_lib, m, n, k, p, q):
           f"e={e_gpu:.4e} e_f64={e_f64:.4e}", flush=True)
     assert d_emul <= TOL_BF16_EMUL
     assert d_f64 <= TOL_BF16_F64
-    assert e_gpu <= 1.05 * e_f64
+    # bfloat16 rounding of A and of the right-hand factors adds noise of
+    # relative size ~2^-9 per entry, of which the projections Q Q^T keep a
+    # fraction ~sqrt(2 d / min(m, n)); allow that much (or 5 %) above e_f64
+    allow = max(0.05 * e_f64, 2.0 ** -9 * np.sqrt(2.0 * (k + p) / min(m, n)))
+    assert e_gpu <= e_f64 + allow
     assert orth_error(Qg) <= 1e-4 and orth_error(Vg) <= 1e-4
     assert np.all(np.triu(Lg, 1) == 0.0)
 

@@ -48,6 +48,8 @@ def test_gaussian_streams_differ(gpu_lib):
 GEMM_CASES = [
     (1000, 800, 25), (129, 77, 1), (300, 200, 33), (8000, 500, 210), (257, 1031, 256), (64, 64, 64),
     (5, 3000, 7),
+    # wider than one column tile: equal column passes
+    (3000, 700, 300), (2000, 1500, 544), (600, 700, 530), (40, 900, 257),
 ]
 
 
@@ -88,7 +90,7 @@ def test_gemm_unaligned_leading_dimension(gpu_lib):
 @pytest.mark.gpu
 @pytest.mark.parametrize("trans", [False, True])
 @pytest.mark.parametrize("m,n,d", [(1000, 777, 37), (300, 2000, 210), (8000, 8000, 210), (129, 67, 256),
-                                   (5, 3, 1)])
+                                   (5, 3, 1), (3000, 2000, 520), (700, 300, 257)])
 def test_gemm_bf16_matches_rounded_product(gpu_lib, trans, m, n, d):
     """bfloat16 products: the kernel multiplies round_bf16(A) and
     round_bf16(X) exactly and accumulates in float32, so it must match the
@@ -120,7 +122,9 @@ def _conditioned(m, d, cond, seed):
 
 
 @pytest.mark.parametrize("m,d,cond", [(1000, 25, 1e3), (8000, 210, 1e4), (500, 256, 1e2), (17, 17, 10.0),
-                                      (300, 1, 1.0), (4000, 110, 1e6)])
+                                      (300, 1, 1.0), (4000, 110, 1e6),
+                                      # d > 256: the Cholesky keeps its trailing tiles in memory
+                                      (3000, 320, 1e4), (2000, 544, 1e2), (1200, 417, 1e6), (600, 257, 10.0)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_orth_matches_householder(gpu_lib, m, d, cond, dtype):
     announce("orth", m, d, cond, dtype)
@@ -159,6 +163,38 @@ def test_orth_rank_deficient_completes_basis(gpu_lib, dtype):
     assert info["completed_cols"] == 9 and info["breakdown_pass"] == 1
     dep = [6, 7, 8, 9, 10, 11, 12, 13, 14]
     assert np.all(R[dep, :] == 0.0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_orth_rank_deficient_wide(gpu_lib, dtype):
+    """d = 300 > 256 with 40 dependent columns spread over the column
+    blocks: the wide Cholesky marks them and the solve substitutes."""
+    announce("orth rank-deficient wide", dtype)
+    rng = np.random.default_rng(19)
+    B = rng.standard_normal((1500, 260))
+    cols, dep = [], []
+    for c in range(260):
+        cols.append(B[:, c:c + 1])
+        if c % 6 == 4 and len(dep) < 40:  # a combination of the columns so far
+            dep.append(len(cols))
+            cols.append(B[:, : c + 1] @ rng.standard_normal((c + 1, 1)))
+    Y = np.hstack(cols)
+    assert Y.shape[1] == 300 and dep[0] == 5 and dep[-1] == 278
+    Y_in = Y.astype(np.float32) if dtype == torch.float32 else Y
+    ctx = gpu_lib.default_context(0)
+    Q, R = gpu_lib.orth(to_dev(Y_in), want_r=True, ctx=ctx)
+    Q, R = to_np(Q), to_np(R)
+    info = ctx.info()
+    d = Y.shape[1]
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    assert np.linalg.norm(Q.T @ Q - np.eye(d)) <= 10 * tol
+    assert np.linalg.norm(Q @ R - Y_in) <= 10 * tol * np.linalg.norm(Y)
+    assert info["completed_cols"] == 40 and info["breakdown_pass"] == 1
+    # a dependent column is a combination of the earlier columns of Q: its
+    # diagonal entry of R is exactly zero (the rest of its row is not, as
+    # later columns have components along the random completing directions)
+    assert np.all(np.diag(R)[dep] == 0.0)
+    assert np.all(np.diag(R)[[j for j in range(d) if j not in dep]] > 0.0)
 
 
 # ---------------------------------------------------------------- CSR
