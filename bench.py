@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {  # MI355X published dense peaks
+    "bf16_mfma_tflops": 2500.0,
     "f32_mfma_tflops": 157.3,
     "f64_mfma_tflops": 78.6,
     "hbm_gbs": 8000.0,
@@ -37,6 +38,9 @@ WORKLOADS = {
     "dense8000_q0": dict(kind="dense", m=8000, n=8000, k=200, p=10, q=0, dtype="f32", spectrum="gapped"),
     "small_fp64": dict(kind="dense", m=1000, n=800, k=20, p=5, q=0, dtype="f64", spectrum="geometric"),
     "csr100k": dict(kind="csr", m=100000, n=50000, k=100, p=10, q=1, dtype="f32", density=1e-3),
+    # bfloat16 products with float32 accumulation, float64 Gram and Cholesky
+    "bf16_20000x15000": dict(kind="dense", m=20000, n=15000, k=500, p=20, q=1, dtype="f32",
+                             spectrum="polynomial", bf16=True),
 }
 
 
@@ -93,10 +97,62 @@ def make_inputs(w, seed):
         if w["spectrum"] == "gapped":
             c = workloads.cfg_gapped_fp32(seed=seed, m=w["m"], n=w["n"], q=w["q"])
             return c["A"]
+        if w["spectrum"] == "polynomial":
+            return workloads.cfg_poly_bf16(seed=seed, m=w["m"], n=w["n"])["A"]
         c = workloads.cfg_small_fp64(seed=seed)
         return c["A"]
     c = workloads.cfg_sparse(seed=seed, m=w["m"], n=w["n"], density=w["density"])
     return c
+
+
+METRIC_NAMES = {
+    "dense8000": "RU-QLP GFLOP/s (8000^2 FP32, k=200, p=10, q=1)",
+    "bf16_20000x15000": "RU-QLP GFLOP/s (20000x15000, k=500, p=20, q=1, BF16 products + FP32 accumulation)",
+}
+
+
+def _recon_stats(torch, A, factors_a, factors_b=None, rows=2048):
+    """||A - Q L V^T||_F / ||A||_F of factors_a and, if factors_b is given,
+    ||Qa La Va^T - Qb Lb Vb^T||_F / ||A||_F, in float64 on the device, by row
+    blocks (measurement only, outside any timed region)."""
+    Qa, La, Va = (x.double() for x in factors_a)
+    LVa = La @ Va.T
+    if factors_b is not None:
+        Qb, Lb, Vb = (x.double() for x in factors_b)
+        LVb = Lb @ Vb.T
+    nA2 = e2 = dd2 = 0.0
+    for r0 in range(0, A.shape[0], rows):
+        Ab = A[r0:r0 + rows].double()
+        Ra = Qa[r0:r0 + rows] @ LVa
+        nA2 += float((Ab * Ab).sum())
+        e2 += float(((Ab - Ra) ** 2).sum())
+        if factors_b is not None:
+            dd2 += float(((Ra - Qb[r0:r0 + rows] @ LVb) ** 2).sum())
+    return np.sqrt(e2 / nA2), (np.sqrt(dd2 / nA2) if factors_b is not None else None)
+
+
+def compare_with_fp32(rqlp, ctx, A, k, p, q, args, out_bf16, ws_fp32_steps):
+    """The plain float32 form on the same GPU and input: its time per step,
+    both reconstruction errors and their difference Delta."""
+    import torch
+    m, n = A.shape
+    d = k + p
+    ws = rqlp.alloc_workspace(rqlp.workspace_size(m, n, k, p, q, A.dtype), A.device)
+    out = tuple(torch.empty_like(x) for x in out_bf16)
+    f32 = lambda: rqlp.decompose(A, k, p, q, seed=args.seed, ctx=ctx, workspace=ws, out=out)  # noqa: E731
+    for _ in range(max(1, args.warmup)):
+        f32()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(ws_fp32_steps):
+        f32()
+    torch.cuda.synchronize()
+    ms32 = (time.perf_counter() - t0) * 1e3 / ws_fp32_steps
+    e_bf, delta = _recon_stats(torch, A, out_bf16, out)
+    e_32, _ = _recon_stats(torch, A, out)
+    del ws
+    return {"fp32_ms_per_step": ms32, "e_bf16": e_bf, "e_fp32": e_32, "delta_bf16_vs_fp32": delta,
+            "d": d}
 
 
 def cpu_baseline(w, A_host, seed, flops):
@@ -109,7 +165,12 @@ def cpu_baseline(w, A_host, seed, flops):
     except Exception:  # pragma: no cover
         threads = os.cpu_count() or 1
     t0 = time.perf_counter()
-    if w["kind"] == "dense":
+    if w["kind"] == "dense" and w.get("bf16"):
+        oracle.ruqlp(A_host.astype(np.float64), w["k"], w["p"], w["q"], seed, omega_dtype="bf16",
+                     operand_dtype="bf16")
+        sample = (f"one full decomposition of the same {w['m']}x{w['n']} workload (q={w['q']}), "
+                  "bfloat16 operand rounding emulated")
+    elif w["kind"] == "dense":
         oracle.ruqlp(A_host.astype(np.float64), w["k"], w["p"], w["q"], seed,
                      omega_dtype="f32" if w["dtype"] == "f32" else "f64")
         sample = f"one full decomposition of the same {w['m']}x{w['n']} workload (q={w['q']})"
@@ -226,17 +287,19 @@ def main():
     ctx = rqlp.Context(0)
     k, p, q = w["k"], w["p"], w["q"]
     d = k + p
+    bf16 = bool(w.get("bf16"))
     if w["kind"] == "dense":
         A = torch.from_numpy(host).to(dev)
         m, n = A.shape
         flops = f_alg(m, n, k, p, q)
-        ws = rqlp.alloc_workspace(rqlp.workspace_size(m, n, k, p, q, A.dtype), dev)
+        ws = rqlp.alloc_workspace(rqlp.workspace_size(m, n, k, p, q, A.dtype, bf16=bf16), dev)
         out = (torch.empty((m, d), dtype=A.dtype, device=dev), torch.empty((d, d), dtype=A.dtype, device=dev),
                torch.empty((n, d), dtype=A.dtype, device=dev))
-        step = lambda: rqlp.decompose(A, k, p, q, seed=args.seed, ctx=ctx, workspace=ws, out=out)  # noqa: E731
+        step = lambda: rqlp.decompose(A, k, p, q, seed=args.seed, ctx=ctx, workspace=ws, out=out,  # noqa: E731
+                                      bf16=bf16)
         dom = ["gemm_nn", "gemm_tn"]
         dom_flops = {"gemm_nn": 2.0 * m * n * d, "gemm_tn": 2.0 * m * n * d}
-        dtype_name = "f32" if A.dtype == torch.float32 else "f64"
+        dtype_name = "bf16" if bf16 else ("f32" if A.dtype == torch.float32 else "f64")
     else:
         c = host
         m, n = c["m"], c["n"]
@@ -277,7 +340,7 @@ def main():
         kname = max(dom_present, key=lambda x: per_kernel[x]["total_ms"])
         avg_s = per_kernel[kname]["avg_ms"] * 1e-3
         if w["kind"] == "dense":
-            peak = PEAK["f32_mfma_tflops"] if dtype_name == "f32" else PEAK["f64_mfma_tflops"]
+            peak = PEAK[{"bf16": "bf16_mfma_tflops", "f32": "f32_mfma_tflops"}.get(dtype_name, "f64_mfma_tflops")]
             achieved = dom_flops[kname] / avg_s / 1e12
             traffic = load_traffic(args.workload, kname)
             roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -292,9 +355,10 @@ def main():
             roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
                         "frac": achieved / PEAK["hbm_gbs"], "traffic": traffic, "kernel": kname}
 
+    vs_fp32 = compare_with_fp32(rqlp, ctx, A, k, p, q, args, out, ws_fp32_steps=args.steps) if bf16 else None
+
     res = {
-        "metric": "RU-QLP GFLOP/s (8000^2 FP32, k=200, p=10, q=1)" if args.workload == "dense8000"
-        else f"RU-QLP GFLOP/s ({args.workload})",
+        "metric": METRIC_NAMES.get(args.workload, f"RU-QLP GFLOP/s ({args.workload})"),
         "value": value,
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -310,6 +374,7 @@ def main():
                    "flops_per_step": flops},
         "roofline": roofline,
         "kernels": per_kernel,
+        **({"vs_fp32_same_gpu": vs_fp32} if vs_fp32 else {}),
         "info": info,
     }
     if not args.no_cpu_baseline:

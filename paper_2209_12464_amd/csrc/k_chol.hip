@@ -27,6 +27,8 @@
 #include "common.h"
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace rqlp {
 
 __device__ inline double bcast(double x, int lane) {
@@ -177,15 +179,21 @@ __device__ inline bool chol_fast_path(const double* __restrict__ G, int d, int d
   return false;
 }
 
+// G (dp x dp block, row stride ld; R the same) is factored in registers.
+// Standalone (block = 0): the whole matrix, with the fast path, and *mode
+// set to 1 or 0.  As a diagonal block of a larger factorization (block =
+// 1): nothing is done when *mode == 2, the dependence test takes the
+// original diagonal from gdiag0, and *mode is only lowered to 0.
 template <int NW, int SLOTS>
-__global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict__ G, int d, int dp,
+__global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict__ G, int ld, int d, int dp,
                                                     double* __restrict__ R,
                                                     double* __restrict__ Rinv16,
                                                     int32_t* __restrict__ flags, DevInfo* info,
                                                     int pass_id, double tol, double fast_tol,
                                                     const double* __restrict__ esq, int nesq,
                                                     int32_t* __restrict__ mode,
-                                                    double* __restrict__ Xfull) {
+                                                    double* __restrict__ Xfull,
+                                                    const double* __restrict__ gdiag0, int block) {
   __shared__ double Pn[kCholRegMax / kTile][kTile][kTile + 1];  // panel tiles L_ik of column k
   __shared__ double Di[kTile][kTile + 1];                        // inverse of the diagonal factor
   __shared__ double Gdiag[kCholRegMax];
@@ -198,13 +206,17 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
   const int T = dp / kTile;
   const int lr = lane >> 4, lc = lane & 15;  // MFMA accumulator layout: row lr + 4 r, col lc
 
-  if (fast_tol > 0.0 && chol_fast_path(G, d, dp, R, Rinv16, flags, fast_tol, esq, nesq, mode, Xfull, red, NW))
+  if (block) {
+    if (*mode == 2) return;
+  } else if (fast_tol > 0.0 &&
+             chol_fast_path(G, d, dp, R, Rinv16, flags, fast_tol, esq, nesq, mode, Xfull, red, NW)) {
     return;
+  }
   if (blockIdx.x != 0) return;  // the factorization runs in one workgroup
 
   // ---------------- full factorization ----------------
   for (int i = tid; i < dp; i += blockDim.x) {
-    Gdiag[i] = (i < d) ? G[(int64_t)i * dp + i] : 1.0;
+    Gdiag[i] = (i < d) ? (gdiag0 ? gdiag0[i] : G[(int64_t)i * ld + i]) : 1.0;
     defl[i] = 0;
   }
   const int ntiles = T * (T + 1) / 2;
@@ -223,7 +235,7 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
       double v = 0.0;
       if (t < ntiles) {
         const int row = i0 * kTile + lr + 4 * r, col = j0 * kTile + lc;
-        v = (row < d && col < d) ? G[(int64_t)row * dp + col] : (row == col ? 1.0 : 0.0);
+        v = (row < d && col < d) ? G[(int64_t)row * ld + col] : (row == col ? 1.0 : 0.0);
       }
       tile[sl][r] = v;
     }
@@ -244,11 +256,11 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
     for (int r = 0; r < 4; ++r) x[r] = (lr + 4 * r == lc) ? 1.0 : 0.0;
     const double gdl = Gdiag[k * kTile + lc];
     int depmask = 0;
-    double* Rt = R + (int64_t)k * kTile * dp + k * kTile;
-    diag_step4<0>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
-    diag_step4<1>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
-    diag_step4<2>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
-    diag_step4<3>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
+    double* Rt = R + (int64_t)k * kTile * ld + k * kTile;
+    diag_step4<0>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, ld, Mb);
+    diag_step4<1>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, ld, Mb);
+    diag_step4<2>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, ld, Mb);
+    diag_step4<3>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, ld, Mb);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = lr + 4 * r;
@@ -323,8 +335,8 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
       const int pw = (kn < T && wave > own) ? wave - 1 : wave;  // rank among them
       for (int e = pw * kWave + lane; e < (T - 1 - k) * kTile * kTile; e += nt * kWave) {
         const int i = k + 1 + e / (kTile * kTile), row = (e / kTile) % kTile, col = e % kTile;
-        R[(int64_t)(k * kTile + col) * dp + i * kTile + row] = Pn[i][row][col];
-        R[(int64_t)(i * kTile + row) * dp + k * kTile + col] = 0.0;
+        R[(int64_t)(k * kTile + col) * ld + i * kTile + row] = Pn[i][row][col];
+        R[(int64_t)(i * kTile + row) * ld + k * kTile + col] = 0.0;
       }
     }
 #pragma unroll
@@ -339,225 +351,161 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
   int anydep = 0;
   for (int i = tid; i < dp; i += blockDim.x) anydep |= defl[i];
   anydep = __syncthreads_or(anydep);
-  if (tid == 0) *mode = anydep ? 0 : 1;
+  if (tid == 0) {
+    if (!block) *mode = anydep ? 0 : 1;
+    else if (anydep) *mode = 0;
+  }
   if (lane == 0 && ndep_total > 0) {
     atomicAdd(&info->completed_cols, ndep_total);
     atomicCAS(&info->breakdown_pass, 0, pass_id);
   }
 }
 
-// Cholesky for dp > kCholRegMax: the same right-looking algorithm, with the
-// lower tiles of the trailing matrix kept in G itself (updated in place,
-// 2.4 MB at d = 544, resident in L2) instead of registers, and 16 waves.
-// A tile is only ever read and written by its owner wave (tile t =
-// i (i + 1) / 2 + j belongs to wave t % NW), and by the same lane for the
-// same element, so no synchronisation beyond the per-step barriers is
-// needed.  Rows and columns in [d, dp) are read as the identity.
-template <int NW>
-__global__ __launch_bounds__(NW * 64) void chol_big_kernel(double* __restrict__ G, int d, int dp,
-                                                        double* __restrict__ R, double* __restrict__ Rinv16,
-                                                        int32_t* __restrict__ flags, DevInfo* info, int pass_id,
-                                                        double tol, double fast_tol, const double* __restrict__ esq,
-                                                        int nesq, int32_t* __restrict__ mode,
-                                                        double* __restrict__ Xfull) {
-  __shared__ double Pn[kDMax / kTile][kTile][kTile + 1];  // panel tiles L_ik of column k
-  __shared__ double Di[kTile][kTile + 1];                  // inverse of the diagonal factor
-  __shared__ double Gdiag[kDMax];
-  __shared__ int defl[kDMax];
-  __shared__ double red[NW];
-  __shared__ double Mb[16];
+// ---------------- d > 256: blocked over register-sized diagonal blocks ----------------
+// The matrix is cut into nb diagonal blocks of at most 256 columns.  For
+// each block b in turn: R_bb = chol(G_bb) (chol_kernel in block mode), then,
+// unless b is the last block, X_bb = R_bb^-1 (inverse kernel),
+// R_b,r = X_bb^T G_b,r for the columns r after the block (rows of dependent
+// columns zero), and the trailing update G_r,r -= R_b,r^T R_b,r (both
+// triangles, in place).  The panel and update spread over many workgroups;
+// only the diagonal blocks run in one.
 
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int T = dp / kTile;
-  const int lr = lane >> 4, lc = lane & 15;
-
-  if (fast_tol > 0.0 && chol_fast_path(G, d, dp, R, Rinv16, flags, fast_tol, esq, nesq, mode, Xfull, red, NW))
+// Fast path of the second pass (all workgroups), else the original diagonal
+// into gd0 (for the dependence test of later blocks) and *mode = 1.
+__global__ __launch_bounds__(1024) void chol_prep_kernel(const double* __restrict__ G, int d, int dp,
+                                                      double* __restrict__ R, double* __restrict__ Rinv16,
+                                                      int32_t* __restrict__ flags, double fast_tol,
+                                                      const double* __restrict__ esq, int nesq,
+                                                      int32_t* __restrict__ mode, double* __restrict__ Xfull,
+                                                      double* __restrict__ gd0) {
+  __shared__ double red[16];
+  if (fast_tol > 0.0 &&
+      chol_fast_path(G, d, dp, R, Rinv16, flags, fast_tol, esq, nesq, mode, Xfull, red, 16))
     return;
   if (blockIdx.x != 0) return;
+  for (int i = threadIdx.x; i < dp; i += blockDim.x) gd0[i] = (i < d) ? G[(int64_t)i * dp + i] : 1.0;
+  if (threadIdx.x == 0) *mode = 1;
+}
 
-  for (int i = tid; i < dp; i += blockDim.x) {
-    Gdiag[i] = (i < d) ? G[(int64_t)i * dp + i] : 1.0;
-    defl[i] = 0;
-  }
-  int ndep_total = 0;
-  __syncthreads();
-
-  auto load_tile = [&](int i, int j) {
-    doublex4 v;
+// R[b, r] = X_bb^T G[b, r] (one wave per 16 x 16 output tile, float64 MFMA)
+// and R[r, b] = 0; X_bb is upper triangular, so tile row I needs only the
+// first 16 (I + 1) rows of X_bb and G.
+__global__ __launch_bounds__(64) void chol_panel_kernel(const double* __restrict__ G, int ld, int off, int db,
+                                                     int rest, const double* __restrict__ X,
+                                                     double* __restrict__ R, const int32_t* __restrict__ flags,
+                                                     const int32_t* __restrict__ mode) {
+  if (*mode == 2) return;
+  const int nI = db / kTile;
+  const int I = blockIdx.x % nI, J = blockIdx.x / nI;
+  const int lane = threadIdx.x, lr = lane >> 4, lc = lane & 15;
+  const double* Xb = X + (int64_t)off * ld + off;
+  const double* Gb = G + (int64_t)off * ld + off + db;
+  doublex4 acc[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = i * kTile + lr + 4 * r, col = j * kTile + lc;
-      const double g = G[(int64_t)row * dp + col];
-      v[r] = (row < d && col < d) ? g : (row == col ? 1.0 : 0.0);
-    }
-    return v;
-  };
-  auto store_tile = [&](int i, int j, const doublex4& v) {
+  for (int u = 0; u < 4; ++u) acc[u] = Mfma<double>::zero();
+  const int kend = (I + 1) * kTile;
+  for (int t0 = 0; t0 < kend; t0 += kTile) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) G[(int64_t)(i * kTile + lr + 4 * r) * dp + j * kTile + lc] = v[r];
-  };
-  auto factor_diag = [&](int k, doublex4 t) {
-    doublex4 x;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) x[r] = (lr + 4 * r == lc) ? 1.0 : 0.0;
-    const double gdl = Gdiag[k * kTile + lc];
-    int depmask = 0;
-    double* Rt = R + (int64_t)k * kTile * dp + k * kTile;
-    diag_step4<0>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
-    diag_step4<1>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
-    diag_step4<2>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
-    diag_step4<3>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, dp, Mb);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = lr + 4 * r;
-      Di[row][lc] = x[r];
-      Rinv16[(int64_t)k * kTile * kTile + lc * kTile + row] = x[r];
-    }
-    if (lane < kTile) {
-      const int dep_c = (depmask >> lane) & 1;
-      defl[k * kTile + lane] = dep_c;
-      flags[k * kTile + lane] = dep_c;
-    }
-    ndep_total += __popc(depmask);
-  };
-  auto update_g = [&](doublex4& t, int i, int j) {
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const int kk = ks * 4 + lr;
-      t = Mfma<double>::mma(-Pn[i][lc][kk], Pn[j][lc][kk], t);
-    }
-  };
-  // first column j >= j0 of row i whose tile this wave owns
-  auto first_owned = [&](int i, int j0) {
-    const int base = i * (i + 1) / 2;
-    return j0 + ((wave - (base + j0)) % NW + NW) % NW;
-  };
-
-  if (wave == 0) factor_diag(0, load_tile(0, 0));
-  for (int k = 0; k < T; ++k) {
-    __syncthreads();
-    // ---------------- B: panel L_ik = G_ik L_kk^-T, two tiles at a time ----------------
-    {
-      int i = k + 1;
-      while (i < T && (i * (i + 1) / 2 + k) % NW != wave) ++i;
-      while (i < T) {
-        int i2 = i + 1;
-        while (i2 < T && (i2 * (i2 + 1) / 2 + k) % NW != wave) ++i2;
-        const doublex4 t1 = load_tile(i, k);
-        const doublex4 t2 = (i2 < T) ? load_tile(i2, k) : Mfma<double>::zero();
-        const int ni = (i2 < T) ? 2 : 1;
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          if (u >= ni) break;
-          const int ii = u ? i2 : i;
-          const doublex4& tt = u ? t2 : t1;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) Pn[ii][lr + 4 * r][lc] = tt[r];
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          doublex4 acc = Mfma<double>::zero();
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) {
-            const int kk = ks * 4 + lr;
-            acc = Mfma<double>::mma(Pn[ii][lc][kk], Di[lc][kk], acc);
-          }
-          const bool zc = defl[k * kTile + lc] != 0;
-          __builtin_amdgcn_wave_barrier();
-#pragma unroll
-          for (int r = 0; r < 4; ++r) Pn[ii][lr + 4 * r][lc] = zc ? 0.0 : acc[r];
-        }
-        i = i2 + 1;
-        while (i < T && (i * (i + 1) / 2 + k) % NW != wave) ++i;
-      }
-    }
-    __syncthreads();
-    // ---------------- C: trailing update, with the next A looked ahead ----------------
-    const int kn = k + 1;
-    const int own = (kn * (kn + 1) / 2 + kn) % NW;
-    const bool ahead = kn < T && wave == own;
-    if (ahead) {
-      doublex4 t = load_tile(kn, kn);
-      update_g(t, kn, kn);
-      factor_diag(kn, t);
-    } else {
-      const int nt = (kn < T) ? NW - 1 : NW;
-      const int pw = (kn < T && wave > own) ? wave - 1 : wave;
-      for (int e = pw * kWave + lane; e < (T - 1 - k) * kTile * kTile; e += nt * kWave) {
-        const int i = k + 1 + e / (kTile * kTile), row = (e / kTile) % kTile, col = e % kTile;
-        R[(int64_t)(k * kTile + col) * dp + i * kTile + row] = Pn[i][row][col];
-        R[(int64_t)(i * kTile + row) * dp + k * kTile + col] = 0.0;
-      }
-    }
-    // owned tiles (i, j), kn <= j <= i, row by row, four loads in flight
-    int ci = kn, cj = (kn < T) ? first_owned(kn, kn) : 0;
-    auto advance = [&]() {
-      cj += NW;
-      while (ci < T && cj > ci) {
-        ++ci;
-        if (ci < T) cj = first_owned(ci, kn);
-      }
-    };
-    while (ci < T && cj > ci) {  // the first row may hold no owned tile
-      ++ci;
-      if (ci < T) cj = first_owned(ci, kn);
-    }
-    while (ci < T) {
-      int bi[4], bj[4], nb = 0;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        bi[u] = ci;
-        bj[u] = cj;
-        if (ci < T) {
-          ++nb;
-          advance();
-        }
-      }
-      doublex4 tb[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) tb[u] = (u < nb) ? load_tile(bi[u], bj[u]) : Mfma<double>::zero();
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (u < nb && !(ahead && bi[u] == kn && bj[u] == kn)) {
-          update_g(tb[u], bi[u], bj[u]);
-          store_tile(bi[u], bj[u], tb[u]);
-        }
-      }
+    for (int u = 0; u < 4; ++u) {  // A[m][kk] = X_bb[t][I*16+m], B[kk][n] = G_b,r[t][J*16+n]
+      const int t = t0 + 4 * u + lr;
+      acc[u] = Mfma<double>::mma(Xb[(int64_t)t * ld + I * kTile + lc], Gb[(int64_t)t * ld + J * kTile + lc],
+                                 acc[u]);
     }
   }
-  int anydep = 0;
-  for (int i = tid; i < dp; i += blockDim.x) anydep |= defl[i];
-  anydep = __syncthreads_or(anydep);
-  if (tid == 0) *mode = anydep ? 0 : 1;
-  if (lane == 0 && ndep_total > 0) {
-    atomicAdd(&info->completed_cols, ndep_total);
-    atomicCAS(&info->breakdown_pass, 0, pass_id);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = I * kTile + lr + 4 * r, col = J * kTile + lc;
+    const double v = ((acc[0][r] + acc[1][r]) + acc[2][r]) + acc[3][r];
+    R[(int64_t)(off + row) * ld + off + db + col] = flags[off + row] ? 0.0 : v;
+    R[(int64_t)(off + db + col) * ld + off + row] = 0.0;
   }
+}
+
+// G[r, r] -= R[b, r]^T R[b, r] (one wave per 16 x 16 tile of the square
+// trailing block, K = db)
+__global__ __launch_bounds__(64) void chol_syrk_kernel(double* __restrict__ G, int ld, int off, int db, int rest,
+                                                    const double* __restrict__ R,
+                                                    const int32_t* __restrict__ mode) {
+  if (*mode == 2) return;
+  const int nI = rest / kTile;
+  const int I = blockIdx.x % nI, J = blockIdx.x / nI;
+  const int lane = threadIdx.x, lr = lane >> 4, lc = lane & 15;
+  const double* Rb = R + (int64_t)off * ld + off + db;
+  doublex4 acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = Mfma<double>::zero();
+  for (int t0 = 0; t0 < db; t0 += kTile) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + 4 * u + lr;
+      acc[u] = Mfma<double>::mma(Rb[(int64_t)t * ld + I * kTile + lc], Rb[(int64_t)t * ld + J * kTile + lc],
+                                 acc[u]);
+    }
+  }
+  double* Gt = G + (int64_t)(off + db + I * kTile) * ld + off + db + J * kTile;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    Gt[(int64_t)(lr + 4 * r) * ld + lc] -= ((acc[0][r] + acc[1][r]) + acc[2][r]) + acc[3][r];
+}
+
+// register slots per wave for the t (t + 1) / 2 lower tiles of a block of t
+// tile columns (8 waves; slots chosen so that tiles and the diagonal-block
+// code fit in registers)
+static hipError_t launch_chol_reg(const double* G, int ld, int d, int db, double* R, double* Rinv16,
+                                  int32_t* flags, void* info, int pass_id, double tol, double fast_tol,
+                                  const double* esq, int nesq, int32_t* mode, double* Xfull, const double* gdiag0,
+                                  int block, hipStream_t s) {
+  const int T = db / kTile;
+  const int tiles = T * (T + 1) / 2;
+  const unsigned grid = (!block && fast_tol > 0.0) ? 16 : 1;  // extra workgroups only help the fast path
+#define RQLP_CHOL_LAUNCH(S)                                                                                   \
+  hipLaunchKernelGGL((chol_kernel<8, S>), dim3(grid), dim3(8 * kWave), 0, s, G, ld, d, db, R, Rinv16, flags, \
+                     (DevInfo*)info, pass_id, tol, fast_tol, esq, nesq, mode, Xfull, gdiag0, block)
+  if (tiles <= 8 * 7) RQLP_CHOL_LAUNCH(7);
+  else if (tiles <= 8 * 14) RQLP_CHOL_LAUNCH(14);
+  else RQLP_CHOL_LAUNCH(17);
+#undef RQLP_CHOL_LAUNCH
+  return hipGetLastError();
 }
 
 hipError_t launch_chol(double* G, int d, int dp, double* R, double* Rinv16, int32_t* flags,
                        void* info, int pass_id, double fast_tol, const double* esq, int nesq,
-                       int32_t* mode, double* Xfull, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                       int32_t* mode, double* Xfull, double* gd0, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const double tol = 64.0 * (double)d * 2.220446049250313e-16;
   if (ev0) (void)hipEventRecord(ev0, s);
-  const int T = dp / kTile;
-  // register slots per wave for the T (T + 1) / 2 lower tiles (waves x
-  // slots chosen so that tiles and the diagonal-block code fit in registers)
-  const int tiles = T * (T + 1) / 2;
-  const unsigned grid = fast_tol > 0.0 ? 16 : 1;  // extra workgroups only help the fast path
-  if (dp > kCholRegMax)
-    hipLaunchKernelGGL((chol_big_kernel<16>), dim3(grid), dim3(16 * kWave), 0, s, G, d, dp, R, Rinv16, flags,
-                       (DevInfo*)info, pass_id, tol, fast_tol, esq, nesq, mode, Xfull);
-  else if (tiles <= 8 * 7)
-    hipLaunchKernelGGL((chol_kernel<8, 7>), dim3(grid), dim3(8 * kWave), 0, s, G, d, dp, R, Rinv16, flags,
-                       (DevInfo*)info, pass_id, tol, fast_tol, esq, nesq, mode, Xfull);
-  else if (tiles <= 8 * 14)
-    hipLaunchKernelGGL((chol_kernel<8, 14>), dim3(grid), dim3(8 * kWave), 0, s, G, d, dp, R, Rinv16, flags,
-                       (DevInfo*)info, pass_id, tol, fast_tol, esq, nesq, mode, Xfull);
-  else
-    hipLaunchKernelGGL((chol_kernel<8, 17>), dim3(grid), dim3(8 * kWave), 0, s, G, d, dp, R, Rinv16, flags,
-                       (DevInfo*)info, pass_id, tol, fast_tol, esq, nesq, mode, Xfull);
+  hipError_t e = hipSuccess;
+  if (dp <= kCholRegMax) {
+    e = launch_chol_reg(G, dp, d, dp, R, Rinv16, flags, info, pass_id, tol, fast_tol, esq, nesq, mode, Xfull,
+                        nullptr, 0, s);
+  } else {
+    hipLaunchKernelGGL(chol_prep_kernel, dim3(fast_tol > 0.0 ? 16 : 1), dim3(1024), 0, s, G, d, dp, R, Rinv16,
+                       flags, fast_tol, esq, nesq, mode, Xfull, gd0);
+    const int T = dp / kTile;
+    const int nb = (int)ceil_div(T, kCholRegMax / kTile);
+    int t0 = 0;
+    for (int b = 0; b < nb && e == hipSuccess; ++b) {
+      const int tb = (T - t0) / (nb - b);  // equal shares, the larger ones first
+      const int tbs = tb + ((T - t0) % (nb - b) ? 1 : 0);
+      const int off = t0 * kTile, db = tbs * kTile, rest = dp - off - db;
+      const int dl = std::max(0, std::min(d - off, db));
+      e = launch_chol_reg(G + (int64_t)off * dp + off, dp, dl, db, R + (int64_t)off * dp + off,
+                          Rinv16 + (int64_t)t0 * kTile * kTile, flags + off, info, pass_id, tol, 0.0, esq, nesq,
+                          mode, Xfull, gd0 + off, 1, s);
+      if (e == hipSuccess && rest > 0) {
+        e = launch_trinv_block(R + (int64_t)off * dp + off, Rinv16 + (int64_t)t0 * kTile * kTile, dp, tbs, mode, 1,
+                               Xfull + (int64_t)off * dp + off, s);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(chol_panel_kernel, dim3((unsigned)(tbs * (rest / kTile))), dim3(kWave), 0, s, G, dp, off,
+                           db, rest, Xfull, R, flags, mode);
+        hipLaunchKernelGGL(chol_syrk_kernel, dim3((unsigned)((rest / kTile) * (rest / kTile))), dim3(kWave), 0, s,
+                           G, dp, off, db, rest, R, mode);
+        e = hipGetLastError();
+      }
+      t0 += tbs;
+    }
+  }
   if (ev1) (void)hipEventRecord(ev1, s);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

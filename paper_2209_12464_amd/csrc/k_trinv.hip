@@ -19,16 +19,17 @@
 
 namespace rqlp {
 
-// kInvWaves waves; up to kInvT block rows (dp <= 16 kInvT); R tiles are
-// loaded kInvAhead steps before they are used.
+// kInvWaves waves; up to kInvT block rows (grid = number of block rows,
+// dp is the row stride of R and X); R tiles are loaded kInvAhead steps
+// before they are used.
 template <int kInvWaves, int kInvT, int kInvAhead>
 __global__ __launch_bounds__(kInvWaves * 64) void trinv_kernel(const double* __restrict__ R,
                                                                const double* __restrict__ Rinv16, int dp,
-                                                               const int32_t* __restrict__ mode,
+                                                               const int32_t* __restrict__ mode, int any_factor,
                                                                double* __restrict__ X) {
   constexpr int kInvRows = (kInvT + kInvWaves - 1) / kInvWaves;  // block rows per wave
   __shared__ double Zs[2][kTile][kTile + 1];
-  if (*mode != 1) return;
+  if (any_factor ? *mode == 2 : *mode != 1) return;
   const int J = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -115,12 +116,17 @@ __global__ __launch_bounds__(kInvWaves * 64) void trinv_kernel(const double* __r
 
 hipError_t launch_trinv(const double* R, const double* Rinv16, int dp, const int32_t* mode, double* X,
                         hipStream_t s) {
-  if (dp <= kCholRegMax)
-    hipLaunchKernelGGL((trinv_kernel<8, kCholRegMax / kTile, 4>), dim3((unsigned)(dp / kTile)), dim3(8 * kWave), 0,
-                       s, R, Rinv16, dp, mode, X);
+  return launch_trinv_block(R, Rinv16, dp, dp / kTile, mode, 0, X, s);
+}
+
+hipError_t launch_trinv_block(const double* R, const double* Rinv16, int ld, int nT, const int32_t* mode,
+                              int any_factor, double* X, hipStream_t s) {
+  if (nT <= kCholRegMax / kTile)
+    hipLaunchKernelGGL((trinv_kernel<8, kCholRegMax / kTile, 4>), dim3((unsigned)nT), dim3(8 * kWave), 0, s, R,
+                       Rinv16, ld, mode, any_factor, X);
   else
-    hipLaunchKernelGGL((trinv_kernel<16, kDMax / kTile, 2>), dim3((unsigned)(dp / kTile)), dim3(16 * kWave), 0,
-                       s, R, Rinv16, dp, mode, X);
+    hipLaunchKernelGGL((trinv_kernel<16, kDMax / kTile, 2>), dim3((unsigned)nT), dim3(16 * kWave), 0, s, R,
+                       Rinv16, ld, mode, any_factor, X);
   return hipGetLastError();
 }
 

@@ -77,6 +77,10 @@ int gram_chunks(int64_t rows, int dp);
 // dependent column).
 hipError_t launch_trinv(const double* R, const double* Rinv16, int dp, const int32_t* mode, double* X,
                         hipStream_t s);
+// The same for the nT x nT block upper-triangular R (row stride ld, as X),
+// run when *mode == 1, or, with any_factor, whenever *mode != 2.
+hipError_t launch_trinv_block(const double* R, const double* Rinv16, int ld, int nT, const int32_t* mode,
+                              int any_factor, double* X, hipStream_t s);
 int gram_reduce_blocks(int dp);
 
 // ---- float64 Cholesky (k_chol.hip) ----
@@ -89,10 +93,11 @@ int gram_reduce_blocks(int dp);
 // and write the explicit inverse I - F to Xfull (dp x dp); *mode is set to
 // 2 in that case.  After a full factorization *mode is 1 (launch_trinv then
 // forms Xfull = R^-1), or 0 when a column was dependent.  For dp > 256 the
-// factorization overwrites the lower triangle of G (its trailing updates).
+// factorization is blocked: it overwrites G's trailing blocks, uses Xfull
+// as scratch, and keeps the original diagonal in gd0 (dp doubles).
 hipError_t launch_chol(double* G, int d, int dp, double* R, double* Rinv16, int32_t* flags,
                        void* info, int pass_id, double fast_tol, const double* esq, int nesq,
-                       int32_t* mode, double* Xfull, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+                       int32_t* mode, double* Xfull, double* gd0, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 
 // ---- triangular solve Q = Y R^-1 (k_apply.hip) ----
 // Y: rows x dp (ldy, type Tin); out1 (ld1, first `ncols1` columns, type

@@ -158,7 +158,7 @@ Layout layout(int64_t m, int64_t n, int d, bool sparse, int64_t nnz, bool bf16 =
   L.rinv = put((size_t)dp * kTile * sizeof(double));
   L.flags = put((size_t)(2 * dp + 2) * sizeof(int32_t));
   L.xf = put((size_t)dp * dp * sizeof(double));
-  L.esq = put((size_t)gram_reduce_blocks(dp) * sizeof(double));
+  L.esq = put((size_t)(gram_reduce_blocks(dp) + dp) * sizeof(double));  // + the original diagonal
   if (sparse) {
     L.csr_rt = put((size_t)(n + 1) * sizeof(int32_t));
     L.csr_ct = put((size_t)nnz * sizeof(int32_t));
@@ -231,8 +231,8 @@ rqlp_status cholqr2(rqlp_ctx* c, const T* Y, int64_t ldy, int64_t rows, int d, c
   t = timer(c, RQLP_KT_GRAM);
   HIP_TRY(launch_gram<T>(Y, ldy, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
   t = timer(c, RQLP_KT_CHOL);
-  HIP_TRY(launch_chol(b.g, d, dp, b.r1, b.rinv, b.flags, c->info, orth_index, 0.0, b.esq, nesq, mode, b.xf, s, t.a,
-                      t.b));
+  HIP_TRY(launch_chol(b.g, d, dp, b.r1, b.rinv, b.flags, c->info, orth_index, 0.0, b.esq, nesq, mode, b.xf,
+                      b.esq + nesq, s, t.a, t.b));
   HIP_TRY(launch_trinv(b.r1, b.rinv, dp, mode, b.xf, s));
   t = timer(c, RQLP_KT_APPLY);
   HIP_TRY((launch_apply<T, double>(Y, ldy, rows, d, dp, b.r1, b.rinv, b.flags, mode, b.xf, b.q1, dp, dp, nullptr,
@@ -241,7 +241,7 @@ rqlp_status cholqr2(rqlp_ctx* c, const T* Y, int64_t ldy, int64_t rows, int d, c
   HIP_TRY(launch_gram<double>(b.q1, dp, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
   t = timer(c, RQLP_KT_CHOL);
   HIP_TRY(launch_chol(b.g, d, dp, b.r2, b.rinv, b.flags + dp, c->info, orth_index, ftol, b.esq, nesq, mode + 1,
-                      b.xf, s, t.a, t.b));
+                      b.xf, b.esq + nesq, s, t.a, t.b));
   HIP_TRY(launch_trinv(b.r2, b.rinv, dp, mode + 1, b.xf, s));
   t = timer(c, RQLP_KT_APPLY);
   HIP_TRY((launch_apply<double, T>(b.q1, dp, rows, d, dp, b.r2, b.rinv, b.flags + dp, mode + 1, b.xf, out1, ld1,
@@ -397,7 +397,7 @@ size_t orth_ws_bytes(int64_t rows, int d, rqlp_precision prec) {
   put((size_t)dp * kTile * sizeof(double));                       // rinv
   put((size_t)(2 * dp + 2) * sizeof(int32_t));                    // flags, modes
   put((size_t)dp * dp * sizeof(double));                          // explicit inverse
-  put((size_t)gram_reduce_blocks(dp) * sizeof(double));           // ||G - I||^2 partials
+  put((size_t)(gram_reduce_blocks(dp) + dp) * sizeof(double));    // ||G - I||^2 partials, diagonal
   put((size_t)rows * dp * (prec == RQLP_FP64 ? 8 : 4));           // padded copy of the output
   (void)prec;
   return off + 256;
@@ -609,7 +609,7 @@ rqlp_status rqlp_orth(rqlp_ctx* c, const void* Y, int64_t rows, int d, int64_t l
   b.rinv = (double*)take((size_t)dp * kTile * sizeof(double));
   b.flags = (int32_t*)take((size_t)(2 * dp + 2) * sizeof(int32_t));
   b.xf = (double*)take((size_t)dp * dp * sizeof(double));
-  b.esq = (double*)take((size_t)gram_reduce_blocks(dp) * sizeof(double));
+  b.esq = (double*)take((size_t)(gram_reduce_blocks(dp) + dp) * sizeof(double));
   HIP_TRY(launch_info_reset(c->info, s));
   if (prec == RQLP_FP64) {
     st = cholqr2<double>(c, (const double*)Y, ldy, rows, d, b, (double*)Q, ldq, d, nullptr, 0, 0, seed, 1, s);

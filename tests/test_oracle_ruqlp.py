@@ -127,3 +127,20 @@ def test_bf16_operand_model(q):
     assert np.linalg.norm(lhs - Qb @ (Qb.T @ A)) > 1e-6 * np.linalg.norm(rhs)
     diff = np.linalg.norm(Qb @ Lb @ Vb.T - Qd @ Ld @ Vd.T) / np.linalg.norm(A)
     assert 1e-6 < diff < 3e-2
+
+
+@pytest.mark.parametrize("m,n,seed", [(300, 200, 7), (257, 257, 1), (64, 5, 3)])
+def test_fast_orth_generator_has_exact_spectrum(m, n, seed):
+    """The structured-orthogonal input generator used for the 20000 x 15000
+    case: its singular values are exactly the prescribed ones, and its
+    singular vectors are spread (no entry of A dominates)."""
+    s = workloads.spectrum("polynomial", n, power=1.5)
+    A = workloads.dense_fast_orth(m, n, s, seed, np.float64)
+    sv = np.linalg.svd(A, compute_uv=False)
+    assert np.max(np.abs(sv - s) / s) < 1e-12
+    assert np.isclose(np.linalg.norm(A) ** 2, np.sum(s ** 2), rtol=1e-13)
+    # singular vectors are signed, permuted orthonormal DCT-II columns, whose
+    # entries are at most sqrt(2 / N): |A_ij| <= 2 sum(sigma) / sqrt(m n)
+    assert np.abs(A).max() <= 2.0 * s.sum() / np.sqrt(m * n) * (1 + 1e-12)
+    with pytest.raises(ValueError):
+        workloads.dense_fast_orth(n - 1 if n > 1 else 0, n, s, seed)

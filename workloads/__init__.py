@@ -14,6 +14,15 @@ by the signs of diag(R), so the distribution is exactly Haar).  Spectra:
 * the four theorem-evaluation matrices of Section V-B (LowRankLargeGap,
   LowRankMediumGap, LowRankSlowDecay, LowRankFastDecay).
 
+The 20000 x 15000 case is built with structured orthogonal factors instead
+(dense_fast_orth): U = P_m C_m D_m (first n columns) and V = P_n C_n D_n,
+with C the orthonormal DCT-II matrix, D a random sign diagonal and P a
+random row permutation.  They are exactly orthogonal, so A has exactly the
+prescribed singular values, and cost O(m n log m) instead of the O(m n^2)
+of Haar factors.  For a Gaussian test matrix the method's output
+distribution depends only on the singular values (V^T Omega is again
+Gaussian), so this changes nothing but the rounding pattern of A.
+
 Terms with sigma_i below `trunc` * sigma_1 are dropped before the product
 (A keeps only the first r singular triplets).  At the default 1e-10 this
 changes A by far less than its float32 rounding.
@@ -77,6 +86,29 @@ def dense_from_spectrum(m, n, sigma, seed, dtype=np.float64, trunc=1e-10):
     return A.astype(dtype), sigma_r, U, V
 
 
+def dense_fast_orth(m, n, sigma, seed, dtype=np.float32):
+    """A = U diag(sigma) V^T (m >= n, len(sigma) = n) with the structured
+    orthogonal factors described above; returns A in `dtype`."""
+    import scipy.fft
+    if m < n or len(sigma) != n:
+        raise ValueError("need m >= n and n singular values")
+    rng = _rng(seed)
+    dm = rng.choice(np.array([-1.0, 1.0]), size=m)
+    dn = rng.choice(np.array([-1.0, 1.0]), size=n)
+    pm = rng.permutation(m)
+    pn = rng.permutation(n)
+    sig = np.asarray(sigma, dtype=np.float64)
+    # V diag(sigma) = (C_n D_n diag(sigma))[pn]
+    vs = scipy.fft.dct(np.diag(dn * sig), type=2, norm="ortho", axis=0, workers=-1)[pn]
+    # A = U (V diag(sigma))^T = (C_m (D_m [ (V diag(sigma))^T ; 0 ]))[pm]
+    Z = np.zeros((m, n), dtype=np.float64)
+    Z[:n] = dm[:n, None] * vs.T
+    del vs
+    A = scipy.fft.dct(Z, type=2, norm="ortho", axis=0, workers=-1, overwrite_x=True)
+    del Z
+    return np.ascontiguousarray(A[pm].astype(dtype))
+
+
 def lowrank_plus_noise(n, k, mu, seed):
     """Section V-B LowRankLargeGap / LowRankMediumGap:
     A = U Sigma V^T + mu * sigma_k * A_N with A_N a Gaussian matrix scaled to
@@ -126,6 +158,14 @@ def cfg_gapped_fp32(seed=2, m=8000, n=8000, q=1):
     A, s, U, V = dense_from_spectrum(m, n, spectrum("gapped", min(m, n), gap_at=200), seed,
                                      np.float32)
     return dict(A=A, sigma=s, U=U, V=V, k=200, p=10, q=q, prec="f32")
+
+
+def cfg_poly_bf16(seed=4, m=20000, n=15000):
+    """20000 x 15000 FP32 input, sigma_i = i^-1.5 (structured orthogonal
+    factors), k=500, p=20, q=1, bfloat16 products."""
+    sigma = spectrum("polynomial", min(m, n), power=1.5)
+    A = dense_fast_orth(m, n, sigma, seed, np.float32)
+    return dict(A=A, sigma=sigma, k=500, p=20, q=1, prec="bf16")
 
 
 def cfg_sparse(seed=3, m=100000, n=50000, density=1e-3):
