@@ -9,9 +9,9 @@
 // both operands are kept k-contiguous: A as stored (row-major m x n) for
 // A X, a transposed copy of A for A^T X (both made by one conversion pass),
 // and the right-hand factor transposed (d x K) by a small conversion kernel.
-// The product kernel is then a single "NT" form, Y = A_op X^T_op, tiled like
-// the float32 kernel: 8 waves as 4 x 2, 128-row slabs with all columns per
-// workgroup (A read once), split-K with the ordered float32 reduction.
+// The product kernel is then a single "NT" form, Y = A_op X^T_op: 128-row
+// slabs with all columns per workgroup (A read once), split-K with the
+// ordered float32 reduction.
 #include <algorithm>
 
 #include "common.h"
@@ -110,24 +110,33 @@ hipError_t launch_cvt_bf16_t(const float* X, int64_t ldx, int64_t K, int64_t N, 
 
 // ---------------------------------------------------------------------------
 // the product: C (M x nst slab of split `split`) = A[M x K] Xt[N x K]^T
+//
+// 8 waves as 2 (row groups of 64) x 4 (column groups of 16 NF); a
+// workgroup owns a 128-row slab and all BN = 64 NF <= 576 columns, so A is
+// read once per product.  Per 32-wide reduction step a wave issues 4 NF
+// MFMAs (4 row fragments x NF column fragments) between barriers; operand
+// tiles go through LDS, double buffered, with the next step's loads in
+// registers meanwhile.
 
 constexpr int kBfThreads = 512;
 constexpr int kBfBK = 32;                 // one bf16 MFMA step
 constexpr int kBfStride = kBfBK + 8;      // LDS row stride (bf16): 80 bytes, conflict-free 16-byte reads
+constexpr int kBfBM = 128;
+constexpr int kBfMaxNF = 9;               // up to 576 columns per workgroup
 
-template <int NBW>
+template <int NF>
 __global__ __launch_bounds__(kBfThreads) void gemm_bf16_kernel(const uint16_t* __restrict__ A, int64_t lda,
                                                                const uint16_t* __restrict__ Xt, int64_t ldx,
                                                                float* __restrict__ C, int64_t ldc, int64_t cslice,
                                                                int M, int N, int K, int kchunk, int mtiles,
                                                                int nst) {
-  constexpr int BM = 128, BN = 32 * NBW;
+  constexpr int BM = kBfBM, BN = 64 * NF;
   constexpr int B_VECS = (BN * kBfBK / 8 + kBfThreads - 1) / kBfThreads;
   __shared__ __attribute__((aligned(16))) uint16_t As[2][BM][kBfStride];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN][kBfStride];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = wave & 3, wn = wave >> 2;
+  const int wm = wave & 1, wn = wave >> 1;
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   const int split = logical / mtiles;
   const int mt = logical - split * mtiles;
@@ -161,13 +170,13 @@ __global__ __launch_bounds__(kBfThreads) void gemm_bf16_kernel(const uint16_t* _
     }
   };
 
-  floatx4 acc[2][NBW];
+  floatx4 acc[4][NF];
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+  for (int rf = 0; rf < 4; ++rf)
 #pragma unroll
-    for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = (floatx4)0.0f;
-  const int arow = wm * 32 + (lane & 15);
-  const int bcol = wn * (BN / 2) + (lane & 15);
+    for (int cf = 0; cf < NF; ++cf) acc[rf][cf] = (floatx4)0.0f;
+  const int arow = wm * 64 + (lane & 15);
+  const int bcol = wn * 16 * NF + (lane & 15);
   const int kq = (lane >> 4) * 8;
   if (kbeg < kend) {
     load_tile(kbeg);
@@ -178,13 +187,16 @@ __global__ __launch_bounds__(kBfThreads) void gemm_bf16_kernel(const uint16_t* _
       const bool more = k0 + kBfBK < kend;
       if (more) load_tile(k0 + kBfBK);
       __builtin_amdgcn_s_setprio(1);
-      const bf16x8 a0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&As[buf][arow][kq]));
-      const bf16x8 a1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&As[buf][arow + 16][kq]));
+      bf16x8 a[4];
 #pragma unroll
-      for (int nb = 0; nb < NBW; ++nb) {
-        const bf16x8 b = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&Bs[buf][bcol + nb * 16][kq]));
-        acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc[0][nb], 0, 0, 0);
-        acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc[1][nb], 0, 0, 0);
+      for (int rf = 0; rf < 4; ++rf)
+        a[rf] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&As[buf][arow + rf * 16][kq]));
+#pragma unroll
+      for (int cf = 0; cf < NF; ++cf) {
+        const bf16x8 b = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&Bs[buf][bcol + cf * 16][kq]));
+#pragma unroll
+        for (int rf = 0; rf < 4; ++rf)
+          acc[rf][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rf], b, acc[rf][cf], 0, 0, 0);
       }
       __builtin_amdgcn_s_setprio(0);
       if (more) store_tile(buf ^ 1);
@@ -194,24 +206,40 @@ __global__ __launch_bounds__(kBfThreads) void gemm_bf16_kernel(const uint16_t* _
   }
   float* Cs = C + (int64_t)split * cslice;
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+  for (int rf = 0; rf < 4; ++rf)
 #pragma unroll
-    for (int nb = 0; nb < NBW; ++nb) {
-      const int col = wn * (BN / 2) + nb * 16 + (lane & 15);
+    for (int cf = 0; cf < NF; ++cf) {
+      const int col = wn * 16 * NF + cf * 16 + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 32 + mb * 16 + 4 * (lane >> 4) + r;
-        if (row < M && col < nst) Cs[(int64_t)row * ldc + col] = acc[mb][nb][r];
+        const int row = m0 + wm * 64 + rf * 16 + 4 * (lane >> 4) + r;
+        if (row < M && col < nst) Cs[(int64_t)row * ldc + col] = acc[rf][cf][r];
       }
     }
 }
 
-// Same split-K plan as the float32 product (a 128-row slab per workgroup,
-// about 512 workgroups in one round).
+// One workgroup per CU (registers and LDS), 256 CUs.  Large M: the split-K
+// count s in 1..4 that fills whole rounds of 256 workgroups best (fewest
+// splits on ties, since every split adds a partial slab to write and sum).
+// Small M: enough splits to reach about 256 workgroups, each with a
+// reduction chunk of at least 256.
 void plan_gemm_bf16(int M, int K, int* mtiles, int* nsplit, int* kchunk) {
-  *mtiles = (int)ceil_div(M, 128);
-  int64_t ns = std::max(1, 512 / *mtiles);
-  ns = std::min<int64_t>(ns, std::max<int64_t>(1, ceil_div(K, 256)));
+  *mtiles = (int)ceil_div(M, kBfBM);
+  const int64_t kmax = std::max<int64_t>(1, ceil_div(K, 256));
+  int64_t ns = 1;
+  if (*mtiles >= 128) {
+    double best = 0.0;
+    for (int sc = 1; sc <= 4 && sc <= kmax; ++sc) {
+      const int64_t wgs = (int64_t)*mtiles * sc;
+      const double eff = (double)wgs / (256.0 * (double)ceil_div(wgs, 256));
+      if (eff > best + 0.02) {
+        best = eff;
+        ns = sc;
+      }
+    }
+  } else {
+    ns = std::min<int64_t>(std::max(1, 256 / *mtiles), kmax);
+  }
   *kchunk = (int)round_up(ceil_div(std::max(K, 1), ns), kBfBK);
   *nsplit = (int)ceil_div(std::max(K, 1), *kchunk);
 }
@@ -232,17 +260,17 @@ hipError_t launch_gemm_bf16(const uint16_t* A, int64_t lda, const uint16_t* Xt, 
   float* C = nsplit == 1 ? Y : P;
   const int64_t ldc = nsplit == 1 ? ldy : nst;
   const int64_t cslice = nsplit == 1 ? 0 : (int64_t)M * nst;
-  // outputs wider than 256 columns take equal column passes (A is streamed once per pass)
-  const int npass = (int)ceil_div(round_up(N, 32), 256);
-  const int cw = (int)round_up(ceil_div(N, npass), 32);
+  // outputs wider than 576 columns take equal column passes (A is streamed once per pass)
+  const int npass = (int)ceil_div(round_up(N, 64), 64 * kBfMaxNF);
+  const int cw = (int)round_up(ceil_div(N, npass), 64);
   if (ev0) (void)hipEventRecord(ev0, s);
-#define RQLP_BF_LAUNCH(NB)                                                                                   \
-  hipLaunchKernelGGL(gemm_bf16_kernel<NB>, dim3(grid), dim3(kBfThreads), 0, s, A, lda, Xt + (int64_t)c0 * ldx, ldx, \
+#define RQLP_BF_LAUNCH(NF)                                                                                   \
+  hipLaunchKernelGGL(gemm_bf16_kernel<NF>, dim3(grid), dim3(kBfThreads), 0, s, A, lda, Xt + (int64_t)c0 * ldx, ldx, \
                      C + c0, ldc, cslice, M, nc, K, kchunk, mtiles, nst_c)
   for (int c0 = 0; c0 < N; c0 += cw) {
     const int nc = std::min(cw, N - c0);
     const int nst_c = (c0 + cw >= N) ? nst - c0 : cw;  // the last pass also writes the zero columns
-    switch ((int)round_up(nc, 32) / 32) {
+    switch ((int)ceil_div(nst_c, 64)) {
       case 1: RQLP_BF_LAUNCH(1); break;
       case 2: RQLP_BF_LAUNCH(2); break;
       case 3: RQLP_BF_LAUNCH(3); break;
@@ -250,7 +278,8 @@ hipError_t launch_gemm_bf16(const uint16_t* A, int64_t lda, const uint16_t* Xt, 
       case 5: RQLP_BF_LAUNCH(5); break;
       case 6: RQLP_BF_LAUNCH(6); break;
       case 7: RQLP_BF_LAUNCH(7); break;
-      default: RQLP_BF_LAUNCH(8); break;
+      case 8: RQLP_BF_LAUNCH(8); break;
+      default: RQLP_BF_LAUNCH(9); break;
     }
   }
 #undef RQLP_BF_LAUNCH
