@@ -198,8 +198,12 @@ typedef enum {
   RQLP_KT_COUNT = 6
 } rqlp_kernel_class;
 
-/* Turn per-launch event timing on (1) or off (0); resets the totals. */
+/* Turn per-launch event timing on (1) or off (0) for every class; resets
+ * the totals.  Each timed launch adds two event records to the stream. */
 rqlp_status rqlp_set_timing(rqlp_ctx* ctx, int enabled);
+
+/* The same for a subset of classes: bit k of mask enables class k. */
+rqlp_status rqlp_set_timing_mask(rqlp_ctx* ctx, uint32_t mask);
 
 /* After synchronizing: total milliseconds and launch count of a class since
  * timing was enabled (all recorded event pairs are resolved). */

@@ -76,7 +76,7 @@ __device__ inline double rsqrt_f64(double x) {
 // R = L^T's rows j0..j0+3 of the tile are written to Rt (row stride dp).
 template <int B>
 __device__ inline void diag_step4(doublex4& a, doublex4& x, int lane, int lr, int lc, double gdl, double tol,
-                                  int& depmask, double* __restrict__ Rt, int dp, double* Mb) {
+                                  int& depmask, double* __restrict__ Rt, int dp) {
   constexpr int j0 = 4 * B;
   double W[4][4];
 #pragma unroll
@@ -112,18 +112,13 @@ __device__ inline void diag_step4(doublex4& a, doublex4& x, int lane, int lr, in
       M[i][j] = -t * inv[i];
     }
   }
-  // A operand: lane (k, m) supplies M[m][k] (rows m >= 4 are zero), handed
-  // out through LDS from lane 0's copy of the uniform values
-  if (lane == 0) {
+  // A operand: lane (k, m) supplies M[m][k] (rows m >= 4 are zero); every
+  // lane holds the uniform M, so each picks its entry by selects
+  double am = 0.0;
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) Mb[4 * m + k] = (k <= m) ? M[m][k] : 0.0;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  const double am = (lc < 4) ? Mb[4 * lc + lr] : 0.0;
-  __builtin_amdgcn_wave_barrier();
+    for (int k = 0; k <= m; ++k) am = (lc == m && lr == k) ? M[m][k] : am;
   const doublex4 z = Mfma<double>::zero();
   const doublex4 c = Mfma<double>::mma(am, a[B], z);   // c[0] = (M S[j0.., :])[lr][lc]
   const doublex4 xn = Mfma<double>::mma(am, x[B], z);  // xn[0] = new X[j0 + lr][lc]
@@ -199,7 +194,6 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
   __shared__ double Gdiag[kCholRegMax];
   __shared__ int defl[kCholRegMax];
   __shared__ double red[NW];
-  __shared__ double Mb[16];  // 4 x 4 inverse of the current diagonal block step
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -257,10 +251,10 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
     const double gdl = Gdiag[k * kTile + lc];
     int depmask = 0;
     double* Rt = R + (int64_t)k * kTile * ld + k * kTile;
-    diag_step4<0>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, ld, Mb);
-    diag_step4<1>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, ld, Mb);
-    diag_step4<2>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, ld, Mb);
-    diag_step4<3>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, ld, Mb);
+    diag_step4<0>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, ld);
+    diag_step4<1>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, ld);
+    diag_step4<2>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, ld);
+    diag_step4<3>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, ld);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = lr + 4 * r;

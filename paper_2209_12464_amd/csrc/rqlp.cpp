@@ -25,7 +25,7 @@ struct rqlp_ctx {
   DevInfo* info = nullptr;      // device record
   void* ws_own = nullptr;       // internal workspace (grown on demand)
   size_t ws_own_bytes = 0;
-  bool timing = false;
+  uint32_t timing = 0;          // bit k: time launches of kernel class k
   struct Pair { hipEvent_t a, b; };
   std::vector<Pair> recorded[RQLP_KT_COUNT];
   std::vector<hipEvent_t> pool;
@@ -57,7 +57,7 @@ hipEvent_t take_event(rqlp_ctx* c) {
 
 EvPair timer(rqlp_ctx* c, rqlp_kernel_class k) {
   EvPair p;
-  if (!c->timing) return p;
+  if (!(c->timing >> (int)k & 1u)) return p;
   p.a = take_event(c);
   p.b = take_event(c);
   if (p.a && p.b) c->recorded[k].push_back({p.a, p.b});
@@ -666,7 +666,7 @@ rqlp_status rqlp_csr_transpose(rqlp_ctx* c, const int32_t* rowptr, const int32_t
   return RQLP_OK;
 }
 
-rqlp_status rqlp_set_timing(rqlp_ctx* c, int enabled) {
+rqlp_status rqlp_set_timing_mask(rqlp_ctx* c, uint32_t mask) {
   if (!c) return RQLP_ERR_INVALID_ARG;
   if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
   resolve_timing(c);
@@ -674,8 +674,12 @@ rqlp_status rqlp_set_timing(rqlp_ctx* c, int enabled) {
     c->total_ms[k] = 0;
     c->launches[k] = 0;
   }
-  c->timing = enabled != 0;
+  c->timing = mask & ((1u << RQLP_KT_COUNT) - 1);
   return RQLP_OK;
+}
+
+rqlp_status rqlp_set_timing(rqlp_ctx* c, int enabled) {
+  return rqlp_set_timing_mask(c, enabled ? (1u << RQLP_KT_COUNT) - 1 : 0u);
 }
 
 rqlp_status rqlp_get_timing(rqlp_ctx* c, rqlp_kernel_class cls, double* total_ms, int64_t* launches) {

@@ -68,6 +68,7 @@ def _lib():
             "rqlp_csr_transpose": (_INT, [_P, _P, _P, _P, _I64, _I64, _I64, _INT, _P, _P, _P, _P,
                                           _SZ, _P]),
             "rqlp_set_timing": (_INT, [_P, _INT]),
+            "rqlp_set_timing_mask": (_INT, [_P, ctypes.c_uint32]),
             "rqlp_get_timing": (_INT, [_P, _INT, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(_I64)]),
         }
@@ -85,7 +86,7 @@ def exported_symbols():
             "rqlp_decompose", "rqlp_decompose_csr", "rqlp_get_info", "rqlp_status_string",
             "rqlp_gaussian", "rqlp_gemm_workspace_size", "rqlp_gemm", "rqlp_orth_workspace_size",
             "rqlp_orth", "rqlp_spmm", "rqlp_csr_transpose_workspace_size", "rqlp_csr_transpose",
-            "rqlp_set_timing", "rqlp_get_timing"]
+            "rqlp_set_timing", "rqlp_set_timing_mask", "rqlp_get_timing"]
 
 
 def _check(status, where):
@@ -143,8 +144,17 @@ class Context:
         return dict(status=out.status, completed_cols=out.completed_cols,
                     breakdown_pass=out.breakdown_pass, nonfinite=out.nonfinite)
 
-    def set_timing(self, enabled):
-        _check(_lib().rqlp_set_timing(self._h, 1 if enabled else 0), "rqlp_set_timing")
+    def set_timing(self, enabled, classes=None):
+        """Event timing of every kernel class, or only of `classes` (names
+        from KERNEL_CLASSES)."""
+        if classes is None:
+            _check(_lib().rqlp_set_timing(self._h, 1 if enabled else 0), "rqlp_set_timing")
+            return
+        mask = 0
+        if enabled:
+            for name in classes:
+                mask |= 1 << KERNEL_CLASSES[name]
+        _check(_lib().rqlp_set_timing_mask(self._h, mask), "rqlp_set_timing_mask")
 
     def timing(self, cls):
         ms = ctypes.c_double()
