@@ -23,6 +23,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 
+// s_waitcnt immediate that waits until at most n vector memory operations
+// are outstanding (expcnt and lgkmcnt left at their no-wait maxima)
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+
 // float -> bfloat16 bits, round to nearest with ties to even (NaN stays NaN)
 __device__ inline uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -114,15 +118,25 @@ hipError_t launch_cvt_bf16_t(const float* X, int64_t ldx, int64_t K, int64_t N, 
 // 8 waves as 2 (row groups of 64) x 4 (column groups of 16 NF); a
 // workgroup owns a 128-row slab and all BN = 64 NF <= 576 columns, so A is
 // read once per product.  Per 32-wide reduction step a wave issues 4 NF
-// MFMAs (4 row fragments x NF column fragments) between barriers; operand
-// tiles go through LDS, double buffered, with the next step's loads in
-// registers meanwhile.
+// MFMAs (4 row fragments x NF column fragments).  Operand tiles go straight
+// from global memory to LDS (16 bytes per lane, no register staging)
+// through a ring of three stages: the tiles of step i + 2 are requested
+// while step i computes, one barrier per step.  A tile row is 64 bytes (32
+// bf16); its four 16-byte chunks are stored XOR-swizzled by (row / 4) mod
+// 4, so that the 16 rows one MFMA operand read touches fall in distinct
+// banks.  K is a multiple of 32 (zero padded) and so is every split, so no
+// step needs masking; rows past M or N are read clamped (their results are
+// not stored, or stored as zero).
 
 constexpr int kBfThreads = 512;
-constexpr int kBfBK = 32;                 // one bf16 MFMA step
-constexpr int kBfStride = kBfBK + 8;      // LDS row stride (bf16): 80 bytes, conflict-free 16-byte reads
+constexpr int kBfBK = 32;                 // one bf16 MFMA step; 64-byte tile rows
 constexpr int kBfBM = 128;
 constexpr int kBfMaxNF = 9;               // up to 576 columns per workgroup
+constexpr int kBfStages = 3;
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+__device__ inline int bf_swz(int row, int chunk) { return chunk ^ ((row >> 2) & 3); }
 
 template <int NF>
 __global__ __launch_bounds__(kBfThreads) void gemm_bf16_kernel(const uint16_t* __restrict__ A, int64_t lda,
@@ -131,9 +145,10 @@ __global__ __launch_bounds__(kBfThreads) void gemm_bf16_kernel(const uint16_t* _
                                                                int M, int N, int K, int kchunk, int mtiles,
                                                                int nst) {
   constexpr int BM = kBfBM, BN = 64 * NF;
-  constexpr int B_VECS = (BN * kBfBK / 8 + kBfThreads - 1) / kBfThreads;
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][BM][kBfStride];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN][kBfStride];
+  constexpr int ROWS = BM + BN;                 // tile rows per stage (A rows, then Xt rows)
+  constexpr int NLOADS = ROWS / 16;             // 1 KB wave loads per stage
+  constexpr int LMIN = NLOADS / 8;              // loads per step of the waves that issue fewest
+  __shared__ __attribute__((aligned(1024))) uint16_t tiles[kBfStages][ROWS * kBfBK];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave & 1, wn = wave >> 1;
@@ -143,30 +158,28 @@ __global__ __launch_bounds__(kBfThreads) void gemm_bf16_kernel(const uint16_t* _
   const int m0 = mt * BM;
   const int kbeg = split * kchunk;
   const int kend = min(K, kbeg + kchunk);
+  const int nsteps = kend > kbeg ? (kend - kbeg) / kBfBK : 0;
 
-  u16x8 areg, breg[B_VECS];
-  auto load_tile = [&](int k0) {
-    {
-      const int r = tid >> 2, kv = tid & 3;
-      const int gr = m0 + r, gk = k0 + kv * 8;
-      areg = (u16x8)0;
-      if (gr < M && gk < kend) areg = *reinterpret_cast<const u16x8*>(A + (int64_t)gr * lda + gk);
-    }
+  // wave load j covers tile rows 16 j .. 16 j + 15; lane i fills the i-th
+  // 16-byte slot: row 16 j + i / 4, stored chunk i % 4, logical chunk
+  // bf_swz(row, i % 4)
+  auto issue = [&](int st, int k0) {
 #pragma unroll
-    for (int v = 0; v < B_VECS; ++v) {
-      const int idx = tid + kBfThreads * v;
-      const int n = idx >> 2, kv = idx & 3;
-      const int gk = k0 + kv * 8;
-      breg[v] = (u16x8)0;
-      if (n < BN && n < N && gk < kend) breg[v] = *reinterpret_cast<const u16x8*>(Xt + (int64_t)n * ldx + gk);
-    }
-  };
-  auto store_tile = [&](int buf) {
-    *reinterpret_cast<u16x8*>(&As[buf][tid >> 2][(tid & 3) * 8]) = areg;
-#pragma unroll
-    for (int v = 0; v < B_VECS; ++v) {
-      const int idx = tid + kBfThreads * v;
-      if ((idx >> 2) < BN) *reinterpret_cast<u16x8*>(&Bs[buf][idx >> 2][(idx & 3) * 8]) = breg[v];
+    for (int u = 0; u < (NLOADS + 7) / 8; ++u) {
+      const int j = wave + 8 * u;
+      if (j < NLOADS) {
+        const int row = 16 * j + (lane >> 2);
+        const int ch = bf_swz(row, lane & 3);
+        const uint16_t* src;
+        if (row < BM) {
+          const int gr = min(m0 + row, M - 1);
+          src = A + (int64_t)gr * lda + k0 + ch * 8;
+        } else {
+          const int gn = min(row - BM, N - 1);
+          src = Xt + (int64_t)gn * ldx + k0 + ch * 8;
+        }
+        __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)&tiles[st][16 * j * kBfBK], 16, 0, 0);
+      }
     }
   };
 
@@ -175,34 +188,43 @@ __global__ __launch_bounds__(kBfThreads) void gemm_bf16_kernel(const uint16_t* _
   for (int rf = 0; rf < 4; ++rf)
 #pragma unroll
     for (int cf = 0; cf < NF; ++cf) acc[rf][cf] = (floatx4)0.0f;
-  const int arow = wm * 64 + (lane & 15);
-  const int bcol = wn * 16 * NF + (lane & 15);
-  const int kq = (lane >> 4) * 8;
-  if (kbeg < kend) {
-    load_tile(kbeg);
-    store_tile(0);
-    __syncthreads();
-    int buf = 0;
-    for (int k0 = kbeg; k0 < kend; k0 += kBfBK) {
-      const bool more = k0 + kBfBK < kend;
-      if (more) load_tile(k0 + kBfBK);
-      __builtin_amdgcn_s_setprio(1);
-      bf16x8 a[4];
+  const int kc = lane >> 4;  // this lane's 8-element chunk of the 32-wide step
+  auto compute = [&](int st) {
+    const uint16_t* T = tiles[st];
+    __builtin_amdgcn_s_setprio(1);
+    bf16x8 a[4];
+#pragma unroll
+    for (int rf = 0; rf < 4; ++rf) {
+      const int row = wm * 64 + rf * 16 + (lane & 15);
+      a[rf] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&T[row * kBfBK + bf_swz(row, kc) * 8]));
+    }
+#pragma unroll
+    for (int cf = 0; cf < NF; ++cf) {
+      const int row = BM + wn * 16 * NF + cf * 16 + (lane & 15);
+      const bf16x8 b =
+          __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&T[row * kBfBK + bf_swz(row, kc) * 8]));
 #pragma unroll
       for (int rf = 0; rf < 4; ++rf)
-        a[rf] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&As[buf][arow + rf * 16][kq]));
-#pragma unroll
-      for (int cf = 0; cf < NF; ++cf) {
-        const bf16x8 b = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&Bs[buf][bcol + cf * 16][kq]));
-#pragma unroll
-        for (int rf = 0; rf < 4; ++rf)
-          acc[rf][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rf], b, acc[rf][cf], 0, 0, 0);
-      }
-      __builtin_amdgcn_s_setprio(0);
-      if (more) store_tile(buf ^ 1);
-      __syncthreads();
-      buf ^= 1;
+        acc[rf][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rf], b, acc[rf][cf], 0, 0, 0);
     }
+    __builtin_amdgcn_s_setprio(0);
+  };
+
+  if (nsteps > 0) issue(0, kbeg);
+  if (nsteps > 1) issue(1, kbeg + kBfBK);
+  int st = 0;
+  for (int i = 0; i < nsteps; ++i) {
+    // this wave's loads of step i are done once at most those of step i + 1 are pending
+    if (i + 1 < nsteps) __builtin_amdgcn_s_waitcnt(vmcnt_imm(LMIN));
+    else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    // every wave's step-i tiles are in, and every wave has consumed its
+    // step i - 1 operands, so that stage may be refilled.  A plain barrier
+    // (a compiler memory barrier, no fence): a fence would also wait for the
+    // loads of step i + 1 still in flight.
+    asm volatile("s_barrier" ::: "memory");
+    if (i + 2 < nsteps) issue(st == 0 ? 2 : st - 1, kbeg + (i + 2) * kBfBK);
+    compute(st);
+    st = (st == kBfStages - 1) ? 0 : st + 1;
   }
   float* Cs = C + (int64_t)split * cslice;
 #pragma unroll
@@ -213,7 +235,7 @@ __global__ __launch_bounds__(kBfThreads) void gemm_bf16_kernel(const uint16_t* _
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm * 64 + rf * 16 + 4 * (lane >> 4) + r;
-        if (row < M && col < nst) Cs[(int64_t)row * ldc + col] = acc[rf][cf][r];
+        if (row < M && col < nst) Cs[(int64_t)row * ldc + col] = (col < N) ? acc[rf][cf][r] : 0.0f;
       }
     }
 }
@@ -254,6 +276,7 @@ hipError_t launch_gemm_bf16(const uint16_t* A, int64_t lda, const uint16_t* Xt, 
                             float* Y, int64_t ldy, int nst, float* P, hipStream_t s, hipEvent_t ev0,
                             hipEvent_t ev1) {
   if (M <= 0 || nst <= 0) return hipSuccess;
+  if (K % kBfBK != 0 || lda % 8 != 0 || ldx % 8 != 0 || N < 1) return hipErrorInvalidValue;
   int mtiles, nsplit, kchunk;
   plan_gemm_bf16(M, K, &mtiles, &nsplit, &kchunk);
   const int grid = mtiles * nsplit;

@@ -52,7 +52,7 @@ hipError_t launch_cvt_bf16(const float* A, int64_t lda, int64_t m, int64_t n, ui
 hipError_t launch_cvt_bf16_t(const float* X, int64_t ldx, int64_t K, int64_t N, uint16_t* Xt, int64_t ldt,
                              hipStream_t s);
 // Y (M x nst, ldy) = A Xt^T with A (M x K bf16, lda) and Xt (N x K bf16,
-// ldx), both k-contiguous, K a multiple of 8 with zero padding, lda and ldx
+// ldx), both k-contiguous, K a multiple of 32 with zero padding, lda and ldx
 // multiples of 8.  P: split-K partials (gemm_bf16_partial_elems).
 hipError_t launch_gemm_bf16(const uint16_t* A, int64_t lda, const uint16_t* Xt, int64_t ldx, int M, int N, int K,
                             float* Y, int64_t ldy, int nst, float* P, hipStream_t s, hipEvent_t ev0,

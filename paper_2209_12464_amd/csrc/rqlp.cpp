@@ -132,7 +132,8 @@ struct Layout {
 };
 
 // leading dimension of a k-contiguous bfloat16 operand of reduction length K
-int64_t bf16_ld(int64_t K) { return round_up(K, 8); }
+// (the product kernel takes whole 32-wide reduction steps; padding is zero)
+int64_t bf16_ld(int64_t K) { return round_up(K, 32); }
 
 template <typename T>
 Layout layout(int64_t m, int64_t n, int d, bool sparse, int64_t nnz, bool bf16 = false) {
