@@ -38,6 +38,8 @@ WORKLOADS = {
     "dense8000_q0": dict(kind="dense", m=8000, n=8000, k=200, p=10, q=0, dtype="f32", spectrum="gapped"),
     "small_fp64": dict(kind="dense", m=1000, n=800, k=20, p=5, q=0, dtype="f64", spectrum="geometric"),
     "csr100k": dict(kind="csr", m=100000, n=50000, k=100, p=10, q=1, dtype="f32", density=1e-3),
+    # a batch of 64 uneven requests of the serving stream (float32, q = 1)
+    "batch64": dict(kind="batch", count=64, q=1, dtype="f32"),
     # bfloat16 products with float32 accumulation, float64 Gram and Cholesky
     "bf16_20000x15000": dict(kind="dense", m=20000, n=15000, k=500, p=20, q=1, dtype="f32",
                              spectrum="polynomial", bf16=True),
@@ -153,6 +155,84 @@ def compare_with_fp32(rqlp, ctx, A, k, p, q, args, out_bf16, ws_fp32_steps):
     del ws
     return {"fp32_ms_per_step": ms32, "e_bf16": e_bf, "e_fp32": e_32, "delta_bf16_vs_fp32": delta,
             "d": d}
+
+
+def run_batch_bench(args, w, rqlp, torch, dev):
+    """One step = one rqlp_decompose_batched call over the whole batch, with
+    graph replay on (the batch repeats).  Also timed: the same batch without
+    graphs, and the problems decomposed one after another."""
+    import workloads
+    reqs = workloads.serving_requests(w["count"], args.seed)
+    hostAs = [workloads.request_matrix(r, np.float32) for r in reqs]
+    As = [torch.from_numpy(a).to(dev) for a in hostAs]
+    params = [(r["k"], r["p"], w["q"], r["seed"]) for r in reqs]
+    flops = sum(f_alg(r["m"], r["n"], r["k"], r["p"], w["q"]) for r in reqs)
+    ctx = rqlp.Context(0)
+    shapes = [(r["m"], r["n"], r["k"], r["p"], w["q"]) for r in reqs]
+    ws = rqlp.alloc_workspace(rqlp.workspace_size_batched(shapes, torch.float32), dev)
+    outs = rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws)
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    eager_ms = timed(lambda: rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs), args.steps)
+    ctx.set_graphs(True)
+    ms = timed(lambda: rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs), args.steps)
+    ctx.set_graphs(False)
+    solo_ws = rqlp.alloc_workspace(max(rqlp.workspace_size(r["m"], r["n"], r["k"], r["p"], w["q"], torch.float32)
+                                       for r in reqs), dev)
+
+    def sequential():
+        for A, (k, p, q, seed), o in zip(As, params, outs):
+            rqlp.decompose(A, k, p, q, seed=seed, ctx=ctx, workspace=solo_ws, out=o)
+    seq_ms = timed(sequential, max(1, args.steps // 4))
+    # products: event-timed in a sequential pass (launches of a batch are not timed)
+    ctx.set_timing(True, classes=["gemm_nn", "gemm_tn"])
+    sequential()
+    torch.cuda.synchronize()
+    g_ms = sum(ctx.timing(c)[0] for c in ("gemm_nn", "gemm_tn"))
+    ctx.set_timing(False)
+    g_flops = sum(2.0 * r["m"] * r["n"] * (r["k"] + r["p"]) * (2 * w["q"] + 2) for r in reqs)
+    achieved = g_flops / (g_ms * 1e-3) / 1e12
+    res = {
+        "metric": f"RU-QLP GFLOP/s (batch of {w['count']} uneven requests, FP32, q={w['q']})",
+        "value": flops / (ms * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "count": w["count"], "q": w["q"], "flops_per_step": flops,
+                   "m_range": [512, 8192], "n_range": [256, 4096], "k_range": [8, 256], "p": 10},
+        "batched_eager_ms": eager_ms, "sequential_ms": seq_ms,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32_mfma_tflops"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK["f32_mfma_tflops"], "traffic": None,
+                     "kernel": "gemm_nn+gemm_tn (sequential pass)"},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        except Exception:  # pragma: no cover
+            threads = os.cpu_count() or 1
+        done, f_done, t_done = 0, 0.0, 0.0
+        for r, a in zip(reqs, hostAs):  # the batch's problems in order, about 15 s
+            t0 = time.perf_counter()
+            oracle.ruqlp(a.astype(np.float64), r["k"], r["p"], w["q"], r["seed"], omega_dtype="f32")
+            t_done += time.perf_counter() - t0
+            f_done += f_alg(r["m"], r["n"], r["k"], r["p"], w["q"])
+            done += 1
+            if t_done > 15.0:
+                break
+        res["cpu_baseline"] = {"value": f_done / t_done / 1e9, "unit": "GFLOP/s", "cores": int(threads),
+                               "kind": "oracle", "sample": f"the first {done} problems of the batch",
+                               "seconds": t_done}
+    print(json.dumps(res), flush=True)
 
 
 def cpu_baseline(w, A_host, seed, flops):
@@ -303,6 +383,9 @@ def main():
 
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
+    if w["kind"] == "batch":
+        run_batch_bench(args, w, rqlp, torch, dev)
+        return
     host = make_inputs(w, args.seed)
     ctx = rqlp.Context(0)
     k, p, q = w["k"], w["p"], w["q"]

@@ -184,6 +184,43 @@ rqlp_status rqlp_csr_transpose(rqlp_ctx* ctx, const int32_t* rowptr, const int32
                                rqlp_precision prec, int32_t* rowptr_t, int32_t* colidx_t,
                                void* vals_t, void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- Batches of dense decompositions ---- */
+
+/* One decomposition of a batch: A (m x n, lda >= n, device), k, p, q and
+ * seed as for rqlp_decompose, outputs Q (m x d), L (d x d), V (n x d) with
+ * leading dimension d = k + p. */
+typedef struct {
+  const void* A;
+  int64_t m, n, lda;
+  int k, p, q;
+  uint64_t seed;
+  void* Q;
+  void* L;
+  void* V;
+} rqlp_problem;
+
+/* Workspace bytes of rqlp_decompose_batched (the sum of the problems' own
+ * workspaces); 0 when a problem is invalid. */
+size_t rqlp_workspace_size_batched(int count, const rqlp_problem* problems, rqlp_precision prec);
+
+/* Batched RU-QLP (the compute side of serving many uneven requests): every
+ * problem is decomposed as by rqlp_decompose, with the same precision
+ * (RQLP_FP64, RQLP_FP32 or RQLP_BF16_REFINED; dense A only) and its own
+ * slice of the workspace.  The problems' launch sequences are spread over
+ * four internal streams forked from and joined back into `stream`, so that
+ * the single-workgroup factorizations and small products of different
+ * problems overlap on the device.  Each result is bitwise the result of
+ * rqlp_decompose on the same problem.  With rqlp_set_graphs enabled, a batch
+ * submitted twice in a row with identical descriptors and workspace is
+ * captured into a HIP graph on its second submission and replayed on later
+ * ones.  The info record covers the whole batch.  `problems` is read
+ * during the call only. */
+rqlp_status rqlp_decompose_batched(rqlp_ctx* ctx, int count, const rqlp_problem* problems,
+                                   rqlp_precision prec, void* workspace, size_t ws_bytes, void* stream);
+
+/* Turn graph capture and replay of repeated batches on (1) or off (0). */
+rqlp_status rqlp_set_graphs(rqlp_ctx* ctx, int enabled);
+
 /* ---- Timing hooks (benchmarking) ---- */
 
 /* Kernel classes whose launches can be timed with HIP events recorded on

@@ -31,6 +31,17 @@ struct rqlp_ctx {
   std::vector<hipEvent_t> pool;
   double total_ms[RQLP_KT_COUNT] = {0};
   int64_t launches[RQLP_KT_COUNT] = {0};
+  // batches: decompositions spread over lanes (streams at the default
+  // priority), forked from and joined back into the caller's stream
+  static constexpr int kLanes = 4;
+  hipStream_t lanes[kLanes] = {};
+  hipStream_t cap = nullptr;  // origin stream of graph captures
+  hipEvent_t fork = nullptr, join[kLanes] = {};
+  bool graphs = false;        // capture a repeated batch once, then replay it
+  bool reset_info = true;     // off inside a batch (reset once for the whole batch)
+  struct GraphEntry { std::vector<uint8_t> key; hipGraphExec_t exec; };
+  std::vector<GraphEntry> graph_cache;
+  std::vector<uint8_t> last_key;  // the last batch run eagerly
 };
 
 namespace {
@@ -294,7 +305,7 @@ rqlp_status run_method(rqlp_ctx* c, char* base, const Layout& Lo, int64_t m, int
   b.xf = (double*)(base + Lo.xf);
   b.esq = (double*)(base + Lo.esq);
   rqlp_status st;
-  HIP_TRY(launch_info_reset(c->info, s));
+  if (c->reset_info) HIP_TRY(launch_info_reset(c->info, s));
   // Omega (n x d, ld dp), then Y = A Omega and Q = orth(Y)
   HIP_TRY(launch_gaussian<T>(seed, kSketchKey1, n, d, om, dp, s));
   if ((st = mulA(om, yb)) != RQLP_OK) return st;
@@ -404,6 +415,82 @@ size_t orth_ws_bytes(int64_t rows, int d, rqlp_precision prec) {
   return off + 256;
 }
 
+
+// ---- batches ---------------------------------------------------------------
+
+size_t problem_ws_bytes(const rqlp_problem& P, rqlp_precision prec) {
+  const int d = P.k + P.p;
+  if (prec == RQLP_FP64) return align256(layout<double>(P.m, P.n, d, false, 0).total);
+  return align256(layout<float>(P.m, P.n, d, false, 0, prec == RQLP_BF16_REFINED).total);
+}
+
+rqlp_status check_problem(const rqlp_problem& P, rqlp_precision prec) {
+  if (!P.A || !P.Q || !P.L || !P.V || P.lda < P.n) return RQLP_ERR_INVALID_ARG;
+  return check_common(P.m, P.n, P.k, P.p, P.q, prec);
+}
+
+rqlp_status make_lanes(rqlp_ctx* c) {
+  if (c->fork) return RQLP_OK;
+  for (int l = 0; l < rqlp_ctx::kLanes; ++l) {
+    HIP_TRY(hipStreamCreateWithFlags(&c->lanes[l], hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&c->join[l], hipEventDisableTiming));
+  }
+  HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+  return RQLP_OK;
+}
+
+// Enqueue the batch on `origin`: reset the info record, fork to the lanes,
+// problem i on lane i % kLanes with its own workspace slice, join back.
+rqlp_status run_batch(rqlp_ctx* c, int count, const rqlp_problem* probs, rqlp_precision prec, char* base,
+                      hipStream_t origin) {
+  HIP_TRY(launch_info_reset(c->info, origin));
+  HIP_TRY(hipEventRecord(c->fork, origin));
+  const int nl = std::min(count, (int)rqlp_ctx::kLanes);
+  for (int l = 0; l < nl; ++l) HIP_TRY(hipStreamWaitEvent(c->lanes[l], c->fork, 0));
+  const uint32_t timing = c->timing;
+  c->timing = 0;
+  c->reset_info = false;
+  rqlp_status st = RQLP_OK;
+  size_t off = 0;
+  for (int i = 0; i < count && st == RQLP_OK; ++i) {
+    const rqlp_problem& P = probs[i];
+    const size_t need = problem_ws_bytes(P, prec);
+    hipStream_t s = c->lanes[i % rqlp_ctx::kLanes];
+    char* ws = base + off;
+    off += need;
+    if (prec == RQLP_FP64)
+      st = decompose_dense<double>(c, (const double*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (double*)P.Q,
+                                   (double*)P.L, (double*)P.V, ws, need, s);
+    else if (prec == RQLP_BF16_REFINED)
+      st = decompose_dense_bf16(c, (const float*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (float*)P.Q,
+                                (float*)P.L, (float*)P.V, ws, need, s);
+    else
+      st = decompose_dense<float>(c, (const float*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (float*)P.Q,
+                                  (float*)P.L, (float*)P.V, ws, need, s);
+  }
+  c->reset_info = true;
+  c->timing = timing;
+  for (int l = 0; l < nl; ++l) {
+    HIP_TRY(hipEventRecord(c->join[l], c->lanes[l]));
+    HIP_TRY(hipStreamWaitEvent(origin, c->join[l], 0));
+  }
+  return st;
+}
+
+std::vector<uint8_t> batch_key(int count, const rqlp_problem* probs, rqlp_precision prec, const void* ws,
+                               size_t ws_bytes) {
+  std::vector<uint8_t> key(sizeof(int) * 2 + sizeof(void*) + sizeof(size_t) + sizeof(rqlp_problem) * count);
+  uint8_t* k = key.data();
+  const int pr = (int)prec;
+  std::memcpy(k, &count, sizeof(int)); k += sizeof(int);
+  std::memcpy(k, &pr, sizeof(int)); k += sizeof(int);
+  std::memcpy(k, &ws, sizeof(void*)); k += sizeof(void*);
+  std::memcpy(k, &ws_bytes, sizeof(size_t)); k += sizeof(size_t);
+  std::memcpy(k, probs, sizeof(rqlp_problem) * count);
+  return key;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -438,6 +525,13 @@ rqlp_status rqlp_destroy(rqlp_ctx* c) {
   hipDeviceSynchronize();
   resolve_timing(c);
   for (hipEvent_t e : c->pool) hipEventDestroy(e);
+  for (auto& e : c->graph_cache) hipGraphExecDestroy(e.exec);
+  for (int l = 0; l < rqlp_ctx::kLanes; ++l) {
+    if (c->lanes[l]) hipStreamDestroy(c->lanes[l]);
+    if (c->join[l]) hipEventDestroy(c->join[l]);
+  }
+  if (c->cap) hipStreamDestroy(c->cap);
+  if (c->fork) hipEventDestroy(c->fork);
   if (c->ws_own) hipFree(c->ws_own);
   if (c->info) hipFree(c->info);
   delete c;
@@ -474,6 +568,74 @@ rqlp_status rqlp_decompose(rqlp_ctx* c, const void* A, int64_t m, int64_t n, int
                                 ws_bytes, s);
   return decompose_dense<float>(c, (const float*)A, m, n, lda, k, p, q, seed, (float*)Q, (float*)L, (float*)V,
                                 ws, ws_bytes, s);
+}
+
+size_t rqlp_workspace_size_batched(int count, const rqlp_problem* probs, rqlp_precision prec) {
+  if (count < 1 || !probs || !valid_prec(prec)) return 0;
+  size_t total = 0;
+  for (int i = 0; i < count; ++i) {
+    if (check_problem(probs[i], prec) != RQLP_OK) return 0;
+    total += problem_ws_bytes(probs[i], prec);
+  }
+  return total + 256;
+}
+
+rqlp_status rqlp_decompose_batched(rqlp_ctx* c, int count, const rqlp_problem* probs, rqlp_precision prec,
+                                   void* ws, size_t ws_bytes, void* stream) {
+  if (!c || count < 1 || !probs || !valid_prec(prec)) return RQLP_ERR_INVALID_ARG;
+  size_t need = 0;
+  for (int i = 0; i < count; ++i) {
+    rqlp_status st = check_problem(probs[i], prec);
+    if (st != RQLP_OK) return st;
+    need += problem_ws_bytes(probs[i], prec);
+  }
+  need += 256;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  rqlp_status st = make_lanes(c);
+  if (st != RQLP_OK) return st;
+  char* base = nullptr;
+  if ((st = get_workspace(c, ws, ws_bytes, need, &base)) != RQLP_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (!c->graphs) return run_batch(c, count, probs, prec, base, s);
+  // graphs: a batch seen for the second time in a row (same problems,
+  // buffers and workspace) is captured once and replayed from then on
+  std::vector<uint8_t> key = batch_key(count, probs, prec, base, need);
+  for (auto& e : c->graph_cache)
+    if (e.key == key) {
+      HIP_TRY(hipGraphLaunch(e.exec, s));
+      return RQLP_OK;
+    }
+  if (key != c->last_key) {
+    c->last_key = key;
+    return run_batch(c, count, probs, prec, base, s);
+  }
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  st = run_batch(c, count, probs, prec, base, c->cap);
+  const hipError_t e_end = hipStreamEndCapture(c->cap, &g);
+  if (st != RQLP_OK) {
+    if (g) hipGraphDestroy(g);
+    return st;
+  }
+  if (e_end != hipSuccess || !g) return RQLP_ERR_HIP;
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e_inst = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e_inst != hipSuccess) return RQLP_ERR_HIP;
+  if (c->graph_cache.size() >= 8) {
+    hipGraphExecDestroy(c->graph_cache.front().exec);
+    c->graph_cache.erase(c->graph_cache.begin());
+  }
+  c->graph_cache.push_back({key, exec});
+  HIP_TRY(hipGraphLaunch(exec, s));
+  return RQLP_OK;
+}
+
+rqlp_status rqlp_set_graphs(rqlp_ctx* c, int enabled) {
+  if (!c) return RQLP_ERR_INVALID_ARG;
+  c->graphs = enabled != 0;
+  c->last_key.clear();
+  return RQLP_OK;
 }
 
 rqlp_status rqlp_decompose_csr(rqlp_ctx* c, const int32_t* rowptr, const int32_t* colidx, const void* vals,

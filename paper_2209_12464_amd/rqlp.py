@@ -32,6 +32,13 @@ class Info(ctypes.Structure):
                 ("breakdown_pass", ctypes.c_int32), ("nonfinite", ctypes.c_int32)]
 
 
+class Problem(ctypes.Structure):
+    """rqlp_problem: one decomposition of a batch."""
+    _fields_ = [("A", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
+                ("k", ctypes.c_int), ("p", ctypes.c_int), ("q", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("Q", ctypes.c_void_p), ("L", ctypes.c_void_p), ("V", ctypes.c_void_p)]
+
+
 _LIB = None
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -67,6 +74,9 @@ def _lib():
             "rqlp_csr_transpose_workspace_size": (_SZ, [_I64, _I64, _I64]),
             "rqlp_csr_transpose": (_INT, [_P, _P, _P, _P, _I64, _I64, _I64, _INT, _P, _P, _P, _P,
                                           _SZ, _P]),
+            "rqlp_workspace_size_batched": (_SZ, [_INT, ctypes.POINTER(Problem), _INT]),
+            "rqlp_decompose_batched": (_INT, [_P, _INT, ctypes.POINTER(Problem), _INT, _P, _SZ, _P]),
+            "rqlp_set_graphs": (_INT, [_P, _INT]),
             "rqlp_set_timing": (_INT, [_P, _INT]),
             "rqlp_set_timing_mask": (_INT, [_P, ctypes.c_uint32]),
             "rqlp_get_timing": (_INT, [_P, _INT, ctypes.POINTER(ctypes.c_double),
@@ -86,7 +96,8 @@ def exported_symbols():
             "rqlp_decompose", "rqlp_decompose_csr", "rqlp_get_info", "rqlp_status_string",
             "rqlp_gaussian", "rqlp_gemm_workspace_size", "rqlp_gemm", "rqlp_orth_workspace_size",
             "rqlp_orth", "rqlp_spmm", "rqlp_csr_transpose_workspace_size", "rqlp_csr_transpose",
-            "rqlp_set_timing", "rqlp_set_timing_mask", "rqlp_get_timing"]
+            "rqlp_set_timing", "rqlp_set_timing_mask", "rqlp_get_timing",
+            "rqlp_workspace_size_batched", "rqlp_decompose_batched", "rqlp_set_graphs"]
 
 
 def _check(status, where):
@@ -143,6 +154,10 @@ class Context:
         _check(_lib().rqlp_get_info(self._h, ctypes.byref(out)), "rqlp_get_info")
         return dict(status=out.status, completed_cols=out.completed_cols,
                     breakdown_pass=out.breakdown_pass, nonfinite=out.nonfinite)
+
+    def set_graphs(self, enabled):
+        """Capture a batch submitted twice in a row into a HIP graph and replay it."""
+        _check(_lib().rqlp_set_graphs(self._h, 1 if enabled else 0), "rqlp_set_graphs")
 
     def set_timing(self, enabled, classes=None):
         """Event timing of every kernel class, or only of `classes` (names
@@ -211,6 +226,50 @@ def decompose(A, k, p, q=0, seed=0, ctx=None, workspace=None, out=None, bf16=Fal
                                  _ptr(Q), _ptr(L), _ptr(V), ws_ptr, ws_bytes, _stream(A.device)),
            "rqlp_decompose")
     return Q, L, V
+
+
+def _problems(As, params, outs):
+    arr = (Problem * len(As))()
+    for i, (A, (k, p, q, seed), (Q, L, V)) in enumerate(zip(As, params, outs)):
+        if A.dim() != 2 or A.stride(1) != 1:
+            raise ValueError("every A must be a 2-D row-major tensor")
+        arr[i] = Problem(_ptr(A), A.shape[0], A.shape[1], A.stride(0), k, p, q, seed, _ptr(Q), _ptr(L), _ptr(V))
+    return arr
+
+
+def workspace_size_batched(shapes, dtype, bf16=False):
+    """Workspace bytes for problems given as (m, n, k, p, q) tuples."""
+    arr = (Problem * len(shapes))()
+    for i, (m, n, k, p, q) in enumerate(shapes):
+        arr[i] = Problem(1, m, n, n, k, p, q, 0, 1, 1, 1)
+    return int(_lib().rqlp_workspace_size_batched(len(shapes), arr, _prec(dtype, bf16)))
+
+
+def decompose_batched(As, params, ctx=None, workspace=None, outs=None, bf16=False):
+    """Batched RU-QLP: As is a list of dense device matrices (one dtype),
+    params a list of (k, p, q, seed).  Returns a list of (Q, L, V), each
+    bitwise what decompose() gives for that problem; enqueued on the
+    current stream."""
+    if not As:
+        return []
+    dev = As[0].device
+    ctx = ctx or default_context(dev.index or 0)
+    dtype = As[0].dtype
+    if outs is None:
+        outs = []
+        for A, (k, p, q, seed) in zip(As, params):
+            m, n = A.shape
+            d = k + p
+            outs.append((torch.empty((m, d), dtype=dtype, device=dev), torch.empty((d, d), dtype=dtype, device=dev),
+                         torch.empty((n, d), dtype=dtype, device=dev)))
+    arr = _problems(As, params, outs)
+    if workspace is None:
+        ws_bytes = int(_lib().rqlp_workspace_size_batched(len(As), arr, _prec(dtype, bf16)))
+        workspace = alloc_workspace(ws_bytes, dev) if ws_bytes else None
+    ws_bytes = workspace.numel() if workspace is not None else 0
+    _check(_lib().rqlp_decompose_batched(ctx.handle, len(As), arr, _prec(dtype, bf16), _ptr(workspace), ws_bytes,
+                                         _stream(dev)), "rqlp_decompose_batched")
+    return outs
 
 
 def decompose_csr(rowptr, colidx, vals, m, n, k, p, q=0, seed=0, ctx=None, workspace=None, out=None):

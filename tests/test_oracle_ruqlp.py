@@ -144,3 +144,18 @@ def test_fast_orth_generator_has_exact_spectrum(m, n, seed):
     assert np.abs(A).max() <= 2.0 * s.sum() / np.sqrt(m * n) * (1 + 1e-12)
     with pytest.raises(ValueError):
         workloads.dense_fast_orth(n - 1 if n > 1 else 0, n, s, seed)
+
+
+def test_serving_request_generator():
+    """Request shapes follow their ranges; a request's matrix has exactly
+    the truncated geometric spectrum, for tall and wide shapes."""
+    reqs = workloads.serving_requests(50, 3)
+    for r in reqs:
+        assert 512 <= r["m"] <= 8192 and 256 <= r["n"] <= 4096 and r["p"] == 10
+        assert 8 <= r["k"] <= min(256, min(r["m"], r["n"]) - 10) and 0.8 <= r["rho"] <= 0.99
+    for r in workloads.serving_requests(4, 7, m_range=(30, 120), n_range=(30, 120), kmax=12):
+        A = workloads.request_matrix(r, np.float64)
+        assert A.shape == (r["m"], r["n"])
+        i = np.arange(1, min(A.shape) + 1)
+        want = np.where(i <= np.ceil(np.log(1e-8) / np.log(r["rho"])), r["rho"] ** i, 0.0)
+        assert np.allclose(np.linalg.svd(A, compute_uv=False), want, rtol=0, atol=1e-13)

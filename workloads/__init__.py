@@ -168,6 +168,34 @@ def cfg_poly_bf16(seed=4, m=20000, n=15000):
     return dict(A=A, sigma=sigma, k=500, p=20, q=1, prec="bf16")
 
 
+def serving_requests(count, seed, m_range=(512, 8192), n_range=(256, 4096), kmax=256, p=10):
+    """Request shapes of the serving stream: m, n uniform in their ranges,
+    k uniform in [8, min(kmax, min(m, n) - p)], p fixed, a geometric decay
+    rate rho uniform in [0.8, 0.99] and a matrix seed per request."""
+    rng = _rng(seed)
+    out = []
+    for _ in range(count):
+        m = int(rng.integers(m_range[0], m_range[1] + 1))
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        k = int(rng.integers(8, min(kmax, min(m, n) - p) + 1))
+        rho = float(rng.uniform(0.8, 0.99))
+        out.append(dict(m=m, n=n, k=k, p=p, rho=rho, seed=int(rng.integers(1, 2 ** 31))))
+    return out
+
+
+def request_matrix(req, dtype=np.float32):
+    """A request's matrix: sigma_i = rho^i up to the rank where it falls
+    below 1e-8, zero after, with structured orthogonal factors."""
+    m, n, rho = req["m"], req["n"], req["rho"]
+    r = min(m, n)
+    i = np.arange(1, r + 1, dtype=np.float64)
+    sig = rho ** i
+    sig[i > np.ceil(np.log(1e-8) / np.log(rho))] = 0.0
+    if m >= n:
+        return dense_fast_orth(m, n, sig, req["seed"], dtype)
+    return np.ascontiguousarray(dense_fast_orth(n, m, sig, req["seed"], dtype).T)
+
+
 def cfg_sparse(seed=3, m=100000, n=50000, density=1e-3):
     """CSR 100000 x 50000, 0.1 % density, N(0,1) FP32, k=100, p=10, q=1."""
     nnz = int(round(density * m * n))
