@@ -40,6 +40,8 @@ WORKLOADS = {
     "csr100k": dict(kind="csr", m=100000, n=50000, k=100, p=10, q=1, dtype="f32", density=1e-3),
     # a batch of 64 uneven requests of the serving stream (float32, q = 1)
     "batch64": dict(kind="batch", count=64, q=1, dtype="f32"),
+    # the serving stream: 4096 Poisson-arrival requests over 64 distinct matrices
+    "serve4096": dict(kind="serve", count=4096, pool=64, q=1, dtype="f32", slots=8, budget_gb=8.0),
     # bfloat16 products with float32 accumulation, float64 Gram and Cholesky
     "bf16_20000x15000": dict(kind="dense", m=20000, n=15000, k=500, p=20, q=1, dtype="f32",
                              spectrum="polynomial", bf16=True),
@@ -157,6 +159,119 @@ def compare_with_fp32(rqlp, ctx, A, k, p, q, args, out_bf16, ws_fp32_steps):
             "d": d}
 
 
+def run_serve_bench(args, w, rqlp, torch, dev):
+    """Serving stream: first all requests at once (saturated throughput),
+    then Poisson arrivals at 0.5, 0.8 and 0.95 of that rate, with p50 / p99
+    of completion - arrival.  Request i decomposes pool matrix i % pool with
+    its own seed and its own output buffers."""
+    import workloads
+    pool = workloads.serving_requests(w["pool"], args.seed)
+    As = [torch.from_numpy(workloads.request_matrix(r, np.float32)).to(dev) for r in pool]
+    n_req, q = w["count"], w["q"]
+    req = [(i % w["pool"], 1000 + i) for i in range(n_req)]
+    outs = []
+    for j, _ in req:
+        r = pool[j]
+        d = r["k"] + r["p"]
+        outs.append((torch.empty((r["m"], d), device=dev), torch.empty((d, d), device=dev),
+                     torch.empty((r["n"], d), device=dev)))
+    flops = sum(f_alg(pool[j]["m"], pool[j]["n"], pool[j]["k"], pool[j]["p"], q) for j, _ in req)
+    ctx = rqlp.Context(0)
+    srv = rqlp.Server(int(w["budget_gb"] * 2 ** 30), slots=w["slots"], ctx=ctx)
+
+    def run(arrivals):
+        """Submit request i at arrivals[i] (seconds from the start); return
+        (wall seconds, completion - arrival per request)."""
+        cnt = len(arrivals)
+        done_at = np.zeros(cnt)
+        tick = {}
+        i = ndone = 0
+        t0 = time.perf_counter()
+        while ndone < cnt:
+            now = time.perf_counter() - t0
+            while i < cnt and arrivals[i] <= now:
+                j, seed = req[i]
+                r = pool[j]
+                tick[srv.submit(As[j], r["k"], r["p"], q, seed, outs[i])] = i
+                i += 1
+            fin, _, _ = srv.poll()
+            if fin:
+                now = time.perf_counter() - t0
+                for t in fin:
+                    done_at[tick[t]] = now
+                ndone += len(fin)
+        return time.perf_counter() - t0, done_at - np.asarray(arrivals)
+
+    run(np.zeros(min(n_req, 256)))  # warm-up
+    torch.cuda.synchronize()
+    wall, lat = run(np.zeros(n_req))
+    sat_rps = n_req / wall
+    rng = np.random.default_rng(args.seed)
+    levels = []
+    for frac in (0.5, 0.8, 0.95):
+        lam = frac * sat_rps
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
+        arr -= arr[0]
+        wl, lt = run(arr)
+        levels.append({"load": frac, "offered_rps": lam, "achieved_rps": n_req / wl,
+                       "p50_ms": float(np.percentile(lt, 50) * 1e3), "p99_ms": float(np.percentile(lt, 99) * 1e3)})
+    srv.close()
+    roof = products_roofline(rqlp, ctx, As, pool, q, torch)
+    res = {
+        "metric": f"RU-QLP served GFLOP/s at saturation ({n_req} requests, FP32, q={q}); p50/p99 latency",
+        "value": flops / wall / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "requests": n_req, "distinct_matrices": w["pool"], "q": q,
+                   "slots": w["slots"], "hbm_budget_gb": w["budget_gb"], "m_range": [512, 8192],
+                   "n_range": [256, 4096], "k_range": [8, 256], "p": 10},
+        "saturated": {"requests_per_s": sat_rps, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                      "p99_ms": float(np.percentile(lat, 99) * 1e3)},
+        "latency_by_load": levels,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = oracle_on_problems(pool, [a.cpu().numpy() for a in As], q)
+    print(json.dumps(res), flush=True)
+
+
+def products_roofline(rqlp, ctx, As, reqs, q, torch):
+    """Products with A of the given problems, event-timed one problem after
+    another: achieved TFLOP/s against the float32 MFMA peak."""
+    ctx.set_timing(True, classes=["gemm_nn", "gemm_tn"])
+    for A, r in zip(As, reqs):
+        rqlp.decompose(A, r["k"], r["p"], q, seed=r["seed"], ctx=ctx)
+    torch.cuda.synchronize()
+    g_ms = sum(ctx.timing(c)[0] for c in ("gemm_nn", "gemm_tn"))
+    ctx.set_timing(False)
+    g_flops = sum(2.0 * r["m"] * r["n"] * (r["k"] + r["p"]) * (2 * q + 2) for r in reqs)
+    achieved = g_flops / (g_ms * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32_mfma_tflops"], "unit": "TFLOP/s",
+            "frac": achieved / PEAK["f32_mfma_tflops"], "traffic": None,
+            "kernel": "gemm_nn+gemm_tn (problems one by one)"}
+
+
+def oracle_on_problems(reqs, hostAs, q, budget_s=15.0):
+    """The float64 oracle on the problems in order until about budget_s."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    done, f_done, t_done = 0, 0.0, 0.0
+    for r, a in zip(reqs, hostAs):
+        t0 = time.perf_counter()
+        oracle.ruqlp(a.astype(np.float64), r["k"], r["p"], q, r["seed"], omega_dtype="f32")
+        t_done += time.perf_counter() - t0
+        f_done += f_alg(r["m"], r["n"], r["k"], r["p"], q)
+        done += 1
+        if t_done > budget_s:
+            break
+    return {"value": f_done / t_done / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"the first {done} distinct problems of the workload", "seconds": t_done}
+
+
 def run_batch_bench(args, w, rqlp, torch, dev):
     """One step = one rqlp_decompose_batched call over the whole batch, with
     graph replay on (the batch repeats).  Also timed: the same batch without
@@ -193,14 +308,8 @@ def run_batch_bench(args, w, rqlp, torch, dev):
         for A, (k, p, q, seed), o in zip(As, params, outs):
             rqlp.decompose(A, k, p, q, seed=seed, ctx=ctx, workspace=solo_ws, out=o)
     seq_ms = timed(sequential, max(1, args.steps // 4))
-    # products: event-timed in a sequential pass (launches of a batch are not timed)
-    ctx.set_timing(True, classes=["gemm_nn", "gemm_tn"])
-    sequential()
-    torch.cuda.synchronize()
-    g_ms = sum(ctx.timing(c)[0] for c in ("gemm_nn", "gemm_tn"))
-    ctx.set_timing(False)
-    g_flops = sum(2.0 * r["m"] * r["n"] * (r["k"] + r["p"]) * (2 * w["q"] + 2) for r in reqs)
-    achieved = g_flops / (g_ms * 1e-3) / 1e12
+    roof = products_roofline(rqlp, ctx, As, [dict(r, seed=s_) for r, (_, _, _, s_) in zip(reqs, params)], w["q"],
+                             torch)
     res = {
         "metric": f"RU-QLP GFLOP/s (batch of {w['count']} uneven requests, FP32, q={w['q']})",
         "value": flops / (ms * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -209,29 +318,10 @@ def run_batch_bench(args, w, rqlp, torch, dev):
         "config": {"workload": args.workload, "count": w["count"], "q": w["q"], "flops_per_step": flops,
                    "m_range": [512, 8192], "n_range": [256, 4096], "k_range": [8, 256], "p": 10},
         "batched_eager_ms": eager_ms, "sequential_ms": seq_ms,
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32_mfma_tflops"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["f32_mfma_tflops"], "traffic": None,
-                     "kernel": "gemm_nn+gemm_tn (sequential pass)"},
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        import oracle
-        try:
-            from threadpoolctl import threadpool_info
-            threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-        except Exception:  # pragma: no cover
-            threads = os.cpu_count() or 1
-        done, f_done, t_done = 0, 0.0, 0.0
-        for r, a in zip(reqs, hostAs):  # the batch's problems in order, about 15 s
-            t0 = time.perf_counter()
-            oracle.ruqlp(a.astype(np.float64), r["k"], r["p"], w["q"], r["seed"], omega_dtype="f32")
-            t_done += time.perf_counter() - t0
-            f_done += f_alg(r["m"], r["n"], r["k"], r["p"], w["q"])
-            done += 1
-            if t_done > 15.0:
-                break
-        res["cpu_baseline"] = {"value": f_done / t_done / 1e9, "unit": "GFLOP/s", "cores": int(threads),
-                               "kind": "oracle", "sample": f"the first {done} problems of the batch",
-                               "seconds": t_done}
+        res["cpu_baseline"] = oracle_on_problems(reqs, hostAs, w["q"])
     print(json.dumps(res), flush=True)
 
 
@@ -385,6 +475,9 @@ def main():
     dev = torch.device("cuda", 0)
     if w["kind"] == "batch":
         run_batch_bench(args, w, rqlp, torch, dev)
+        return
+    if w["kind"] == "serve":
+        run_serve_bench(args, w, rqlp, torch, dev)
         return
     host = make_inputs(w, args.seed)
     ctx = rqlp.Context(0)

@@ -221,6 +221,37 @@ rqlp_status rqlp_decompose_batched(rqlp_ctx* ctx, int count, const rqlp_problem*
 /* Turn graph capture and replay of repeated batches on (1) or off (0). */
 rqlp_status rqlp_set_graphs(rqlp_ctx* ctx, int enabled);
 
+/* ---- Serving: continuous batching of requests ---- */
+
+/* A server owns an HBM budget (one device allocation of hbm_budget bytes,
+ * sub-allocated first-fit for the requests' workspaces) and `slots`
+ * streams at the default priority.  Requests (rqlp_problem, caller-owned
+ * device buffers, precision fixed per server) are queued by submit; poll
+ * reports finished requests and admits queued ones in arrival order as soon
+ * as a slot is free and the head request's workspace fits, launching each on
+ * its slot's stream, so requests admitted while others run overlap with
+ * them on the device.  Each result is bitwise the rqlp_decompose result of
+ * the same request.  Single-threaded use; the context must outlive the
+ * server; its info record accumulates over everything the server runs. */
+typedef struct rqlp_server rqlp_server;
+
+rqlp_status rqlp_server_create(rqlp_server** server, rqlp_ctx* ctx, size_t hbm_budget, int slots,
+                               rqlp_precision prec);
+rqlp_status rqlp_server_destroy(rqlp_server* server);
+
+/* Workspace bytes a request takes from the budget (0 when invalid). */
+size_t rqlp_server_request_bytes(const rqlp_problem* request, rqlp_precision prec);
+
+/* Queue a request; *ticket identifies it in poll's reports.  A request
+ * whose workspace exceeds the whole budget is refused (RQLP_ERR_OUT_OF_MEMORY). */
+rqlp_status rqlp_server_submit(rqlp_server* server, const rqlp_problem* request, int64_t* ticket);
+
+/* Report up to max_done finished tickets (their outputs are complete on the
+ * device), then admit and launch queued requests.  inflight and queued (may
+ * be NULL) receive the counts after the call. */
+rqlp_status rqlp_server_poll(rqlp_server* server, int64_t* done, int max_done, int* ndone, int* inflight,
+                             int* queued);
+
 /* ---- Timing hooks (benchmarking) ---- */
 
 /* Kernel classes whose launches can be timed with HIP events recorded on

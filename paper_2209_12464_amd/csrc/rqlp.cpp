@@ -11,6 +11,8 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -851,6 +853,195 @@ rqlp_status rqlp_get_timing(rqlp_ctx* c, rqlp_kernel_class cls, double* total_ms
   resolve_timing(c);
   *total_ms = c->total_ms[cls];
   *launches = c->launches[cls];
+  return RQLP_OK;
+}
+
+}  // extern "C"
+
+// ---- serving -----------------------------------------------------------------
+// Continuous batching at request granularity: a request is admitted as soon
+// as a slot (a stream of its own) is free and its workspace fits into the
+// free part of the HBM budget; admitted requests run concurrently on their
+// slots' streams, so requests arriving while others are on the GPU overlap
+// with them.  Completion is observed with events by rqlp_server_poll.
+
+struct rqlp_server {
+  rqlp_ctx* ctx = nullptr;
+  rqlp_precision prec = RQLP_FP32;
+  char* pool = nullptr;
+  size_t budget = 0;
+  struct Slot {
+    hipStream_t s = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    int64_t ticket = -1;
+    size_t off = 0, size = 0;
+  };
+  std::vector<Slot> slots;
+  std::deque<std::pair<int64_t, rqlp_problem>> queue;
+  std::map<size_t, size_t> free_ranges;  // offset -> bytes, coalesced
+  int64_t next_ticket = 0;
+  int64_t inflight_bytes = 0;
+};
+
+namespace {
+
+bool pool_alloc(rqlp_server* sv, size_t bytes, size_t* off) {
+  for (auto it = sv->free_ranges.begin(); it != sv->free_ranges.end(); ++it) {
+    if (it->second >= bytes) {  // first fit
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t roff = it->first + bytes;
+      sv->free_ranges.erase(it);
+      if (rest) sv->free_ranges[roff] = rest;
+      return true;
+    }
+  }
+  return false;
+}
+
+void pool_free(rqlp_server* sv, size_t off, size_t bytes) {
+  auto it = sv->free_ranges.emplace(off, bytes).first;
+  auto nx = std::next(it);
+  if (nx != sv->free_ranges.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    sv->free_ranges.erase(nx);
+  }
+  if (it != sv->free_ranges.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      sv->free_ranges.erase(it);
+    }
+  }
+}
+
+rqlp_status launch_request(rqlp_server* sv, rqlp_server::Slot& sl, const rqlp_problem& P) {
+  rqlp_ctx* c = sv->ctx;
+  const uint32_t timing = c->timing;
+  c->timing = 0;
+  c->reset_info = false;
+  char* ws = sv->pool + sl.off;
+  rqlp_status st;
+  if (sv->prec == RQLP_FP64)
+    st = decompose_dense<double>(c, (const double*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (double*)P.Q,
+                                 (double*)P.L, (double*)P.V, ws, sl.size, sl.s);
+  else if (sv->prec == RQLP_BF16_REFINED)
+    st = decompose_dense_bf16(c, (const float*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (float*)P.Q,
+                              (float*)P.L, (float*)P.V, ws, sl.size, sl.s);
+  else
+    st = decompose_dense<float>(c, (const float*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (float*)P.Q,
+                                (float*)P.L, (float*)P.V, ws, sl.size, sl.s);
+  c->reset_info = true;
+  c->timing = timing;
+  if (st != RQLP_OK) return st;
+  HIP_TRY(hipEventRecord(sl.done, sl.s));
+  return RQLP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rqlp_status rqlp_server_create(rqlp_server** out, rqlp_ctx* c, size_t hbm_budget, int slots,
+                               rqlp_precision prec) {
+  if (!out || !c || hbm_budget < 4096 || slots < 1 || slots > 64 || !valid_prec(prec)) return RQLP_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  rqlp_server* sv = new (std::nothrow) rqlp_server();
+  if (!sv) return RQLP_ERR_OUT_OF_MEMORY;
+  sv->ctx = c;
+  sv->prec = prec;
+  sv->budget = hbm_budget & ~(size_t)255;
+  if (hipMalloc(&sv->pool, sv->budget) != hipSuccess) {
+    delete sv;
+    return RQLP_ERR_OUT_OF_MEMORY;
+  }
+  sv->free_ranges[0] = sv->budget;
+  sv->slots.resize(slots);
+  for (auto& sl : sv->slots) {
+    if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+      rqlp_server_destroy(sv);
+      return RQLP_ERR_HIP;
+    }
+  }
+  // one reset of the shared info record for everything the server runs
+  if (launch_info_reset(c->info, sv->slots[0].s) != hipSuccess ||
+      hipStreamSynchronize(sv->slots[0].s) != hipSuccess) {
+    rqlp_server_destroy(sv);
+    return RQLP_ERR_HIP;
+  }
+  *out = sv;
+  return RQLP_OK;
+}
+
+rqlp_status rqlp_server_destroy(rqlp_server* sv) {
+  if (!sv) return RQLP_OK;
+  hipSetDevice(sv->ctx->device);
+  for (auto& sl : sv->slots) {
+    if (sl.s) hipStreamSynchronize(sl.s);
+    if (sl.done) hipEventDestroy(sl.done);
+    if (sl.s) hipStreamDestroy(sl.s);
+  }
+  if (sv->pool) hipFree(sv->pool);
+  delete sv;
+  return RQLP_OK;
+}
+
+size_t rqlp_server_request_bytes(const rqlp_problem* req, rqlp_precision prec) {
+  if (!req || !valid_prec(prec) || check_problem(*req, prec) != RQLP_OK) return 0;
+  return problem_ws_bytes(*req, prec);
+}
+
+rqlp_status rqlp_server_submit(rqlp_server* sv, const rqlp_problem* req, int64_t* ticket) {
+  if (!sv || !req || !ticket) return RQLP_ERR_INVALID_ARG;
+  rqlp_status st = check_problem(*req, sv->prec);
+  if (st != RQLP_OK) return st;
+  if (problem_ws_bytes(*req, sv->prec) > sv->budget) return RQLP_ERR_OUT_OF_MEMORY;
+  *ticket = sv->next_ticket++;
+  sv->queue.emplace_back(*ticket, *req);
+  return RQLP_OK;
+}
+
+rqlp_status rqlp_server_poll(rqlp_server* sv, int64_t* done, int max_done, int* ndone, int* inflight,
+                             int* queued) {
+  if (!sv || !ndone || (max_done > 0 && !done)) return RQLP_ERR_INVALID_ARG;
+  if (hipSetDevice(sv->ctx->device) != hipSuccess) return RQLP_ERR_HIP;
+  *ndone = 0;
+  // completions (reported up to max_done per call; the rest on later calls)
+  for (auto& sl : sv->slots) {
+    if (!sl.busy || *ndone >= max_done) continue;
+    const hipError_t q = hipEventQuery(sl.done);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) return RQLP_ERR_HIP;
+    sl.busy = false;
+    pool_free(sv, sl.off, sl.size);
+    done[(*ndone)++] = sl.ticket;
+  }
+  // admissions, in arrival order: the head waits until it fits
+  for (auto& sl : sv->slots) {
+    if (sl.busy) continue;
+    if (sv->queue.empty()) break;
+    const rqlp_problem P = sv->queue.front().second;
+    const size_t need = problem_ws_bytes(P, sv->prec);
+    size_t off = 0;
+    if (!pool_alloc(sv, need, &off)) break;
+    sl.off = off;
+    sl.size = need;
+    sl.ticket = sv->queue.front().first;
+    sv->queue.pop_front();
+    rqlp_status st = launch_request(sv, sl, P);
+    if (st != RQLP_OK) {
+      pool_free(sv, off, need);
+      return st;
+    }
+    sl.busy = true;
+  }
+  int nb = 0;
+  for (auto& sl : sv->slots) nb += sl.busy ? 1 : 0;
+  if (inflight) *inflight = nb;
+  if (queued) *queued = (int)sv->queue.size();
   return RQLP_OK;
 }
 

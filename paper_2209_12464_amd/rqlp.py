@@ -77,6 +77,12 @@ def _lib():
             "rqlp_workspace_size_batched": (_SZ, [_INT, ctypes.POINTER(Problem), _INT]),
             "rqlp_decompose_batched": (_INT, [_P, _INT, ctypes.POINTER(Problem), _INT, _P, _SZ, _P]),
             "rqlp_set_graphs": (_INT, [_P, _INT]),
+            "rqlp_server_create": (_INT, [ctypes.POINTER(_P), _P, _SZ, _INT, _INT]),
+            "rqlp_server_destroy": (_INT, [_P]),
+            "rqlp_server_request_bytes": (_SZ, [ctypes.POINTER(Problem), _INT]),
+            "rqlp_server_submit": (_INT, [_P, ctypes.POINTER(Problem), ctypes.POINTER(_I64)]),
+            "rqlp_server_poll": (_INT, [_P, ctypes.POINTER(_I64), _INT, ctypes.POINTER(_INT),
+                                        ctypes.POINTER(_INT), ctypes.POINTER(_INT)]),
             "rqlp_set_timing": (_INT, [_P, _INT]),
             "rqlp_set_timing_mask": (_INT, [_P, ctypes.c_uint32]),
             "rqlp_get_timing": (_INT, [_P, _INT, ctypes.POINTER(ctypes.c_double),
@@ -97,7 +103,9 @@ def exported_symbols():
             "rqlp_gaussian", "rqlp_gemm_workspace_size", "rqlp_gemm", "rqlp_orth_workspace_size",
             "rqlp_orth", "rqlp_spmm", "rqlp_csr_transpose_workspace_size", "rqlp_csr_transpose",
             "rqlp_set_timing", "rqlp_set_timing_mask", "rqlp_get_timing",
-            "rqlp_workspace_size_batched", "rqlp_decompose_batched", "rqlp_set_graphs"]
+            "rqlp_workspace_size_batched", "rqlp_decompose_batched", "rqlp_set_graphs",
+            "rqlp_server_create", "rqlp_server_destroy", "rqlp_server_request_bytes", "rqlp_server_submit",
+            "rqlp_server_poll"]
 
 
 def _check(status, where):
@@ -270,6 +278,54 @@ def decompose_batched(As, params, ctx=None, workspace=None, outs=None, bf16=Fals
     _check(_lib().rqlp_decompose_batched(ctx.handle, len(As), arr, _prec(dtype, bf16), _ptr(workspace), ws_bytes,
                                          _stream(dev)), "rqlp_decompose_batched")
     return outs
+
+
+def server_request_bytes(m, n, k, p, q, dtype=torch.float32, bf16=False):
+    """Workspace bytes a request takes from a server's HBM budget."""
+    pr = Problem(1, m, n, n, k, p, q, 0, 1, 1, 1)
+    return int(_lib().rqlp_server_request_bytes(ctypes.byref(pr), _prec(dtype, bf16)))
+
+
+class Server:
+    """Continuous-batching request server (rqlp_server_*): an HBM budget for
+    the requests' workspaces, `slots` concurrent requests.  submit() queues a
+    request (device tensors stay owned and kept alive by the caller until
+    poll() reports its ticket); poll() returns finished tickets and admits
+    queued requests."""
+
+    def __init__(self, budget_bytes, slots=8, dtype=torch.float32, bf16=False, ctx=None, device=0):
+        self.ctx = ctx or default_context(device)
+        self._prec = _prec(dtype, bf16)
+        h = ctypes.c_void_p()
+        _check(_lib().rqlp_server_create(ctypes.byref(h), self.ctx.handle, int(budget_bytes), int(slots),
+                                         self._prec), "rqlp_server_create")
+        self._h = h
+        self._done = (ctypes.c_int64 * 256)()
+
+    def close(self):
+        if self._h:
+            _lib().rqlp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, A, k, p, q, seed, out):
+        Q, L, V = out
+        pr = Problem(_ptr(A), A.shape[0], A.shape[1], A.stride(0), k, p, q, seed, _ptr(Q), _ptr(L), _ptr(V))
+        t = ctypes.c_int64()
+        _check(_lib().rqlp_server_submit(self._h, ctypes.byref(pr), ctypes.byref(t)), "rqlp_server_submit")
+        return t.value
+
+    def poll(self):
+        """(finished tickets, in flight, queued)."""
+        nd, inf, qd = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(_lib().rqlp_server_poll(self._h, self._done, len(self._done), ctypes.byref(nd), ctypes.byref(inf),
+                                       ctypes.byref(qd)), "rqlp_server_poll")
+        return [self._done[i] for i in range(nd.value)], inf.value, qd.value
 
 
 def decompose_csr(rowptr, colidx, vals, m, n, k, p, q=0, seed=0, ctx=None, workspace=None, out=None):
