@@ -14,6 +14,9 @@ What it computes follows the paper:
   [V, Rt] = qr(B^T), L = Rt^T, so that A ~ Q L V^T.  This is the paper's
   algorithm run on A^T (Section III-A with A replaced by A^T), stopping
   before the extra d x d qr of R^T.
+* ruqlp_paper follows Algorithm 1 as printed instead (row sketch Phi,
+  P-bar = orth(A^T Phi), qr(A P-bar), then the d x d qr of R^T, P = P-bar
+  P-tilde, L = R-tilde^T).
 * orth() and qr() are the thin unpivoted Householder QR with a positive
   diagonal in R (Section II-B defines the unpivoted QR; the sign convention
   is this oracle's reading, which makes the factors unique for full column
@@ -36,6 +39,6 @@ or "parity unpinned").
 
 from .philox import philox4x64_10, gaussian_matrix, uniform_pair, box_muller  # noqa: F401
 from .householder import householder_qr  # noqa: F401
-from .ruqlp import ruqlp, ruqlp_csr, orth  # noqa: F401
+from .ruqlp import ruqlp, ruqlp_csr, ruqlp_paper, orth  # noqa: F401
 from .csr import csr_matmul, csr_transpose  # noqa: F401
 from .metrics import recon_diff, recon_error, orth_error, recon_error_csr  # noqa: F401

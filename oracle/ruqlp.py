@@ -99,3 +99,37 @@ def ruqlp_csr(rowptr, colidx, vals, m, n, k, p, q, seed, omega_dtype="f64"):
     mul_A = lambda X: csr_matmul(rowptr, colidx, vals, m, n, X)  # noqa: E731
     mul_At = lambda X: csr_matmul(rt, ct, vt, n, m, X)  # noqa: E731
     return _ruqlp_core(mul_A, mul_At, n, k, p, q, seed, omega_dtype)
+
+
+def ruqlp_paper(A, k, p, q, seed, omega_dtype="f64"):
+    """RU-QLP in the paper's own orientation: Algorithm 1 as printed
+    (Section III-A) with Algorithm 2 (Section III-B) computing P-bar.
+
+      1. Phi = randn(m, d)                 (rounded as in ruqlp)
+      2. P-bar = orth(A^T Phi); q times: P-bar = orth(A P-bar), then
+         P-bar = orth(A^T P-bar)           (Algorithm 2)
+      3. [Q, R] = qr(A P-bar)
+      4. [P-tilde, R-tilde] = qr(R^T)
+      5. Q;  P = P-bar P-tilde;  L = R-tilde^T
+
+    Returns (Q, L, P): Q m x d, L d x d lower triangular, P n x d; A is
+    approximated by Q L P^T = A P-bar P-bar^T.
+
+    Pinned by: tests/test_oracle_ruqlp.py -- invariants (orthonormal Q and
+    P, triangular L, Q L P^T = A P-bar P-bar^T), exact recovery when
+    rank(A) <= d, sigma_i(L) <= sigma_i(A), and its relation to the column
+    orientation on A^T (same P-bar and Q, and L-values of the extra QR).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    d = k + p
+    if not (1 <= k and d <= min(m, n)):
+        raise ValueError("need 1 <= k and k + p <= min(m, n)")
+    phi = round_to(gaussian_matrix(seed, m, d), omega_dtype)
+    Pbar = orth(A.T @ phi)
+    for _ in range(q):
+        Pbar = orth(A @ Pbar)
+        Pbar = orth(A.T @ Pbar)
+    Q, R = householder_qr(A @ Pbar)
+    Pt, Rt = householder_qr(R.T)
+    return Q, Rt.T.copy(), Pbar @ Pt

@@ -159,3 +159,45 @@ def test_serving_request_generator():
         i = np.arange(1, min(A.shape) + 1)
         want = np.where(i <= np.ceil(np.log(1e-8) / np.log(r["rho"])), r["rho"] ** i, 0.0)
         assert np.allclose(np.linalg.svd(A, compute_uv=False), want, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("m,n,k,p,q", [(120, 90, 10, 4, 0), (90, 120, 8, 3, 1), (200, 150, 20, 5, 2)])
+def test_paper_orientation_invariants(m, n, k, p, q):
+    """Algorithm 1 as printed: orthonormal Q and P, lower-triangular L,
+    Q L P^T = A P-bar P-bar^T (P-bar = P P-tilde^T), and sigma_i(L) <= sigma_i(A)."""
+    sigma = workloads.spectrum("geometric", min(m, n), rho=0.85)
+    A, s, _, _ = workloads.dense_from_spectrum(m, n, sigma, seed=m + n, trunc=0.0)
+    Q, L, P = oracle.ruqlp_paper(A, k, p, q, seed=3)
+    d = k + p
+    assert np.linalg.norm(Q.T @ Q - np.eye(d)) < 1e-13
+    assert np.linalg.norm(P.T @ P - np.eye(d)) < 1e-13
+    assert np.all(np.triu(L, 1) == 0)
+    # Q L P^T is the projection of A's rows onto span(P)
+    assert np.linalg.norm(Q @ L @ P.T - A @ P @ P.T) < 1e-12 * np.linalg.norm(A)
+    assert np.all(np.linalg.svd(L, compute_uv=False) <= s[:d] * (1 + 1e-12))
+
+
+def test_paper_orientation_is_column_orientation_of_transpose():
+    """The paper's P-bar, Q and R are the column orientation's Q, V and L^T
+    on A^T with the same Gaussian (m x d): the extra d x d QR only rotates
+    P and re-triangularizes L."""
+    m, n, k, p, q = 150, 110, 12, 4, 1
+    sigma = workloads.spectrum("geometric", min(m, n), rho=0.9)
+    A, _, _, _ = workloads.dense_from_spectrum(m, n, sigma, seed=5, trunc=0.0)
+    Q, L, P = oracle.ruqlp_paper(A, k, p, q, seed=8)
+    Qc, Lc, Vc = oracle.ruqlp(A.T, k, p, q, seed=8)  # Qc spans A^T's range sketch: P-bar
+    # Q (paper) = Vc (column orientation on A^T); R = Lc^T; R^T = Lc = P-tilde R-tilde
+    assert np.linalg.norm(Q - Vc) < 1e-11
+    Pt, Rt = np.linalg.qr(Lc)
+    sgn = np.sign(np.diag(Rt))
+    Pt, Rt = Pt * sgn, Rt * sgn[:, None]
+    assert np.linalg.norm(L - Rt.T) < 1e-11 * np.linalg.norm(L)
+    assert np.linalg.norm(P - Qc @ Pt) < 1e-11
+
+
+@pytest.mark.parametrize("rank", [3, 9])
+def test_paper_orientation_exact_recovery(rank):
+    rng = np.random.default_rng(rank)
+    A = rng.standard_normal((80, rank)) @ rng.standard_normal((rank, 60))
+    Q, L, P = oracle.ruqlp_paper(A, 8, 2, 0, seed=1)
+    assert np.linalg.norm(Q @ L @ P.T - A) < 1e-12 * np.linalg.norm(A)
