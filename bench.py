@@ -38,6 +38,9 @@ WORKLOADS = {
     "dense8000_q0": dict(kind="dense", m=8000, n=8000, k=200, p=10, q=0, dtype="f32", spectrum="gapped"),
     "small_fp64": dict(kind="dense", m=1000, n=800, k=20, p=5, q=0, dtype="f64", spectrum="geometric"),
     "csr100k": dict(kind="csr", m=100000, n=50000, k=100, p=10, q=1, dtype="f32", density=1e-3),
+    # the same 8000^2 workload in the paper's own row-sketch orientation (Algorithm 1 as printed)
+    "paper_dense8000": dict(kind="dense", m=8000, n=8000, k=200, p=10, q=1, dtype="f32", spectrum="gapped",
+                            paper=True),
     # a batch of 64 uneven requests of the serving stream (float32, q = 1)
     "batch64": dict(kind="batch", count=64, q=1, dtype="f32"),
     # the serving stream: 4096 Poisson-arrival requests over 64 distinct matrices
@@ -54,6 +57,13 @@ def f_alg(m, n, k, p, q):
     prods = 2.0 * m * n * d * (2 * q + 2)
     qrs = qr(m) * (q + 1) + qr(n) * (q + 1)
     return prods + qrs
+
+
+def f_alg_paper(m, n, k, p, q):
+    """F_alg of the row-sketch orientation: the same products and tall QRs
+    plus the d x d QR of R^T and the product P-bar P-tilde."""
+    d = k + p
+    return f_alg(m, n, k, p, q) + (4.0 * d ** 3 - 4.0 * d ** 3 / 3.0) + 2.0 * n * d * d
 
 
 def f_alg_csr(nnz, m, n, k, p, q):
@@ -112,6 +122,7 @@ def make_inputs(w, seed):
 METRIC_NAMES = {
     "dense8000": "RU-QLP GFLOP/s (8000^2 FP32, k=200, p=10, q=1)",
     "bf16_20000x15000": "RU-QLP GFLOP/s (20000x15000, k=500, p=20, q=1, BF16 products + FP32 accumulation)",
+    "paper_dense8000": "RU-QLP GFLOP/s (8000^2 FP32, k=200, p=10, q=1, row-sketch orientation of Algorithm 1)",
 }
 
 
@@ -348,6 +359,9 @@ def cpu_baseline(w, A_host, seed, flops):
         return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
                 "sample": (f"one decomposition of the same recipe at half size ({mh}x{nh}, k={kh}, p={ph}, "
                            f"q={w['q']}), bfloat16 operand rounding emulated"), "seconds": dt}
+    elif w["kind"] == "dense" and w.get("paper"):
+        oracle.ruqlp_paper(A_host.astype(np.float64), w["k"], w["p"], w["q"], seed, omega_dtype="f32")
+        sample = f"one full decomposition of the same {w['m']}x{w['n']} workload (q={w['q']}), row-sketch orientation"
     elif w["kind"] == "dense":
         oracle.ruqlp(A_host.astype(np.float64), w["k"], w["p"], w["q"], seed,
                      omega_dtype="f32" if w["dtype"] == "f32" else "f64")
@@ -487,12 +501,19 @@ def main():
     if w["kind"] == "dense":
         A = torch.from_numpy(host).to(dev)
         m, n = A.shape
-        flops = f_alg(m, n, k, p, q)
-        ws = rqlp.alloc_workspace(rqlp.workspace_size(m, n, k, p, q, A.dtype, bf16=bf16), dev)
         out = (torch.empty((m, d), dtype=A.dtype, device=dev), torch.empty((d, d), dtype=A.dtype, device=dev),
                torch.empty((n, d), dtype=A.dtype, device=dev))
-        step = lambda: rqlp.decompose(A, k, p, q, seed=args.seed, ctx=ctx, workspace=ws, out=out,  # noqa: E731
-                                      bf16=bf16)
+        if w.get("paper"):
+            flops = f_alg_paper(m, n, k, p, q)
+            ws = rqlp.alloc_workspace(int(rqlp._lib().rqlp_workspace_size_paper(m, n, k, p, q, rqlp._prec(A.dtype))),
+                                      dev)
+            step = lambda: rqlp.decompose_paper(A, k, p, q, seed=args.seed, ctx=ctx, workspace=ws,  # noqa: E731
+                                                out=out)
+        else:
+            flops = f_alg(m, n, k, p, q)
+            ws = rqlp.alloc_workspace(rqlp.workspace_size(m, n, k, p, q, A.dtype, bf16=bf16), dev)
+            step = lambda: rqlp.decompose(A, k, p, q, seed=args.seed, ctx=ctx, workspace=ws, out=out,  # noqa: E731
+                                          bf16=bf16)
         dom = ["gemm_nn", "gemm_tn"]
         dom_flops = {"gemm_nn": 2.0 * m * n * d, "gemm_tn": 2.0 * m * n * d}
         dtype_name = "bf16" if bf16 else ("f32" if A.dtype == torch.float32 else "f64")

@@ -161,6 +161,8 @@ Layout layout(int64_t m, int64_t n, int d, bool sparse, int64_t nnz, bool bf16 =
   L.q1 = put((size_t)mx * dp * sizeof(double));
   size_t pe = 0;
   if (!sparse) pe = std::max(gemm_partial_elems<T>((int)m, (int)n, dp), gemm_partial_elems<T>((int)n, (int)m, dp));
+  if (!sparse)  // the paper orientation's P = P-bar P-tilde (reduction over d)
+    pe = std::max({pe, gemm_partial_elems<T>((int)m, d, dp), gemm_partial_elems<T>((int)n, d, dp)});
   if (bf16) pe = std::max(gemm_bf16_partial_elems((int)m, (int)bf16_ld(n), dp),
                           gemm_bf16_partial_elems((int)n, (int)bf16_ld(m), dp));
   L.part = put(pe * sizeof(T));
@@ -329,6 +331,53 @@ rqlp_status run_method(rqlp_ctx* c, char* base, const Layout& Lo, int64_t m, int
   return RQLP_OK;
 }
 
+// The paper's own orientation (Algorithm 1 as printed, with Algorithm 2):
+// Phi = randn(m, d); P-bar = orth(A^T Phi), q times P-bar = orth(A P-bar),
+// P-bar = orth(A^T P-bar); [Q, R] = qr(A P-bar); [P-tilde, R-tilde] =
+// qr(R^T); P = P-bar P-tilde; L = R-tilde^T.  Lo is the layout with m and n
+// exchanged, so its "Omega" buffer is m x dp (Phi, and the m x d bases of
+// the power steps) and its "Q" buffer n x dp (P-bar).
+template <typename T, typename MulA, typename MulAt>
+rqlp_status run_method_paper(rqlp_ctx* c, char* base, const Layout& Lo, int64_t m, int64_t n, int k, int p, int q,
+                             uint64_t seed, T* Q, T* Lout, T* P, hipStream_t s, MulA mulA, MulAt mulAt) {
+  const int d = k + p, dp = padded_d(d);
+  T* phi = (T*)(base + Lo.om);
+  T* yb = (T*)(base + Lo.yb);
+  T* pb = (T*)(base + Lo.qi);
+  T* part = (T*)(base + Lo.part);
+  Bufs b;
+  b.q1 = (double*)(base + Lo.q1);
+  b.gp = (double*)(base + Lo.gp);
+  b.g = (double*)(base + Lo.g);
+  b.r1 = (double*)(base + Lo.r1);
+  b.r2 = (double*)(base + Lo.r2);
+  b.rinv = (double*)(base + Lo.rinv);
+  b.flags = (int32_t*)(base + Lo.flags);
+  b.xf = (double*)(base + Lo.xf);
+  b.esq = (double*)(base + Lo.esq);
+  rqlp_status st;
+  if (c->reset_info) HIP_TRY(launch_info_reset(c->info, s));
+  HIP_TRY(launch_gaussian<T>(seed, kSketchKey1, m, d, phi, dp, s));
+  if ((st = mulAt(phi, yb)) != RQLP_OK) return st;  // A^T Phi (n x dp)
+  int oi = 1;
+  if ((st = cholqr2<T>(c, yb, dp, n, d, b, pb, dp, dp, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
+  for (int it = 1; it <= q; ++it) {
+    if ((st = mulA(pb, yb)) != RQLP_OK) return st;  // A P-bar (m x dp)
+    if ((st = cholqr2<T>(c, yb, dp, m, d, b, phi, dp, dp, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
+    if ((st = mulAt(phi, yb)) != RQLP_OK) return st;  // A^T P-bar (n x dp)
+    if ((st = cholqr2<T>(c, yb, dp, n, d, b, pb, dp, dp, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
+  }
+  // [Q, R] = qr(A P-bar); R^T (lower, d x d) goes to the Phi buffer
+  if ((st = mulA(pb, yb)) != RQLP_OK) return st;
+  if ((st = cholqr2<T>(c, yb, dp, m, d, b, Q, d, d, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
+  HIP_TRY(launch_form_l<T>(b.r2, b.r1, b.flags, d, dp, phi, dp, s));
+  // [P-tilde, R-tilde] = qr(R^T): P-tilde (d x dp, zero padding columns) into yb; L = R-tilde^T
+  if ((st = cholqr2<T>(c, phi, dp, d, d, b, yb, dp, dp, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
+  HIP_TRY(launch_form_l<T>(b.r2, b.r1, b.flags, d, dp, Lout, d, s));
+  // P = P-bar P-tilde (n x d)
+  return gemm<T>(c, 0, pb, dp, n, d, yb, dp, d, P, d, d, part, s, true);
+}
+
 template <typename T>
 rqlp_status decompose_dense(rqlp_ctx* c, const T* A, int64_t m, int64_t n, int64_t lda, int k, int p, int q,
                             uint64_t seed, T* Q, T* L, T* V, void* ws, size_t ws_bytes, hipStream_t s) {
@@ -341,6 +390,20 @@ rqlp_status decompose_dense(rqlp_ctx* c, const T* A, int64_t m, int64_t n, int64
   auto mulA = [&](const T* X, T* Y) { return gemm<T>(c, 0, A, lda, m, n, X, dp, d, Y, dp, dp, part, s, true); };
   auto mulAt = [&](const T* X, T* Y) { return gemm<T>(c, 1, A, lda, m, n, X, dp, d, Y, dp, dp, part, s, true); };
   return run_method<T>(c, base, Lo, m, n, k, p, q, seed, Q, L, V, s, mulA, mulAt);
+}
+
+template <typename T>
+rqlp_status decompose_paper(rqlp_ctx* c, const T* A, int64_t m, int64_t n, int64_t lda, int k, int p, int q,
+                            uint64_t seed, T* Q, T* L, T* P, void* ws, size_t ws_bytes, hipStream_t s) {
+  const int d = k + p, dp = padded_d(d);
+  const Layout Lo = layout<T>(n, m, d, false, 0);
+  char* base = nullptr;
+  rqlp_status st = get_workspace(c, ws, ws_bytes, Lo.total, &base);
+  if (st != RQLP_OK) return st;
+  T* part = (T*)(base + Lo.part);
+  auto mulA = [&](const T* X, T* Y) { return gemm<T>(c, 0, A, lda, m, n, X, dp, d, Y, dp, dp, part, s, true); };
+  auto mulAt = [&](const T* X, T* Y) { return gemm<T>(c, 1, A, lda, m, n, X, dp, d, Y, dp, dp, part, s, true); };
+  return run_method_paper<T>(c, base, Lo, m, n, k, p, q, seed, Q, L, P, s, mulA, mulAt);
 }
 
 // RQLP_BF16_REFINED: A (float) is rounded to bfloat16 once, in both layouts;
@@ -638,6 +701,28 @@ rqlp_status rqlp_set_graphs(rqlp_ctx* c, int enabled) {
   c->graphs = enabled != 0;
   c->last_key.clear();
   return RQLP_OK;
+}
+
+size_t rqlp_workspace_size_paper(int64_t m, int64_t n, int k, int p, int q, rqlp_precision prec) {
+  if (check_common(m, n, k, p, q, prec) != RQLP_OK || prec == RQLP_BF16_REFINED) return 0;
+  return prec == RQLP_FP64 ? layout<double>(n, m, k + p, false, 0).total : layout<float>(n, m, k + p, false, 0).total;
+}
+
+rqlp_status rqlp_decompose_paper(rqlp_ctx* c, const void* A, int64_t m, int64_t n, int64_t lda, int k, int p, int q,
+                                 rqlp_precision prec, uint64_t seed, void* Q, void* L, void* P, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  if (!c || !A || !Q || !L || !P) return RQLP_ERR_INVALID_ARG;
+  rqlp_status st = check_common(m, n, k, p, q, prec);
+  if (st != RQLP_OK) return st;
+  if (lda < n) return RQLP_ERR_INVALID_ARG;
+  if (prec == RQLP_BF16_REFINED) return RQLP_ERR_UNSUPPORTED;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == RQLP_FP64)
+    return decompose_paper<double>(c, (const double*)A, m, n, lda, k, p, q, seed, (double*)Q, (double*)L, (double*)P,
+                                   ws, ws_bytes, s);
+  return decompose_paper<float>(c, (const float*)A, m, n, lda, k, p, q, seed, (float*)Q, (float*)L, (float*)P, ws,
+                                ws_bytes, s);
 }
 
 rqlp_status rqlp_decompose_csr(rqlp_ctx* c, const int32_t* rowptr, const int32_t* colidx, const void* vals,

@@ -77,6 +77,9 @@ def _lib():
             "rqlp_workspace_size_batched": (_SZ, [_INT, ctypes.POINTER(Problem), _INT]),
             "rqlp_decompose_batched": (_INT, [_P, _INT, ctypes.POINTER(Problem), _INT, _P, _SZ, _P]),
             "rqlp_set_graphs": (_INT, [_P, _INT]),
+            "rqlp_workspace_size_paper": (_SZ, [_I64, _I64, _INT, _INT, _INT, _INT]),
+            "rqlp_decompose_paper": (_INT, [_P, _P, _I64, _I64, _I64, _INT, _INT, _INT, _INT, _U64,
+                                            _P, _P, _P, _P, _SZ, _P]),
             "rqlp_server_create": (_INT, [ctypes.POINTER(_P), _P, _SZ, _INT, _INT]),
             "rqlp_server_destroy": (_INT, [_P]),
             "rqlp_server_request_bytes": (_SZ, [ctypes.POINTER(Problem), _INT]),
@@ -105,7 +108,7 @@ def exported_symbols():
             "rqlp_set_timing", "rqlp_set_timing_mask", "rqlp_get_timing",
             "rqlp_workspace_size_batched", "rqlp_decompose_batched", "rqlp_set_graphs",
             "rqlp_server_create", "rqlp_server_destroy", "rqlp_server_request_bytes", "rqlp_server_submit",
-            "rqlp_server_poll"]
+            "rqlp_server_poll", "rqlp_workspace_size_paper", "rqlp_decompose_paper"]
 
 
 def _check(status, where):
@@ -234,6 +237,31 @@ def decompose(A, k, p, q=0, seed=0, ctx=None, workspace=None, out=None, bf16=Fal
                                  _ptr(Q), _ptr(L), _ptr(V), ws_ptr, ws_bytes, _stream(A.device)),
            "rqlp_decompose")
     return Q, L, V
+
+
+def decompose_paper(A, k, p, q=0, seed=0, ctx=None, workspace=None, out=None):
+    """RU-QLP in the paper's row-sketch orientation (Algorithm 1 as printed):
+    returns (Q, L, P) with A ~ Q L P^T; float32 or float64 dense A."""
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D row-major tensor")
+    ctx = ctx or default_context(A.device.index or 0)
+    m, n = A.shape
+    d = k + p
+    prec = _prec(A.dtype)
+    if out is None:
+        Q = torch.empty((m, d), dtype=A.dtype, device=A.device)
+        L = torch.empty((d, d), dtype=A.dtype, device=A.device)
+        P = torch.empty((n, d), dtype=A.dtype, device=A.device)
+    else:
+        Q, L, P = out
+    if workspace is None:
+        ws_bytes = int(_lib().rqlp_workspace_size_paper(m, n, k, p, q, prec))
+        workspace = alloc_workspace(ws_bytes, A.device) if ws_bytes else None
+    ws_bytes = workspace.numel() if workspace is not None else 0
+    _check(_lib().rqlp_decompose_paper(ctx.handle, _ptr(A), m, n, A.stride(0), k, p, q, prec, seed, _ptr(Q),
+                                       _ptr(L), _ptr(P), _ptr(workspace), ws_bytes, _stream(A.device)),
+           "rqlp_decompose_paper")
+    return Q, L, P
 
 
 def _problems(As, params, outs):

@@ -214,3 +214,27 @@ def test_csr_full_size(gpu_lib):
     Qo, Lo, Vo = oracle.ruqlp_csr(c["rowptr"], c["colidx"], c["vals"], m, n, 100, 10, 1, 7, omega_dtype="f32")
     nA = np.linalg.norm(c["vals"].astype(np.float64))
     assert recon_diff(Qg, Lg, Vg, Qo, Lo, Vo) / nA <= 1e-5
+
+
+# ---------------------------------------------------------------- the paper's own orientation
+@pytest.mark.parametrize("m,n,k,p,q", [(600, 450, 30, 10, 1), (450, 600, 20, 5, 0), (1000, 800, 20, 5, 0),
+                                       (700, 500, 120, 8, 2)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_paper_orientation_matches_oracle(gpu_lib, m, n, k, p, q, dtype):
+    """rqlp_decompose_paper against oracle.ruqlp_paper (Algorithm 1 as
+    printed): the same Delta gates; the factors are unique here."""
+    announce("decompose paper orientation", m, n, k, p, q, dtype)
+    sigma = workloads.spectrum("geometric", min(m, n), rho=0.97)
+    A, _, _, _ = workloads.dense_from_spectrum(m, n, sigma, seed=m + 3 * n, trunc=0.0)
+    A = A.astype(np.float32) if dtype == torch.float32 else A
+    Qg, Lg, Pg = (to_np(x) for x in gpu_lib.decompose_paper(to_dev(A), k, p, q, seed=6))
+    A64 = A.astype(np.float64)
+    Qo, Lo, Po = oracle.ruqlp_paper(A64, k, p, q, 6, omega_dtype=_omega_dtype(dtype))
+    tol = TOL[dtype]
+    assert recon_diff(Qg, Lg, Pg, Qo, Lo, Po) / np.linalg.norm(A64) <= tol
+    d = k + p
+    assert orth_error(Qg) <= 100 * d * (tol if dtype == torch.float32 else 1e-15)
+    assert orth_error(Pg) <= 100 * d * (tol if dtype == torch.float32 else 1e-15)
+    assert np.all(np.triu(Lg, 1) == 0.0)
+    if dtype == torch.float64:
+        assert np.linalg.norm(Lg - Lo) <= 1e-10 * np.linalg.norm(Lo)
