@@ -15,7 +15,7 @@ namespace rqlp {
 
 constexpr int kApRows = 64;           // rows per workgroup (16 per wave)
 constexpr int kApCols = 4 * kTile;    // columns per workgroup (4 blocks)
-constexpr int kApXS = kApCols + 2;    // LDS row stride of the X tile (doubles)
+constexpr int kApXS = kApCols + 16;   // LDS row stride of the X tile (doubles): rows 32 banks apart
 constexpr int kApYS = kTile + 1;      // LDS row stride of the Y tile (doubles)
 
 __host__ __device__ inline size_t apply_lds_doubles(int dp) {

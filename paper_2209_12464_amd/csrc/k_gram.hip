@@ -152,10 +152,13 @@ int gram_reduce_blocks(int dp) { return (int)ceil_div((int64_t)dp * dp, 256); }
 
 int gram_chunks(int64_t rows, int dp) {
   // about 512 workgroups in total, two per CU, so that one workgroup's
-  // MFMAs cover the other's load latency
+  // MFMAs cover the other's load latency; for wide Gram matrices (21 or
+  // more tile pairs, dp > 320) about 1024, four per CU: their long
+  // per-chunk MFMA work hides more latency with more workgroups, while for
+  // narrow ones the extra partial slabs cost more than they gain (measured)
   const int t = (int)ceil_div(dp, kGT);
   const int npairs = t * (t + 1) / 2;
-  int64_t chunks = ceil_div(512, npairs);
+  int64_t chunks = ceil_div(npairs >= 21 ? 1024 : 512, npairs);
   const int64_t maxc = ceil_div(rows, kGK);
   if (chunks > maxc) chunks = maxc;
   if (chunks < 1) chunks = 1;
