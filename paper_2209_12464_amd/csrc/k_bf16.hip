@@ -44,7 +44,7 @@ constexpr int kCvT = 64;
 // ldt, bf16) = A^T.  Columns [n, ldb) of Ab and [m, ldt) of At are zero.
 __global__ __launch_bounds__(256) void cvt_bf16_kernel(const float* __restrict__ A, int64_t lda, int64_t m,
                                                        int64_t n, uint16_t* __restrict__ Ab, int64_t ldb,
-                                                       uint16_t* __restrict__ At, int64_t ldt) {
+                                                       uint16_t* __restrict__ At, int64_t ldt, bool vec) {
   __shared__ uint16_t tile[kCvT][kCvT + 2];
   const int tid = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.y * kCvT, c0 = (int64_t)blockIdx.x * kCvT;
@@ -54,12 +54,19 @@ __global__ __launch_bounds__(256) void cvt_bf16_kernel(const float* __restrict__
     const int rl = (tid >> 4) + 16 * i;
     const int64_t r = r0 + rl;
     u16x4 v;
+    if (vec && r < m && c0 + cl + 4 <= n) {  // one 16-byte load
+      const floatx4 x = *reinterpret_cast<const floatx4*>(A + r * lda + c0 + cl);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t c = c0 + cl + j;
-      v[j] = (r < m && c < n) ? f2bf(A[r * lda + c]) : (uint16_t)0;
-      tile[rl][cl + j] = v[j];
+      for (int j = 0; j < 4; ++j) v[j] = f2bf(x[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t c = c0 + cl + j;
+        v[j] = (r < m && c < n) ? f2bf(A[r * lda + c]) : (uint16_t)0;
+      }
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tile[rl][cl + j] = v[j];
     if (r < m && c0 + cl < ldb) {
       if (c0 + cl + 4 <= ldb) {
         *reinterpret_cast<u16x4*>(Ab + r * ldb + c0 + cl) = v;
@@ -97,7 +104,8 @@ hipError_t launch_cvt_bf16(const float* A, int64_t lda, int64_t m, int64_t n, ui
   // the grid covers the padded extents so that the zero padding is written
   const int64_t cols = std::max<int64_t>(ldb, n), rows = At ? std::max<int64_t>(ldt, m) : m;
   dim3 grid((unsigned)ceil_div(cols, kCvT), (unsigned)ceil_div(rows, kCvT));
-  hipLaunchKernelGGL(cvt_bf16_kernel, grid, dim3(256), 0, s, A, lda, m, n, Ab, ldb, At, ldt);
+  const bool vec = lda % 4 == 0 && ((uintptr_t)A & 15) == 0;  // rows 16-byte aligned: vector loads
+  hipLaunchKernelGGL(cvt_bf16_kernel, grid, dim3(256), 0, s, A, lda, m, n, Ab, ldb, At, ldt, vec);
   return hipGetLastError();
 }
 
@@ -107,8 +115,9 @@ hipError_t launch_cvt_bf16_t(const float* X, int64_t ldx, int64_t K, int64_t N, 
   if (K <= 0 || N <= 0) return hipSuccess;
   // only the transposed copy is wanted: Ab is written to a null-sized target
   dim3 grid((unsigned)ceil_div(N, kCvT), (unsigned)ceil_div(std::max<int64_t>(ldt, K), kCvT));
+  const bool vec = ldx % 4 == 0 && ((uintptr_t)X & 15) == 0;
   hipLaunchKernelGGL(cvt_bf16_kernel, grid, dim3(256), 0, s, X, ldx, K, N, (uint16_t*)nullptr, (int64_t)0, Xt,
-                     ldt);
+                     ldt, vec);
   return hipGetLastError();
 }
 
