@@ -3,7 +3,9 @@
 // type of Y and Q.  Normally R^-1 is available explicitly (the Cholesky's
 // fast path, or the inverse kernel after a full factorization), and every
 // 16 x 16 output block is an independent sum Q[:, J] = sum_{t <= J} Y[:, t]
-// X[t, J]: workgroups take 64 rows x 4 column blocks with LDS-staged tiles.
+// X[t, J]: workgroups take 64 RF rows x 4 column blocks with LDS-staged
+// tiles, each wave RF 16-row fragments (RF = 2 for tall inputs, so that a
+// wave issues 32 MFMAs per staged block row).
 // When the Cholesky marked a dependent column, a blocked substitution runs
 // instead, and those columns are replaced by N(0,1)/sqrt(rows) columns from
 // a Philox stream of their own (completion of a rank-deficient basis);
@@ -13,18 +15,17 @@
 
 namespace rqlp {
 
-constexpr int kApRows = 64;           // rows per workgroup (16 per wave)
 constexpr int kApCols = 4 * kTile;    // columns per workgroup (4 blocks)
 constexpr int kApXS = kApCols + 16;   // LDS row stride of the X tile (doubles): rows 32 banks apart
 constexpr int kApYS = kTile + 1;      // LDS row stride of the Y tile (doubles)
 
-__host__ __device__ inline size_t apply_lds_doubles(int dp) {
-  const size_t expl = 2 * (size_t)(kTile * kApXS + kApRows * kApYS);
+__host__ __device__ inline size_t apply_lds_doubles(int dp, int rf) {
+  const size_t expl = 2 * (size_t)(kTile * kApXS + 64 * rf * kApYS);
   const size_t subst = (size_t)kTile * (dp + 1);
   return expl > subst ? expl : subst;
 }
 
-template <typename Tin, typename Tout>
+template <typename Tin, typename Tout, int RF>
 __global__ __launch_bounds__(256) void apply_kernel(const Tin* __restrict__ Y, int64_t ldy, int64_t rows,
                                                     int d, int dp, const double* __restrict__ R,
                                                     const double* __restrict__ Rinv16,
@@ -34,6 +35,7 @@ __global__ __launch_bounds__(256) void apply_kernel(const Tin* __restrict__ Y, i
                                                     Tout* __restrict__ out1, int64_t ld1, int ncols1,
                                                     Tout* __restrict__ out2, int64_t ld2, int ncols2,
                                                     uint64_t seed, uint64_t key1, double inv_sqrt_rows) {
+  constexpr int kApRows = 64 * RF;  // rows per workgroup (16 RF per wave)
   extern __shared__ double smem[];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -52,7 +54,7 @@ __global__ __launch_bounds__(256) void apply_kernel(const Tin* __restrict__ Y, i
     double* Xs = smem;                           // [2][16][kApXS]
     double* Ys = smem + 2 * kTile * kApXS;       // [2][64][kApYS]
     double xr[4];
-    Tin yr[4];
+    Tin yr[4 * RF];
     auto load = [&](int t) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -60,6 +62,10 @@ __global__ __launch_bounds__(256) void apply_kernel(const Tin* __restrict__ Y, i
         const int kr = e >> 6, c = e & 63;       // X[t*16 + kr][J0*16 + c]
         const int col = J0 * kTile + c;
         xr[q] = (col < J1 * kTile) ? Xfull[(int64_t)(t * kTile + kr) * dp + col] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4 * RF; ++q) {
+        const int e = tid + 256 * q;
         const int rr = e >> 4, cc = e & 15;      // Y[r0 + rr][t*16 + cc]
         const int64_t row = r0 + rr;
         const int ycol = t * kTile + cc;
@@ -71,12 +77,18 @@ __global__ __launch_bounds__(256) void apply_kernel(const Tin* __restrict__ Y, i
       for (int q = 0; q < 4; ++q) {
         const int e = tid + 256 * q;
         Xs[buf * kTile * kApXS + (e >> 6) * kApXS + (e & 63)] = xr[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 4 * RF; ++q) {
+        const int e = tid + 256 * q;
         Ys[buf * kApRows * kApYS + (e >> 4) * kApYS + (e & 15)] = (double)yr[q];
       }
     };
-    doublex4 acc[4];
+    doublex4 acc[RF][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc[u] = Mfma<double>::zero();
+    for (int f = 0; f < RF; ++f)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[f][u] = Mfma<double>::zero();
     load(0);
     store(0);
     __syncthreads();
@@ -85,16 +97,22 @@ __global__ __launch_bounds__(256) void apply_kernel(const Tin* __restrict__ Y, i
       const bool more = t + 1 < J1;
       if (more) load(t + 1);
       const double* xs = Xs + buf * kTile * kApXS;
-      const double* ys = Ys + buf * kApRows * kApYS + (wave * kTile + lc) * kApYS;
-      double a[4];
+      const double* ys = Ys + buf * kApRows * kApYS + (wave * kTile * RF + lc) * kApYS;
+      double a[RF][4];
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) a[ks] = ys[ks * 4 + lr];  // A[m][k] = Y[16 w + m][t*16 + k]
+      for (int f = 0; f < RF; ++f)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)  // A[m][k] = Y[16 (RF w + f) + m][t*16 + k]
+          a[f][ks] = ys[f * kTile * kApYS + ks * 4 + lr];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         if (J0 + u >= t && J0 + u < J1) {
 #pragma unroll
-          for (int ks = 0; ks < 4; ++ks)
-            acc[u] = Mfma<double>::mma(a[ks], xs[(ks * 4 + lr) * kApXS + u * kTile + lc], acc[u]);
+          for (int ks = 0; ks < 4; ++ks) {
+            const double b = xs[(ks * 4 + lr) * kApXS + u * kTile + lc];
+#pragma unroll
+            for (int f = 0; f < RF; ++f) acc[f][u] = Mfma<double>::mma(a[f][ks], b, acc[f][u]);
+          }
         }
       }
       if (more) store(buf ^ 1);
@@ -106,13 +124,15 @@ __global__ __launch_bounds__(256) void apply_kernel(const Tin* __restrict__ Y, i
       if (J0 + u >= J1) break;
       const int col = (J0 + u) * kTile + lc;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + wave * kTile + lr + 4 * r;
-        if (row < rows) {
-          if (col < ncols1) out1[row * ld1 + col] = (Tout)acc[u][r];
-          if (out2 && col < ncols2) out2[row * ld2 + col] = (Tout)acc[u][r];
+      for (int f = 0; f < RF; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = r0 + (wave * RF + f) * kTile + lr + 4 * r;
+          if (row < rows) {
+            if (col < ncols1) out1[row * ld1 + col] = (Tout)acc[f][u][r];
+            if (out2 && col < ncols2) out2[row * ld2 + col] = (Tout)acc[f][u][r];
+          }
         }
-      }
     }
     return;
   }
@@ -189,18 +209,28 @@ hipError_t launch_apply(const Tin* Y, int64_t ldy, int64_t rows, int d, int dp, 
                         int64_t ld2, int ncols2, uint64_t seed, uint64_t key1, hipStream_t s,
                         hipEvent_t ev0, hipEvent_t ev1) {
   if (rows <= 0) return hipSuccess;
-  const size_t shmem = apply_lds_doubles(dp) * sizeof(double);
   const double isr = 1.0 / sqrt((double)rows);
   const unsigned groups = (unsigned)ceil_div(dp / kTile, 4);
+  // two row fragments per wave for wide R (five or more column groups, whose
+  // workgroups run long triangular loops) once that still gives about four
+  // workgroups per CU; narrow R keeps one (measured faster there)
+  const int rf = (groups >= 5 && ceil_div(rows, 128) * groups >= 1024) ? 2 : 1;
+  const size_t shmem = apply_lds_doubles(dp, rf) * sizeof(double);
+  const void* fn = rf == 2 ? reinterpret_cast<const void*>(apply_kernel<Tin, Tout, 2>)
+                           : reinterpret_cast<const void*>(apply_kernel<Tin, Tout, 1>);
   if (shmem > 65536) {  // the substitution rows of a wide R take more than 64 KB
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(apply_kernel<Tin, Tout>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
   }
   if (ev0) (void)hipEventRecord(ev0, s);
-  hipLaunchKernelGGL((apply_kernel<Tin, Tout>), dim3((unsigned)ceil_div(rows, kApRows), groups), dim3(256), shmem,
-                     s, Y, ldy, rows, d, dp, R, Rinv16, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2,
-                     seed, key1, isr);
+  if (rf == 2)
+    hipLaunchKernelGGL((apply_kernel<Tin, Tout, 2>), dim3((unsigned)ceil_div(rows, 128), groups), dim3(256), shmem,
+                       s, Y, ldy, rows, d, dp, R, Rinv16, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2,
+                       seed, key1, isr);
+  else
+    hipLaunchKernelGGL((apply_kernel<Tin, Tout, 1>), dim3((unsigned)ceil_div(rows, 64), groups), dim3(256), shmem,
+                       s, Y, ldy, rows, d, dp, R, Rinv16, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2,
+                       seed, key1, isr);
   if (ev1) (void)hipEventRecord(ev1, s);
   return hipGetLastError();
 }

@@ -124,7 +124,9 @@ def _conditioned(m, d, cond, seed):
 @pytest.mark.parametrize("m,d,cond", [(1000, 25, 1e3), (8000, 210, 1e4), (500, 256, 1e2), (17, 17, 10.0),
                                       (300, 1, 1.0), (4000, 110, 1e6),
                                       # d > 256: the Cholesky keeps its trailing tiles in memory
-                                      (3000, 320, 1e4), (2000, 544, 1e2), (1200, 417, 1e6), (600, 257, 10.0)])
+                                      (3000, 320, 1e4), (2000, 544, 1e2), (1200, 417, 1e6), (600, 257, 10.0),
+                                      # tall enough for two row fragments per wave in the solve
+                                      (70000, 100, 1e3), (30000, 300, 1e2)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_orth_matches_householder(gpu_lib, m, d, cond, dtype):
     announce("orth", m, d, cond, dtype)
@@ -165,13 +167,15 @@ def test_orth_rank_deficient_completes_basis(gpu_lib, dtype):
     assert np.all(R[dep, :] == 0.0)
 
 
+@pytest.mark.parametrize("rows", [1500, 30000])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_orth_rank_deficient_wide(gpu_lib, dtype):
+def test_orth_rank_deficient_wide(gpu_lib, dtype, rows):
     """d = 300 > 256 with 40 dependent columns spread over the column
-    blocks: the wide Cholesky marks them and the solve substitutes."""
-    announce("orth rank-deficient wide", dtype)
+    blocks: the wide Cholesky marks them and the solve substitutes (with
+    one and with two row fragments per wave)."""
+    announce("orth rank-deficient wide", dtype, rows)
     rng = np.random.default_rng(19)
-    B = rng.standard_normal((1500, 260))
+    B = rng.standard_normal((rows, 260))
     cols, dep = [], []
     for c in range(260):
         cols.append(B[:, c:c + 1])
