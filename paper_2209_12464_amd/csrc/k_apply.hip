@@ -138,16 +138,16 @@ __global__ __launch_bounds__(256) void apply_kernel(const Tin* __restrict__ Y, i
   }
 
   // ---- blocked substitution (a dependent column was found) ----
-  // Wave 0 of the first column group walks the workgroup's four 16-row
-  // slabs one after another (this path is taken only for rank-deficient
-  // inputs); per slab it goes through the 16-column blocks J in order,
+  // Wave 0 of the workgroup of column group g takes the 16-row slabs g,
+  // g + groups, ... of the 64 RF-row block (this path is taken only for
+  // rank-deficient inputs); per slab it goes through the 16-column blocks J in order,
   //     acc    = Y[:, J] - sum_{t < J} Q[:, t] R[t, J]      (float64 MFMA)
   //     Q[:,J] = acc * inv(R[J, J])                         (4 MFMAs)
   // keeping the finished Q blocks in LDS as the A operand of later blocks.
-  if (blockIdx.y != 0 || wave != 0) return;
+  if (wave != 0) return;
   double* Qs = smem;  // [16][dp + 1]
   const int S = dp + 1;
-  for (int slab = 0; slab < kApRows / kTile; ++slab) {
+  for (int slab = blockIdx.y; slab < kApRows / kTile; slab += gridDim.y) {
     const int64_t q0 = r0 + slab * kTile;
     if (q0 >= rows) break;
     for (int J = 0; J < T; ++J) {
