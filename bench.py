@@ -308,7 +308,12 @@ def run_batch_bench(args, w, rqlp, torch, dev):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps
 
+    # eager: grouped factorizations (lockstep), then every problem's
+    # sequence on its own stream; graph replay (ungrouped form)
     eager_ms = timed(lambda: rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs), args.steps)
+    ctx.set_batch_grouping(False)
+    ungrouped_ms = timed(lambda: rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs), args.steps)
+    ctx.set_batch_grouping(True)
     ctx.set_graphs(True)
     ms = timed(lambda: rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs), args.steps)
     ctx.set_graphs(False)
@@ -328,7 +333,7 @@ def run_batch_bench(args, w, rqlp, torch, dev):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "count": w["count"], "q": w["q"], "flops_per_step": flops,
                    "m_range": [512, 8192], "n_range": [256, 4096], "k_range": [8, 256], "p": 10},
-        "batched_eager_ms": eager_ms, "sequential_ms": seq_ms,
+        "batched_eager_ms": eager_ms, "ungrouped_eager_ms": ungrouped_ms, "sequential_ms": seq_ms,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -222,18 +222,28 @@ size_t rqlp_workspace_size_batched(int count, const rqlp_problem* problems, rqlp
  * (RQLP_FP64, RQLP_FP32 or RQLP_BF16_REFINED; dense A only) and its own
  * slice of the workspace.  The problems' launch sequences are spread over
  * four internal streams forked from and joined back into `stream`, so that
- * the single-workgroup factorizations and small products of different
- * problems overlap on the device.  Each result is bitwise the result of
+ * the small products of different problems overlap on the device.  With
+ * grouping on (the default, rqlp_set_batch_grouping), the problems advance
+ * in lockstep from one Cholesky factorization to the next, and the t-th
+ * factorizations (and explicit inverses) of all problems go out together as
+ * a few grouped launches, one workgroup (or 16, for the second pass's
+ * first-order form) per matrix.  Each result is bitwise the result of
  * rqlp_decompose on the same problem.  With rqlp_set_graphs enabled, a batch
  * submitted twice in a row with identical descriptors and workspace is
- * captured into a HIP graph on its second submission and replayed on later
- * ones.  The info record covers the whole batch.  `problems` is read
+ * captured into a HIP graph (ungrouped form) on its second submission and
+ * replayed on later ones.  The info record covers the whole batch.  `problems` is read
  * during the call only. */
 rqlp_status rqlp_decompose_batched(rqlp_ctx* ctx, int count, const rqlp_problem* problems,
                                    rqlp_precision prec, void* workspace, size_t ws_bytes, void* stream);
 
 /* Turn graph capture and replay of repeated batches on (1) or off (0). */
 rqlp_status rqlp_set_graphs(rqlp_ctx* ctx, int enabled);
+
+/* Turn the grouped (lockstep) factorizations of batches on (1, default) or
+ * off (0: every problem's launch sequence runs on its stream unchanged).
+ * The results are the same bits either way.  A batch captured into a graph
+ * (rqlp_set_graphs) always takes the ungrouped form. */
+rqlp_status rqlp_set_batch_grouping(rqlp_ctx* ctx, int enabled);
 
 /* ---- Serving: continuous batching of requests ---- */
 

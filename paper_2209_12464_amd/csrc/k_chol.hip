@@ -142,7 +142,7 @@ __device__ inline void diag_step4(doublex4& a, doublex4& x, int lane, int lr, in
 __device__ inline bool chol_fast_path(const double* __restrict__ G, int d, int dp, double* __restrict__ R,
                                       double* __restrict__ Rinv16, int32_t* __restrict__ flags, double fast_tol,
                                       const double* __restrict__ esq, int nesq, int32_t* __restrict__ mode,
-                                      double* __restrict__ Xfull, double* red, int nw) {
+                                      double* __restrict__ Xfull, double* red, int nw, int bid, int nblk) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   double ss = 0.0;
@@ -153,7 +153,7 @@ __device__ inline bool chol_fast_path(const double* __restrict__ G, int d, int d
   double tot = 0.0;
   for (int w = 0; w < nw; ++w) tot += red[w];
   if (tot < fast_tol * fast_tol) {  // false for NaN
-    for (int e = blockIdx.x * blockDim.x + tid; e < dp * dp; e += gridDim.x * blockDim.x) {
+    for (int e = bid * blockDim.x + tid; e < dp * dp; e += nblk * blockDim.x) {
       const int i = e / dp, j = e - (e / dp) * dp;
       double f = 0.0;  // F[i][j]
       if (i < d && j < d && i <= j) {
@@ -166,8 +166,8 @@ __device__ inline bool chol_fast_path(const double* __restrict__ G, int d, int d
       if ((i >> 4) == (j >> 4))
         Rinv16[(int64_t)(i >> 4) * kTile * kTile + (i & 15) * kTile + (j & 15)] = id - f;
     }
-    for (int i = blockIdx.x * blockDim.x + tid; i < dp; i += gridDim.x * blockDim.x) flags[i] = 0;
-    if (blockIdx.x == 0 && tid == 0) *mode = 2;  // explicit inverse already written
+    for (int i = bid * blockDim.x + tid; i < dp; i += nblk * blockDim.x) flags[i] = 0;
+    if (bid == 0 && tid == 0) *mode = 2;  // explicit inverse already written
     return true;
   }
   __syncthreads();
@@ -179,8 +179,11 @@ __device__ inline bool chol_fast_path(const double* __restrict__ G, int d, int d
 // set to 1 or 0.  As a diagonal block of a larger factorization (block =
 // 1): nothing is done when *mode == 2, the dependence test takes the
 // original diagonal from gdiag0, and *mode is only lowered to 0.
+// The body is shared by the one-matrix kernel and the grouped kernel that
+// factors many matrices in one launch (bid, nblk: this workgroup's index
+// and the workgroup count of its matrix).
 template <int NW, int SLOTS>
-__global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict__ G, int ld, int d, int dp,
+__device__ __attribute__((always_inline)) inline void chol_body(const double* __restrict__ G, int ld, int d, int dp,
                                                     double* __restrict__ R,
                                                     double* __restrict__ Rinv16,
                                                     int32_t* __restrict__ flags, DevInfo* info,
@@ -188,7 +191,7 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
                                                     const double* __restrict__ esq, int nesq,
                                                     int32_t* __restrict__ mode,
                                                     double* __restrict__ Xfull,
-                                                    const double* __restrict__ gdiag0, int block) {
+                                                    const double* __restrict__ gdiag0, int block, int bid, int nblk) {
   __shared__ double Pn[kCholRegMax / kTile][kTile][kTile + 1];  // panel tiles L_ik of column k
   __shared__ double Di[kTile][kTile + 1];                        // inverse of the diagonal factor
   __shared__ double Gdiag[kCholRegMax];
@@ -203,10 +206,10 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
   if (block) {
     if (*mode == 2) return;
   } else if (fast_tol > 0.0 &&
-             chol_fast_path(G, d, dp, R, Rinv16, flags, fast_tol, esq, nesq, mode, Xfull, red, NW)) {
+             chol_fast_path(G, d, dp, R, Rinv16, flags, fast_tol, esq, nesq, mode, Xfull, red, NW, bid, nblk)) {
     return;
   }
-  if (blockIdx.x != 0) return;  // the factorization runs in one workgroup
+  if (bid != 0) return;  // the factorization runs in one workgroup
 
   // ---------------- full factorization ----------------
   for (int i = tid; i < dp; i += blockDim.x) {
@@ -355,6 +358,28 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
   }
 }
 
+template <int NW, int SLOTS>
+__global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict__ G, int ld, int d, int dp,
+                                                    double* __restrict__ R, double* __restrict__ Rinv16,
+                                                    int32_t* __restrict__ flags, DevInfo* info, int pass_id,
+                                                    double tol, double fast_tol, const double* __restrict__ esq,
+                                                    int nesq, int32_t* __restrict__ mode,
+                                                    double* __restrict__ Xfull, const double* __restrict__ gdiag0,
+                                                    int block) {
+  chol_body<NW, SLOTS>(G, ld, d, dp, R, Rinv16, flags, info, pass_id, tol, fast_tol, esq, nesq, mode, Xfull, gdiag0,
+                       block, blockIdx.x, gridDim.x);
+}
+
+// Many independent matrices (dp <= 256, one register-slot class) in one
+// launch: matrix blockIdx.x / g.per, its workgroup blockIdx.x % g.per.
+template <int NW, int SLOTS>
+__global__ __launch_bounds__(NW * 64) void chol_grouped_kernel(CholGroup g) {
+  const int p = blockIdx.x / g.per;
+  const CholArgs& a = g.a[p];
+  chol_body<NW, SLOTS>(a.G, a.dp, a.d, a.dp, a.R, a.Rinv16, a.flags, (DevInfo*)a.info, a.pass_id, a.tol, a.fast_tol,
+                       a.esq, a.nesq, a.mode, a.Xfull, nullptr, 0, blockIdx.x - p * g.per, g.per);
+}
+
 // ---------------- d > 256: blocked over register-sized diagonal blocks ----------------
 // The matrix is cut into nb diagonal blocks of at most 256 columns.  For
 // each block b in turn: R_bb = chol(G_bb) (chol_kernel in block mode), then,
@@ -374,7 +399,7 @@ __global__ __launch_bounds__(1024) void chol_prep_kernel(const double* __restric
                                                       double* __restrict__ gd0) {
   __shared__ double red[16];
   if (fast_tol > 0.0 &&
-      chol_fast_path(G, d, dp, R, Rinv16, flags, fast_tol, esq, nesq, mode, Xfull, red, 16))
+      chol_fast_path(G, d, dp, R, Rinv16, flags, fast_tol, esq, nesq, mode, Xfull, red, 16, blockIdx.x, gridDim.x))
     return;
   if (blockIdx.x != 0) return;
   for (int i = threadIdx.x; i < dp; i += blockDim.x) gd0[i] = (i < d) ? G[(int64_t)i * dp + i] : 1.0;
@@ -500,6 +525,37 @@ hipError_t launch_chol(double* G, int d, int dp, double* R, double* Rinv16, int3
   }
   if (ev1) (void)hipEventRecord(ev1, s);
   if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+int chol_slot_class(int dp) {
+  const int T = dp / kTile;
+  const int tiles = T * (T + 1) / 2;
+  return tiles <= 8 * 7 ? 7 : (tiles <= 8 * 14 ? 14 : 17);
+}
+
+hipError_t launch_chol_grouped(const CholArgs* args, int count, hipStream_t s) {
+  for (const int cls : {7, 14, 17})
+  for (const int per : {1, 16}) {  // extra workgroups per matrix only help the fast path
+    CholGroup g;
+    g.count = 0;
+    g.per = per;
+    auto flush = [&]() {
+      if (g.count == 0) return;
+      const dim3 grid((unsigned)(g.count * g.per));
+      if (cls == 7) hipLaunchKernelGGL((chol_grouped_kernel<8, 7>), grid, dim3(8 * kWave), 0, s, g);
+      else if (cls == 14) hipLaunchKernelGGL((chol_grouped_kernel<8, 14>), grid, dim3(8 * kWave), 0, s, g);
+      else hipLaunchKernelGGL((chol_grouped_kernel<8, 17>), grid, dim3(8 * kWave), 0, s, g);
+      g.count = 0;
+    };
+    for (int i = 0; i < count; ++i) {
+      if (args[i].dp > kCholRegMax) return hipErrorInvalidValue;
+      if (chol_slot_class(args[i].dp) != cls || (args[i].fast_tol > 0.0 ? 16 : 1) != per) continue;
+      g.a[g.count++] = args[i];
+      if (g.count == kCholGroup) flush();
+    }
+    flush();
+  }
   return hipGetLastError();
 }
 

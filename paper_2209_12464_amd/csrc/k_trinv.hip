@@ -22,15 +22,16 @@ namespace rqlp {
 // kInvWaves waves; up to kInvT block rows (grid = number of block rows,
 // dp is the row stride of R and X); R tiles are loaded kInvAhead steps
 // before they are used.
+// The body is shared by the one-matrix kernel and the grouped kernel
+// (J: the column block this workgroup forms).
 template <int kInvWaves, int kInvT, int kInvAhead>
-__global__ __launch_bounds__(kInvWaves * 64) void trinv_kernel(const double* __restrict__ R,
+__device__ __attribute__((always_inline)) inline void trinv_body(const double* __restrict__ R,
                                                                const double* __restrict__ Rinv16, int dp,
                                                                const int32_t* __restrict__ mode, int any_factor,
-                                                               double* __restrict__ X) {
+                                                               double* __restrict__ X, const int J) {
   constexpr int kInvRows = (kInvT + kInvWaves - 1) / kInvWaves;  // block rows per wave
   __shared__ double Zs[2][kTile][kTile + 1];
   if (any_factor ? *mode == 2 : *mode != 1) return;
-  const int J = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane >> 4, lc = lane & 15;
@@ -112,6 +113,44 @@ __global__ __launch_bounds__(kInvWaves * 64) void trinv_kernel(const double* __r
   [&]<int... Is>(std::integer_sequence<int, Is...>) {
     (step(std::integral_constant<int, kInvT - 1 - Is>{}), ...);
   }(std::make_integer_sequence<int, kInvT>{});
+}
+
+template <int kInvWaves, int kInvT, int kInvAhead>
+__global__ __launch_bounds__(kInvWaves * 64) void trinv_kernel(const double* __restrict__ R,
+                                                               const double* __restrict__ Rinv16, int dp,
+                                                               const int32_t* __restrict__ mode, int any_factor,
+                                                               double* __restrict__ X) {
+  trinv_body<kInvWaves, kInvT, kInvAhead>(R, Rinv16, dp, mode, any_factor, X, blockIdx.x);
+}
+
+// Many matrices in one launch: workgroups start[p] .. start[p + 1] - 1 form
+// the column blocks of matrix p.
+__global__ __launch_bounds__(8 * 64) void trinv_grouped_kernel(TrinvGroup g) {
+  int p = 0;
+  while (p + 1 < g.count && g.start[p + 1] <= (int)blockIdx.x) ++p;
+  const TrinvArgs& a = g.a[p];
+  trinv_body<8, kCholRegMax / kTile, 4>(a.R, a.Rinv16, a.dp, a.mode, 0, a.X, (int)blockIdx.x - g.start[p]);
+}
+
+hipError_t launch_trinv_grouped(const TrinvArgs* args, int count, hipStream_t s) {
+  TrinvGroup g;
+  g.count = 0;
+  g.start[0] = 0;
+  auto flush = [&]() {
+    if (g.count == 0) return;
+    hipLaunchKernelGGL(trinv_grouped_kernel, dim3((unsigned)g.start[g.count]), dim3(8 * kWave), 0, s, g);
+    g.count = 0;
+    g.start[0] = 0;
+  };
+  for (int i = 0; i < count; ++i) {
+    if (args[i].dp > kCholRegMax) return hipErrorInvalidValue;
+    g.a[g.count] = args[i];
+    g.start[g.count + 1] = g.start[g.count] + args[i].dp / kTile;
+    ++g.count;
+    if (g.count == kTrinvGroup) flush();
+  }
+  flush();
+  return hipGetLastError();
 }
 
 hipError_t launch_trinv(const double* R, const double* Rinv16, int dp, const int32_t* mode, double* X,

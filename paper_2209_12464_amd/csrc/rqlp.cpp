@@ -44,9 +44,26 @@ struct rqlp_ctx {
   struct GraphEntry { std::vector<uint8_t> key; hipGraphExec_t exec; };
   std::vector<GraphEntry> graph_cache;
   std::vector<uint8_t> last_key;  // the last batch run eagerly
+  // Lockstep batches: the launch sequence of every problem is walked once
+  // per segment (the work up to the next Cholesky factorization); only the
+  // target segment's kernels are enqueued, and the factorization closing it
+  // is recorded, so that the factorizations of all problems go out as a few
+  // grouped launches.
+  struct Lockstep {
+    int target = 0, seg = 0;
+    std::vector<CholArgs> chol;     // register-tile factorizations (dp <= 256)
+    std::vector<TrinvArgs> trinv;   // their explicit inverses
+    struct Big { double *G, *R, *rinv, *xf, *esq; int32_t *flags, *mode; int d, dp, pass_id, nesq; double ftol; };
+    std::vector<Big> big;           // blocked factorizations, one launch sequence each
+  };
+  bool lockstep = true;
+  Lockstep* lock = nullptr;
 };
 
 namespace {
+
+// False while a lockstep walk passes over a segment other than its target.
+inline bool live(const rqlp_ctx* c) { return !c->lock || c->lock->seg == c->lock->target; }
 
 #define HIP_TRY(expr)                                   \
   do {                                                  \
@@ -231,6 +248,31 @@ uint64_t completion_key(int orth_index, int pass) {
   return kSketchKey1 + 1 + 2 * (uint64_t)orth_index + (uint64_t)pass;
 }
 
+// R = chol(G) and its explicit inverse for one CholeskyQR pass (R: r1 or r2,
+// flags and mode of that pass).  In a lockstep walk the factorization that
+// closes the target segment is recorded instead, and every later launch of
+// the walk is skipped.
+hipError_t factor(rqlp_ctx* c, const Bufs& b, double* R, int32_t* flags, int d, int dp, int orth_index,
+                  double ftol, int32_t* mode, int nesq, hipStream_t s) {
+  if (!c->lock) {
+    EvPair t = timer(c, RQLP_KT_CHOL);
+    hipError_t e = launch_chol(b.g, d, dp, R, b.rinv, flags, c->info, orth_index, ftol, b.esq, nesq, mode, b.xf,
+                               b.esq + nesq, s, t.a, t.b);
+    if (e != hipSuccess) return e;
+    return launch_trinv(R, b.rinv, dp, mode, b.xf, s);
+  }
+  rqlp_ctx::Lockstep& L = *c->lock;
+  if (L.seg++ != L.target) return hipSuccess;
+  if (dp <= kCholRegMax) {
+    L.chol.push_back(CholArgs{b.g, R, b.rinv, flags, c->info, b.esq, mode, b.xf, 64.0 * (double)d * 2.220446049250313e-16,
+                              ftol, d, dp, orth_index, nesq});
+    L.trinv.push_back(TrinvArgs{R, b.rinv, mode, b.xf, dp});
+  } else {
+    L.big.push_back({b.g, R, b.rinv, b.xf, b.esq, flags, mode, d, dp, orth_index, nesq, ftol});
+  }
+  return hipSuccess;
+}
+
 // orth()/qr() of a rows x d matrix Y (ld ldy) by CholeskyQR2.  Pass 1 writes
 // the float64 basis Q1; pass 2 writes out1 (ld1, ncols1 columns) and
 // optionally out2.  R1, R2 and the flags of both passes stay in `b`.
@@ -244,24 +286,24 @@ rqlp_status cholqr2(rqlp_ctx* c, const T* Y, int64_t ldy, int64_t rows, int d, c
   int32_t* mode = b.flags + 2 * dp;
   const int nesq = gram_reduce_blocks(dp);
   EvPair t;
-  t = timer(c, RQLP_KT_GRAM);
-  HIP_TRY(launch_gram<T>(Y, ldy, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
-  t = timer(c, RQLP_KT_CHOL);
-  HIP_TRY(launch_chol(b.g, d, dp, b.r1, b.rinv, b.flags, c->info, orth_index, 0.0, b.esq, nesq, mode, b.xf,
-                      b.esq + nesq, s, t.a, t.b));
-  HIP_TRY(launch_trinv(b.r1, b.rinv, dp, mode, b.xf, s));
-  t = timer(c, RQLP_KT_APPLY);
-  HIP_TRY((launch_apply<T, double>(Y, ldy, rows, d, dp, b.r1, b.rinv, b.flags, mode, b.xf, b.q1, dp, dp, nullptr,
-                                   0, 0, seed, completion_key(orth_index, 0), s, t.a, t.b)));
-  t = timer(c, RQLP_KT_GRAM);
-  HIP_TRY(launch_gram<double>(b.q1, dp, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
-  t = timer(c, RQLP_KT_CHOL);
-  HIP_TRY(launch_chol(b.g, d, dp, b.r2, b.rinv, b.flags + dp, c->info, orth_index, ftol, b.esq, nesq, mode + 1,
-                      b.xf, b.esq + nesq, s, t.a, t.b));
-  HIP_TRY(launch_trinv(b.r2, b.rinv, dp, mode + 1, b.xf, s));
-  t = timer(c, RQLP_KT_APPLY);
-  HIP_TRY((launch_apply<double, T>(b.q1, dp, rows, d, dp, b.r2, b.rinv, b.flags + dp, mode + 1, b.xf, out1, ld1,
-                                   ncols1, out2, ld2, ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b)));
+  if (live(c)) {
+    t = timer(c, RQLP_KT_GRAM);
+    HIP_TRY(launch_gram<T>(Y, ldy, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
+  }
+  HIP_TRY(factor(c, b, b.r1, b.flags, d, dp, orth_index, 0.0, mode, nesq, s));
+  if (live(c)) {
+    t = timer(c, RQLP_KT_APPLY);
+    HIP_TRY((launch_apply<T, double>(Y, ldy, rows, d, dp, b.r1, b.rinv, b.flags, mode, b.xf, b.q1, dp, dp, nullptr,
+                                     0, 0, seed, completion_key(orth_index, 0), s, t.a, t.b)));
+    t = timer(c, RQLP_KT_GRAM);
+    HIP_TRY(launch_gram<double>(b.q1, dp, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
+  }
+  HIP_TRY(factor(c, b, b.r2, b.flags + dp, d, dp, orth_index, ftol, mode + 1, nesq, s));
+  if (live(c)) {
+    t = timer(c, RQLP_KT_APPLY);
+    HIP_TRY((launch_apply<double, T>(b.q1, dp, rows, d, dp, b.r2, b.rinv, b.flags + dp, mode + 1, b.xf, out1, ld1,
+                                     ncols1, out2, ld2, ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b)));
+  }
   return RQLP_OK;
 }
 
@@ -311,23 +353,23 @@ rqlp_status run_method(rqlp_ctx* c, char* base, const Layout& Lo, int64_t m, int
   rqlp_status st;
   if (c->reset_info) HIP_TRY(launch_info_reset(c->info, s));
   // Omega (n x d, ld dp), then Y = A Omega and Q = orth(Y)
-  HIP_TRY(launch_gaussian<T>(seed, kSketchKey1, n, d, om, dp, s));
-  if ((st = mulA(om, yb)) != RQLP_OK) return st;
+  if (live(c)) HIP_TRY(launch_gaussian<T>(seed, kSketchKey1, n, d, om, dp, s));
+  if (live(c) && (st = mulA(om, yb)) != RQLP_OK) return st;
   int oi = 1;
   if ((st = cholqr2<T>(c, yb, dp, m, d, b, qi, dp, dp, q == 0 ? Q : nullptr, d, d, seed, oi++, s)) != RQLP_OK)
     return st;
   for (int it = 1; it <= q; ++it) {
     // W = orth(A^T Q) (stored in the Omega buffer), Q = orth(A W)
-    if ((st = mulAt(qi, yb)) != RQLP_OK) return st;
+    if (live(c) && (st = mulAt(qi, yb)) != RQLP_OK) return st;
     if ((st = cholqr2<T>(c, yb, dp, n, d, b, om, dp, dp, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
-    if ((st = mulA(om, yb)) != RQLP_OK) return st;
+    if (live(c) && (st = mulA(om, yb)) != RQLP_OK) return st;
     if ((st = cholqr2<T>(c, yb, dp, m, d, b, qi, dp, dp, it == q ? Q : nullptr, d, d, seed, oi++, s)) != RQLP_OK)
       return st;
   }
   // B^T = A^T Q; [V, R] = qr(B^T); L = R^T
-  if ((st = mulAt(qi, yb)) != RQLP_OK) return st;
+  if (live(c) && (st = mulAt(qi, yb)) != RQLP_OK) return st;
   if ((st = cholqr2<T>(c, yb, dp, n, d, b, V, d, d, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
-  HIP_TRY(launch_form_l<T>(b.r2, b.r1, b.flags, d, dp, Lout, d, s));
+  if (live(c)) HIP_TRY(launch_form_l<T>(b.r2, b.r1, b.flags, d, dp, Lout, d, s));
   return RQLP_OK;
 }
 
@@ -422,7 +464,7 @@ rqlp_status decompose_dense_bf16(rqlp_ctx* c, const float* A, int64_t m, int64_t
   uint16_t* at = (uint16_t*)(base + Lo.at);
   uint16_t* xt = (uint16_t*)(base + Lo.xt);
   const int64_t ldn = bf16_ld(n), ldm = bf16_ld(m);
-  HIP_TRY(launch_cvt_bf16(A, lda, m, n, ab, ldn, at, ldm, s));
+  if (live(c)) HIP_TRY(launch_cvt_bf16(A, lda, m, n, ab, ldn, at, ldm, s));
   auto mulA = [&](const float* X, float* Y) -> rqlp_status {  // Y (m x dp) = A X, X n x dp
     HIP_TRY(launch_cvt_bf16_t(X, dp, n, dp, xt, ldn, s));
     EvPair t = timer(c, RQLP_KT_GEMM_NN);
@@ -507,8 +549,9 @@ rqlp_status make_lanes(rqlp_ctx* c) {
 
 // Enqueue the batch on `origin`: reset the info record, fork to the lanes,
 // problem i on lane i % kLanes with its own workspace slice, join back.
+// `grouped`: the lockstep form with grouped factorizations.
 rqlp_status run_batch(rqlp_ctx* c, int count, const rqlp_problem* probs, rqlp_precision prec, char* base,
-                      hipStream_t origin) {
+                      hipStream_t origin, bool grouped) {
   HIP_TRY(launch_info_reset(c->info, origin));
   HIP_TRY(hipEventRecord(c->fork, origin));
   const int nl = std::min(count, (int)rqlp_ctx::kLanes);
@@ -516,23 +559,87 @@ rqlp_status run_batch(rqlp_ctx* c, int count, const rqlp_problem* probs, rqlp_pr
   const uint32_t timing = c->timing;
   c->timing = 0;
   c->reset_info = false;
-  rqlp_status st = RQLP_OK;
-  size_t off = 0;
-  for (int i = 0; i < count && st == RQLP_OK; ++i) {
-    const rqlp_problem& P = probs[i];
-    const size_t need = problem_ws_bytes(P, prec);
-    hipStream_t s = c->lanes[i % rqlp_ctx::kLanes];
-    char* ws = base + off;
-    off += need;
-    if (prec == RQLP_FP64)
-      st = decompose_dense<double>(c, (const double*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (double*)P.Q,
-                                   (double*)P.L, (double*)P.V, ws, need, s);
-    else if (prec == RQLP_BF16_REFINED)
-      st = decompose_dense_bf16(c, (const float*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (float*)P.Q,
-                                (float*)P.L, (float*)P.V, ws, need, s);
-    else
-      st = decompose_dense<float>(c, (const float*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (float*)P.Q,
+  auto walk = [&]() -> rqlp_status {  // every problem's launch sequence, problem i on lane i % kLanes
+    rqlp_status st = RQLP_OK;
+    size_t off = 0;
+    for (int i = 0; i < count && st == RQLP_OK; ++i) {
+      const rqlp_problem& P = probs[i];
+      const size_t need = problem_ws_bytes(P, prec);
+      hipStream_t s = c->lanes[i % rqlp_ctx::kLanes];
+      char* ws = base + off;
+      off += need;
+      if (c->lock) c->lock->seg = 0;
+      if (prec == RQLP_FP64)
+        st = decompose_dense<double>(c, (const double*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (double*)P.Q,
+                                     (double*)P.L, (double*)P.V, ws, need, s);
+      else if (prec == RQLP_BF16_REFINED)
+        st = decompose_dense_bf16(c, (const float*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (float*)P.Q,
                                   (float*)P.L, (float*)P.V, ws, need, s);
+      else
+        st = decompose_dense<float>(c, (const float*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (float*)P.Q,
+                                    (float*)P.L, (float*)P.V, ws, need, s);
+    }
+    return st;
+  };
+  // every lane waits for the work enqueued so far on all lanes
+  auto lane_barrier = [&]() -> rqlp_status {
+    for (int l = 0; l < nl; ++l) HIP_TRY(hipEventRecord(c->join[l], c->lanes[l]));
+    for (int l = 0; l < nl; ++l)
+      for (int l2 = 0; l2 < nl; ++l2)
+        if (l2 != l) HIP_TRY(hipStreamWaitEvent(c->lanes[l], c->join[l2], 0));
+    return RQLP_OK;
+  };
+  rqlp_status st = RQLP_OK;
+  if (!grouped || count < 2) {
+    st = walk();
+  } else {
+    // Lockstep: segment t of every problem, then the t-th factorization of
+    // every problem as grouped launches spread over the lanes (chunks of
+    // one slot class; a chunk's inverses follow its factorizations on the
+    // same lane), then segment t + 1 ...
+    rqlp_ctx::Lockstep L;
+    c->lock = &L;
+    for (L.target = 0; st == RQLP_OK; ++L.target) {
+      L.chol.clear();
+      L.trinv.clear();
+      L.big.clear();
+      if ((st = walk()) != RQLP_OK) break;
+      if (L.chol.empty() && L.big.empty()) break;
+      if ((st = lane_barrier()) != RQLP_OK) break;
+      int lane = 0;
+      for (const int cls : {7, 14, 17}) {
+        for (const bool fast : {false, true}) {
+          std::vector<CholArgs> ca;
+          std::vector<TrinvArgs> ta;
+          auto flush = [&]() -> rqlp_status {
+            if (ca.empty()) return RQLP_OK;
+            hipStream_t s = c->lanes[lane++ % nl];
+            HIP_TRY(launch_chol_grouped(ca.data(), (int)ca.size(), s));
+            HIP_TRY(launch_trinv_grouped(ta.data(), (int)ta.size(), s));
+            ca.clear();
+            ta.clear();
+            return RQLP_OK;
+          };
+          for (size_t j = 0; j < L.chol.size() && st == RQLP_OK; ++j) {
+            if (chol_slot_class(L.chol[j].dp) != cls || (L.chol[j].fast_tol > 0.0) != fast) continue;
+            ca.push_back(L.chol[j]);
+            ta.push_back(L.trinv[j]);
+            if ((int)ca.size() == kCholGroup) st = flush();
+          }
+          if (st == RQLP_OK) st = flush();
+        }
+      }
+      for (size_t j = 0; j < L.big.size() && st == RQLP_OK; ++j) {
+        const rqlp_ctx::Lockstep::Big& g = L.big[j];
+        hipStream_t s = c->lanes[lane++ % nl];
+        if (launch_chol(g.G, g.d, g.dp, g.R, g.rinv, g.flags, c->info, g.pass_id, g.ftol, g.esq, g.nesq, g.mode,
+                        g.xf, g.esq + g.nesq, s, nullptr, nullptr) != hipSuccess ||
+            launch_trinv(g.R, g.rinv, g.dp, g.mode, g.xf, s) != hipSuccess)
+          st = RQLP_ERR_HIP;
+      }
+      if (st == RQLP_OK) st = lane_barrier();
+    }
+    c->lock = nullptr;
   }
   c->reset_info = true;
   c->timing = timing;
@@ -661,7 +768,7 @@ rqlp_status rqlp_decompose_batched(rqlp_ctx* c, int count, const rqlp_problem* p
   char* base = nullptr;
   if ((st = get_workspace(c, ws, ws_bytes, need, &base)) != RQLP_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  if (!c->graphs) return run_batch(c, count, probs, prec, base, s);
+  if (!c->graphs) return run_batch(c, count, probs, prec, base, s, c->lockstep);
   // graphs: a batch seen for the second time in a row (same problems,
   // buffers and workspace) is captured once and replayed from then on
   std::vector<uint8_t> key = batch_key(count, probs, prec, base, need);
@@ -672,11 +779,13 @@ rqlp_status rqlp_decompose_batched(rqlp_ctx* c, int count, const rqlp_problem* p
     }
   if (key != c->last_key) {
     c->last_key = key;
-    return run_batch(c, count, probs, prec, base, s);
+    return run_batch(c, count, probs, prec, base, s, c->lockstep);
   }
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-  st = run_batch(c, count, probs, prec, base, c->cap);
+  // captured batches keep every problem's sequence on its stream: the
+  // grouped form has not been validated under stream capture
+  st = run_batch(c, count, probs, prec, base, c->cap, false);
   const hipError_t e_end = hipStreamEndCapture(c->cap, &g);
   if (st != RQLP_OK) {
     if (g) hipGraphDestroy(g);
@@ -699,6 +808,13 @@ rqlp_status rqlp_decompose_batched(rqlp_ctx* c, int count, const rqlp_problem* p
 rqlp_status rqlp_set_graphs(rqlp_ctx* c, int enabled) {
   if (!c) return RQLP_ERR_INVALID_ARG;
   c->graphs = enabled != 0;
+  c->last_key.clear();
+  return RQLP_OK;
+}
+
+rqlp_status rqlp_set_batch_grouping(rqlp_ctx* c, int enabled) {
+  if (!c) return RQLP_ERR_INVALID_ARG;
+  c->lockstep = enabled != 0;
   c->last_key.clear();
   return RQLP_OK;
 }

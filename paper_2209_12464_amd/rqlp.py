@@ -77,6 +77,7 @@ def _lib():
             "rqlp_workspace_size_batched": (_SZ, [_INT, ctypes.POINTER(Problem), _INT]),
             "rqlp_decompose_batched": (_INT, [_P, _INT, ctypes.POINTER(Problem), _INT, _P, _SZ, _P]),
             "rqlp_set_graphs": (_INT, [_P, _INT]),
+            "rqlp_set_batch_grouping": (_INT, [_P, _INT]),
             "rqlp_workspace_size_paper": (_SZ, [_I64, _I64, _INT, _INT, _INT, _INT]),
             "rqlp_decompose_paper": (_INT, [_P, _P, _I64, _I64, _I64, _INT, _INT, _INT, _INT, _U64,
                                             _P, _P, _P, _P, _SZ, _P]),
@@ -107,6 +108,7 @@ def exported_symbols():
             "rqlp_orth", "rqlp_spmm", "rqlp_csr_transpose_workspace_size", "rqlp_csr_transpose",
             "rqlp_set_timing", "rqlp_set_timing_mask", "rqlp_get_timing",
             "rqlp_workspace_size_batched", "rqlp_decompose_batched", "rqlp_set_graphs",
+            "rqlp_set_batch_grouping",
             "rqlp_server_create", "rqlp_server_destroy", "rqlp_server_request_bytes", "rqlp_server_submit",
             "rqlp_server_poll", "rqlp_workspace_size_paper", "rqlp_decompose_paper"]
 
@@ -169,6 +171,10 @@ class Context:
     def set_graphs(self, enabled):
         """Capture a batch submitted twice in a row into a HIP graph and replay it."""
         _check(_lib().rqlp_set_graphs(self._h, 1 if enabled else 0), "rqlp_set_graphs")
+
+    def set_batch_grouping(self, enabled):
+        """Grouped (lockstep) factorizations in batches (on by default)."""
+        _check(_lib().rqlp_set_batch_grouping(self._h, 1 if enabled else 0), "rqlp_set_batch_grouping")
 
     def set_timing(self, enabled, classes=None):
         """Event timing of every kernel class, or only of `classes` (names

@@ -33,12 +33,14 @@ def _same(outs, ref):
         assert torch.equal(Q, Qr) and torch.equal(L, Lr) and torch.equal(V, Vr)
 
 
+@pytest.mark.parametrize("grouped", [True, False])
 @pytest.mark.parametrize("dtype,bf16", [(torch.float32, False), (torch.float64, False), (torch.float32, True)])
-def test_batched_equals_solo(gpu_lib, dtype, bf16):
-    announce("batched vs solo", dtype, bf16)
+def test_batched_equals_solo(gpu_lib, dtype, bf16, grouped):
+    announce("batched vs solo", dtype, bf16, "grouped" if grouped else "streams")
     reqs, As, params = _batch(dtype)
     ref = _solo(gpu_lib, As, params, bf16)
     ctx = gpu_lib.Context(0)
+    ctx.set_batch_grouping(grouped)
     outs = gpu_lib.decompose_batched(As, params, ctx=ctx, bf16=bf16)
     torch.cuda.synchronize()
     _same(outs, ref)
@@ -79,6 +81,38 @@ def test_graph_replays_match_eager(gpu_lib):
         gpu_lib.decompose_batched(As, params2, ctx=ctx, workspace=ws, outs=outs)
         torch.cuda.synchronize()
         _same(outs, ref2)
+
+
+def test_grouped_mixed_classes_and_blocked(gpu_lib):
+    """Grouped factorizations across every register-slot class, more
+    problems than one grouped launch holds, unequal q (problems leave the
+    lockstep at different segments), a dependent-column problem and one
+    blocked (d > 256) factorization: bitwise the solo results."""
+    announce("grouped mixed classes")
+    rng = np.random.default_rng(7)
+    As, params = [], []
+    ks = [6, 20, 50, 90, 120, 150, 200, 240, 250] * 3 + [300]
+    for i, k in enumerate(ks):
+        m, n = int(rng.integers(k + 40, k + 700)), int(rng.integers(k + 20, k + 400))
+        A = rng.standard_normal((m, n)).astype(np.float32)
+        As.append(to_dev(A))
+        params.append((k, 10 if k < 300 else 4, i % 3, 100 + i))
+    # rank 2 with k + p = 6: dependent columns in every pass
+    As.append(to_dev((np.outer(np.arange(1.0, 61.0), np.ones(40)) + np.outer(np.ones(60), np.arange(40.0)))
+                     .astype(np.float32)))
+    params.append((4, 2, 1, 9))
+    ref = _solo(gpu_lib, As, params)
+    ctx = gpu_lib.Context(0)
+    ws = gpu_lib.alloc_workspace(gpu_lib.workspace_size_batched(
+        [(A.shape[0], A.shape[1], k, p, q) for A, (k, p, q, s) in zip(As, params)], torch.float32), As[0].device)
+    outs = [tuple(torch.empty_like(x) for x in r) for r in ref]
+    for rep in range(2):  # the same workspace twice
+        for o in outs:
+            for x in o:
+                x.fill_(float("nan"))
+        gpu_lib.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs)
+        torch.cuda.synchronize()
+        _same(outs, ref)
 
 
 def test_batched_info_covers_batch(gpu_lib):
