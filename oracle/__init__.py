@@ -29,6 +29,7 @@ Module map:
   philox.py       counter-based generator and normal transform
   householder.py  Householder QR with positive diagonal
   ruqlp.py        the method (dense and CSR input)
+  svdlike.py      Remark 1: the SVD-like form from an SVD of the d x d factor
   csr.py          CSR products and the CSR transpose, by definition
   metrics.py      reconstruction differences and errors, blockwise
   bf16.py         round-to-nearest-even to bfloat16, by bit definition
@@ -40,5 +41,6 @@ or "parity unpinned").
 from .philox import philox4x64_10, gaussian_matrix, uniform_pair, box_muller  # noqa: F401
 from .householder import householder_qr  # noqa: F401
 from .ruqlp import ruqlp, ruqlp_csr, ruqlp_paper, orth  # noqa: F401
+from .svdlike import svd_small, svd_like, ruqlp_svd  # noqa: F401
 from .csr import csr_matmul, csr_transpose  # noqa: F401
 from .metrics import recon_diff, recon_error, orth_error, recon_error_csr  # noqa: F401
