@@ -42,6 +42,9 @@ WORKLOADS = {
     "paper_dense8000": dict(kind="dense", m=8000, n=8000, k=200, p=10, q=1, dtype="f32", spectrum="gapped",
                             paper=True),
     # a batch of 64 uneven requests of the serving stream (float32, q = 1)
+    # the same 8000^2 workload in the SVD-like form of Remark 1
+    "svd_dense8000": dict(kind="dense", m=8000, n=8000, k=200, p=10, q=1, dtype="f32", spectrum="gapped",
+                          svd=True),
     "batch64": dict(kind="batch", count=64, q=1, dtype="f32"),
     # the serving stream: 4096 Poisson-arrival requests over 64 distinct matrices
     "serve4096": dict(kind="serve", count=4096, pool=64, q=1, dtype="f32", slots=8, budget_gb=8.0),
@@ -123,6 +126,7 @@ METRIC_NAMES = {
     "dense8000": "RU-QLP GFLOP/s (8000^2 FP32, k=200, p=10, q=1)",
     "bf16_20000x15000": "RU-QLP GFLOP/s (20000x15000, k=500, p=20, q=1, BF16 products + FP32 accumulation)",
     "paper_dense8000": "RU-QLP GFLOP/s (8000^2 FP32, k=200, p=10, q=1, row-sketch orientation of Algorithm 1)",
+    "svd_dense8000": "RU-QLP SVD-like form GFLOP/s (8000^2 FP32, k=200, p=10, q=1, Remark 1)",
 }
 
 
@@ -364,6 +368,9 @@ def cpu_baseline(w, A_host, seed, flops):
         return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
                 "sample": (f"one decomposition of the same recipe at half size ({mh}x{nh}, k={kh}, p={ph}, "
                            f"q={w['q']}), bfloat16 operand rounding emulated"), "seconds": dt}
+    elif w["kind"] == "dense" and w.get("svd"):
+        oracle.ruqlp_svd(A_host.astype(np.float64), w["k"], w["p"], w["q"], seed, omega_dtype="f32")
+        sample = f"one full SVD-like decomposition of the same {w['m']}x{w['n']} workload (q={w['q']})"
     elif w["kind"] == "dense" and w.get("paper"):
         oracle.ruqlp_paper(A_host.astype(np.float64), w["k"], w["p"], w["q"], seed, omega_dtype="f32")
         sample = f"one full decomposition of the same {w['m']}x{w['n']} workload (q={w['q']}), row-sketch orientation"
@@ -459,6 +466,19 @@ def record_traffic(workload, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv,
     print(json.dumps({workload: out}, indent=1), flush=True)
 
 
+def time_svd_small(rqlp, ctx, A, k, p, q, seed, torch, reps=10):
+    """Time of the d x d SVD alone (rqlp_svd_small on this workload's L)."""
+    _, L, _ = rqlp.decompose(A, k, p, q, seed=seed, ctx=ctx)
+    ws = rqlp.alloc_workspace(int(rqlp._lib().rqlp_svd_workspace_size(k + p)), A.device)
+    out = rqlp.svd_small(L, ctx=ctx, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rqlp.svd_small(L, ctx=ctx, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -508,7 +528,18 @@ def main():
         m, n = A.shape
         out = (torch.empty((m, d), dtype=A.dtype, device=dev), torch.empty((d, d), dtype=A.dtype, device=dev),
                torch.empty((n, d), dtype=A.dtype, device=dev))
-        if w.get("paper"):
+        svd_small_ms = None
+        if w.get("svd"):
+            # the decomposition's work plus the two products Q U-bar and V V-bar
+            # (the small SVD's iteration count depends on the input: not counted)
+            flops = f_alg(m, n, k, p, q) + 2.0 * (m + n) * d * d
+            ws = rqlp.alloc_workspace(rqlp.workspace_size_svd(m, n, k, p, q, A.dtype), dev)
+            out = (torch.empty((m, d), dtype=A.dtype, device=dev), torch.empty((d,), dtype=A.dtype, device=dev),
+                   torch.empty((n, d), dtype=A.dtype, device=dev))
+            step = lambda: rqlp.decompose_svd(A, k, p, q, seed=args.seed, ctx=ctx, workspace=ws,  # noqa: E731
+                                              out=out)
+            svd_small_ms = time_svd_small(rqlp, ctx, A, k, p, q, args.seed, torch)
+        elif w.get("paper"):
             flops = f_alg_paper(m, n, k, p, q)
             ws = rqlp.alloc_workspace(int(rqlp._lib().rqlp_workspace_size_paper(m, n, k, p, q, rqlp._prec(A.dtype))),
                                       dev)
@@ -601,6 +632,7 @@ def main():
         "roofline": roofline,
         "kernels": per_kernel,
         **({"vs_fp32_same_gpu": vs_fp32} if vs_fp32 else {}),
+        **({"svd_small_ms": svd_small_ms} if w["kind"] == "dense" and w.get("svd") else {}),
         "info": info,
     }
     if not args.no_cpu_baseline:

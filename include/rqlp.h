@@ -198,6 +198,33 @@ rqlp_status rqlp_decompose_paper(rqlp_ctx* ctx, const void* A, int64_t m, int64_
                                  int q, rqlp_precision prec, uint64_t seed, void* Q, void* L, void* P,
                                  void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- The SVD-like form (Remark 1 of Section III-B) ---- */
+
+/* SVD of a small square matrix, M = U diag(S) V^T (Remark 1: an SVD of the
+ * d x d middle factor).  M, U, V: d x d row-major device matrices with
+ * leading dimensions ldm, ldu, ldv >= d (M is read only); S: d device
+ * values.  d <= 544; RQLP_FP64 or RQLP_FP32 (the iteration is float64 in
+ * both).  Conventions: S descending; each pair of singular vectors signed so
+ * that the entry of largest magnitude of the V column is positive (the
+ * first on ties); the U column of a singular value that is exactly zero is
+ * zero.  One-sided Jacobi; when it has not converged within 40 sweeps the
+ * info record's status is RQLP_ERR_NUMERICAL.  Workspace as elsewhere
+ * (rqlp_svd_workspace_size bytes, or NULL). */
+size_t rqlp_svd_workspace_size(int d);
+rqlp_status rqlp_svd_small(rqlp_ctx* ctx, const void* M, int d, int64_t ldm, void* U, int64_t ldu, void* S,
+                           void* V, int64_t ldv, rqlp_precision prec, void* workspace, size_t ws_bytes,
+                           void* stream);
+
+/* RU-QLP in its SVD-like form (Remark 1): A ~ Q L V^T as by rqlp_decompose,
+ * then L = U-bar diag(S) V-bar^T (rqlp_svd_small's conventions), U = Q U-bar
+ * (m x d) and W = V V-bar (n x d), so that A ~ U diag(S) W^T.  U, W: leading
+ * dimension d; S: d values.  Precisions as for rqlp_decompose (the bfloat16
+ * form computes the SVD and the two products in float32); dense A. */
+size_t rqlp_workspace_size_svd(int64_t m, int64_t n, int k, int p, int q, rqlp_precision prec);
+rqlp_status rqlp_decompose_svd(rqlp_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda, int k, int p,
+                               int q, rqlp_precision prec, uint64_t seed, void* U, void* S, void* W,
+                               void* workspace, size_t ws_bytes, void* stream);
+
 /* ---- Batches of dense decompositions ---- */
 
 /* One decomposition of a batch: A (m x n, lda >= n, device), k, p, q and

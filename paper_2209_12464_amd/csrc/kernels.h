@@ -141,6 +141,21 @@ struct TrinvGroup {
 // launch_trinv for `count` matrices (each dp <= 256) in few launches.
 hipError_t launch_trinv_grouped(const TrinvArgs* args, int count, hipStream_t s);
 
+// ---- SVD of the small factor (k_svd.hip) ----
+// M (d x d, row-major, ld ldm, d <= 544) = U diag(S) V^T: S descending, U
+// (ld ldu) and V (ld ldv) row-major d x d, each pair of singular vectors
+// signed so that the entry of largest magnitude of the V column is
+// positive; U columns of zero singular values are zero.  ws: svd_ws_bytes(d)
+// bytes of device memory.  info->status is set to 5 (numerical) when the
+// Jacobi iteration has not converged in kSvSweeps sweeps (one cooperative
+// launch runs them all).
+constexpr int kSvSweeps = 40;
+inline int svd_padded(int d) { return (d + 15) / 16 * 16; }
+size_t svd_ws_bytes(int d);
+template <typename T>
+hipError_t launch_svd_small(const T* M, int64_t ldm, int d, T* U, int64_t ldu, T* S, T* V, int64_t ldv, void* ws,
+                            void* info, hipStream_t s);
+
 // ---- triangular solve Q = Y R^-1 (k_apply.hip) ----
 // Y: rows x dp (ldy, type Tin); out1 (ld1, first `ncols1` columns, type
 // Tout) and optional out2 (ld2, first `ncols2` columns).  Dependent columns (flags) are replaced

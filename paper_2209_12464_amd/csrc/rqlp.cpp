@@ -663,6 +663,48 @@ std::vector<uint8_t> batch_key(int count, const rqlp_problem* probs, rqlp_precis
   return key;
 }
 
+// ---- the SVD-like form (Remark 1) ------------------------------------------
+
+// Workspace after the decomposition's own: the factors Q, L, V, the small
+// SVD's buffers, U-bar, V-bar and the partial slabs of the two products.
+struct SvdLayout { size_t q, l, v, svd, ub, vb, part, total; };
+
+SvdLayout svd_layout(int64_t m, int64_t n, int d, rqlp_precision prec) {
+  const size_t es = prec == RQLP_FP64 ? 8 : 4;
+  const int dp = padded_d(d);
+  SvdLayout L;
+  size_t off = 0;
+  auto put = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  L.q = put((size_t)m * d * es);
+  L.l = put((size_t)d * d * es);
+  L.v = put((size_t)n * d * es);
+  L.svd = put(svd_ws_bytes(d));
+  L.ub = put((size_t)d * d * es);
+  L.vb = put((size_t)d * d * es);
+  const size_t pe = prec == RQLP_FP64
+                        ? std::max(gemm_partial_elems<double>((int)m, d, dp), gemm_partial_elems<double>((int)n, d, dp))
+                        : std::max(gemm_partial_elems<float>((int)m, d, dp), gemm_partial_elems<float>((int)n, d, dp));
+  L.part = put(pe * es);
+  L.total = off;
+  return L;
+}
+
+// L = U-bar diag(S) V-bar^T, then U = Q U-bar and W = V V-bar.
+template <typename T>
+rqlp_status svd_like(rqlp_ctx* c, const SvdLayout& Ly, char* b, int64_t m, int64_t n, int d, T* U, T* S, T* W,
+                     hipStream_t s) {
+  T* Q = (T*)(b + Ly.q);
+  T* L = (T*)(b + Ly.l);
+  T* V = (T*)(b + Ly.v);
+  T* Ub = (T*)(b + Ly.ub);
+  T* Vb = (T*)(b + Ly.vb);
+  T* part = (T*)(b + Ly.part);
+  HIP_TRY(launch_svd_small<T>(L, d, d, Ub, d, S, Vb, d, b + Ly.svd, c->info, s));
+  rqlp_status st = gemm<T>(c, 0, Q, d, m, d, Ub, d, d, U, d, d, part, s, false);
+  if (st != RQLP_OK) return st;
+  return gemm<T>(c, 0, V, d, n, d, Vb, d, d, W, d, d, part, s, false);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -817,6 +859,69 @@ rqlp_status rqlp_set_batch_grouping(rqlp_ctx* c, int enabled) {
   c->lockstep = enabled != 0;
   c->last_key.clear();
   return RQLP_OK;
+}
+
+size_t rqlp_svd_workspace_size(int d) {
+  if (d < 1 || d > kDMax) return 0;
+  return svd_ws_bytes(d) + 256;
+}
+
+rqlp_status rqlp_svd_small(rqlp_ctx* c, const void* M, int d, int64_t ldm, void* U, int64_t ldu, void* S, void* V,
+                           int64_t ldv, rqlp_precision prec, void* ws, size_t ws_bytes, void* stream) {
+  if (!c || !M || !U || !S || !V || d < 1 || ldm < d || ldu < d || ldv < d ||
+      (prec != RQLP_FP64 && prec != RQLP_FP32))
+    return RQLP_ERR_INVALID_ARG;
+  if (d > kDMax) return RQLP_ERR_UNSUPPORTED;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  char* base = nullptr;
+  rqlp_status st = get_workspace(c, ws, ws_bytes, svd_ws_bytes(d) + 256, &base);
+  if (st != RQLP_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_info_reset(c->info, s));
+  if (prec == RQLP_FP64)
+    HIP_TRY(launch_svd_small<double>((const double*)M, ldm, d, (double*)U, ldu, (double*)S, (double*)V, ldv, base,
+                                     c->info, s));
+  else
+    HIP_TRY(launch_svd_small<float>((const float*)M, ldm, d, (float*)U, ldu, (float*)S, (float*)V, ldv, base, c->info,
+                                    s));
+  return RQLP_OK;
+}
+
+size_t rqlp_workspace_size_svd(int64_t m, int64_t n, int k, int p, int q, rqlp_precision prec) {
+  const size_t dec = rqlp_workspace_size(m, n, k, p, q, prec);
+  if (!dec) return 0;
+  return align256(dec) + svd_layout(m, n, k + p, prec).total + 256;
+}
+
+rqlp_status rqlp_decompose_svd(rqlp_ctx* c, const void* A, int64_t m, int64_t n, int64_t lda, int k, int p, int q,
+                               rqlp_precision prec, uint64_t seed, void* U, void* S, void* W, void* ws,
+                               size_t ws_bytes, void* stream) {
+  if (!c || !A || !U || !S || !W) return RQLP_ERR_INVALID_ARG;
+  rqlp_status st = check_common(m, n, k, p, q, prec);
+  if (st != RQLP_OK) return st;
+  if (lda < n) return RQLP_ERR_INVALID_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  const int d = k + p;
+  const size_t dec = align256(rqlp_workspace_size(m, n, k, p, q, prec));
+  const SvdLayout Ly = svd_layout(m, n, d, prec);
+  char* base = nullptr;
+  if ((st = get_workspace(c, ws, ws_bytes, dec + Ly.total + 256, &base)) != RQLP_OK) return st;
+  char* sb = base + dec;
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == RQLP_FP64) {
+    if ((st = decompose_dense<double>(c, (const double*)A, m, n, lda, k, p, q, seed, (double*)(sb + Ly.q),
+                                      (double*)(sb + Ly.l), (double*)(sb + Ly.v), base, dec, s)) != RQLP_OK)
+      return st;
+    return svd_like<double>(c, Ly, sb, m, n, d, (double*)U, (double*)S, (double*)W, s);
+  }
+  if (prec == RQLP_BF16_REFINED)
+    st = decompose_dense_bf16(c, (const float*)A, m, n, lda, k, p, q, seed, (float*)(sb + Ly.q), (float*)(sb + Ly.l),
+                              (float*)(sb + Ly.v), base, dec, s);
+  else
+    st = decompose_dense<float>(c, (const float*)A, m, n, lda, k, p, q, seed, (float*)(sb + Ly.q),
+                                (float*)(sb + Ly.l), (float*)(sb + Ly.v), base, dec, s);
+  if (st != RQLP_OK) return st;
+  return svd_like<float>(c, Ly, sb, m, n, d, (float*)U, (float*)S, (float*)W, s);
 }
 
 size_t rqlp_workspace_size_paper(int64_t m, int64_t n, int k, int p, int q, rqlp_precision prec) {

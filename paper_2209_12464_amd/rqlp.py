@@ -78,6 +78,11 @@ def _lib():
             "rqlp_decompose_batched": (_INT, [_P, _INT, ctypes.POINTER(Problem), _INT, _P, _SZ, _P]),
             "rqlp_set_graphs": (_INT, [_P, _INT]),
             "rqlp_set_batch_grouping": (_INT, [_P, _INT]),
+            "rqlp_svd_workspace_size": (_SZ, [_INT]),
+            "rqlp_svd_small": (_INT, [_P, _P, _INT, _I64, _P, _I64, _P, _P, _I64, _INT, _P, _SZ, _P]),
+            "rqlp_workspace_size_svd": (_SZ, [_I64, _I64, _INT, _INT, _INT, _INT]),
+            "rqlp_decompose_svd": (_INT, [_P, _P, _I64, _I64, _I64, _INT, _INT, _INT, _INT, _U64,
+                                          _P, _P, _P, _P, _SZ, _P]),
             "rqlp_workspace_size_paper": (_SZ, [_I64, _I64, _INT, _INT, _INT, _INT]),
             "rqlp_decompose_paper": (_INT, [_P, _P, _I64, _I64, _I64, _INT, _INT, _INT, _INT, _U64,
                                             _P, _P, _P, _P, _SZ, _P]),
@@ -108,7 +113,8 @@ def exported_symbols():
             "rqlp_orth", "rqlp_spmm", "rqlp_csr_transpose_workspace_size", "rqlp_csr_transpose",
             "rqlp_set_timing", "rqlp_set_timing_mask", "rqlp_get_timing",
             "rqlp_workspace_size_batched", "rqlp_decompose_batched", "rqlp_set_graphs",
-            "rqlp_set_batch_grouping",
+            "rqlp_set_batch_grouping", "rqlp_svd_workspace_size", "rqlp_svd_small",
+            "rqlp_workspace_size_svd", "rqlp_decompose_svd",
             "rqlp_server_create", "rqlp_server_destroy", "rqlp_server_request_bytes", "rqlp_server_submit",
             "rqlp_server_poll", "rqlp_workspace_size_paper", "rqlp_decompose_paper"]
 
@@ -268,6 +274,57 @@ def decompose_paper(A, k, p, q=0, seed=0, ctx=None, workspace=None, out=None):
                                        _ptr(L), _ptr(P), _ptr(workspace), ws_bytes, _stream(A.device)),
            "rqlp_decompose_paper")
     return Q, L, P
+
+
+def svd_small(M, ctx=None, workspace=None, out=None):
+    """SVD of a small square device matrix (float32 or float64, d <= 544):
+    returns (U, S, V) with M = U diag(S) V^T (rqlp_svd_small's conventions)."""
+    if M.dim() != 2 or M.shape[0] != M.shape[1] or M.stride(1) != 1:
+        raise ValueError("M must be a square row-major matrix")
+    ctx = ctx or default_context(M.device.index or 0)
+    d = M.shape[0]
+    if out is None:
+        U = torch.empty((d, d), dtype=M.dtype, device=M.device)
+        S = torch.empty((d,), dtype=M.dtype, device=M.device)
+        V = torch.empty((d, d), dtype=M.dtype, device=M.device)
+    else:
+        U, S, V = out
+    if workspace is None:
+        ws_bytes = int(_lib().rqlp_svd_workspace_size(d))
+        workspace = alloc_workspace(ws_bytes, M.device) if ws_bytes else None
+    ws_bytes = workspace.numel() if workspace is not None else 0
+    _check(_lib().rqlp_svd_small(ctx.handle, _ptr(M), d, M.stride(0), _ptr(U), U.stride(0), _ptr(S), _ptr(V),
+                                 V.stride(0), _prec(M.dtype), _ptr(workspace), ws_bytes, _stream(M.device)),
+           "rqlp_svd_small")
+    return U, S, V
+
+
+def workspace_size_svd(m, n, k, p, q, dtype, bf16=False):
+    return int(_lib().rqlp_workspace_size_svd(m, n, k, p, q, _prec(dtype, bf16)))
+
+
+def decompose_svd(A, k, p, q=0, seed=0, ctx=None, workspace=None, out=None, bf16=False):
+    """RU-QLP in its SVD-like form (Remark 1): returns (U, S, W) with
+    A ~ U diag(S) W^T."""
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D row-major tensor")
+    ctx = ctx or default_context(A.device.index or 0)
+    m, n = A.shape
+    d = k + p
+    prec = _prec(A.dtype, bf16)
+    if out is None:
+        U = torch.empty((m, d), dtype=A.dtype, device=A.device)
+        S = torch.empty((d,), dtype=A.dtype, device=A.device)
+        W = torch.empty((n, d), dtype=A.dtype, device=A.device)
+    else:
+        U, S, W = out
+    if workspace is None:
+        ws_bytes = int(_lib().rqlp_workspace_size_svd(m, n, k, p, q, prec))
+        workspace = alloc_workspace(ws_bytes, A.device) if ws_bytes else None
+    ws_bytes = workspace.numel() if workspace is not None else 0
+    _check(_lib().rqlp_decompose_svd(ctx.handle, _ptr(A), m, n, A.stride(0), k, p, q, prec, seed, _ptr(U), _ptr(S),
+                                     _ptr(W), _ptr(workspace), ws_bytes, _stream(A.device)), "rqlp_decompose_svd")
+    return U, S, W
 
 
 def _problems(As, params, outs):
