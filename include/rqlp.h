@@ -198,6 +198,32 @@ rqlp_status rqlp_decompose_paper(rqlp_ctx* ctx, const void* A, int64_t m, int64_
                                  int q, rqlp_precision prec, uint64_t seed, void* Q, void* L, void* P,
                                  void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- Autotuning of the products' split-K plans ---- */
+
+/* Time the split-K candidates of the two products a dense decomposition of
+ * this shape issues (Y = A X and Y = A^T X with d columns, float32 or
+ * float64 kernel; the products of Section III-A steps 2 and 4) and keep the
+ * fastest split count per product shape in the context's plan table; later
+ * calls on the context (decompositions, batches, servers, rqlp_gemm) use
+ * it.  The default plan fills about two workgroups per CU; candidates go up
+ * to four.  A (m x n, lda >= n) is only read; scratch comes from the
+ * context's internal workspace.  Synchronizes `stream`.  The chosen counts
+ * are returned in *nsplit_nn and *nsplit_tn (either may be NULL).  A plan
+ * changes the summation order of a product, so results are reproducible
+ * bit for bit for a given plan table, not across tables. */
+rqlp_status rqlp_autotune(rqlp_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda, int d,
+                          rqlp_precision prec, void* stream, int* nsplit_nn, int* nsplit_tn);
+/* Forget every tuned plan. */
+rqlp_status rqlp_autotune_clear(rqlp_ctx* ctx);
+/* Number of tuned product shapes in the table. */
+rqlp_status rqlp_autotune_count(rqlp_ctx* ctx, int* count);
+/* Write the plan table to a text file ("rqlp-plans 1", then one line
+ * "gemm <element bytes> <trans> <M> <N> <K> <nsplit>" per shape), or merge
+ * one read from such a file into the table (RQLP_ERR_INVALID_ARG, table
+ * unchanged, on a malformed file). */
+rqlp_status rqlp_autotune_save(rqlp_ctx* ctx, const char* path);
+rqlp_status rqlp_autotune_load(rqlp_ctx* ctx, const char* path);
+
 /* ---- The SVD-like form (Remark 1 of Section III-B) ---- */
 
 /* SVD of a small square matrix, M = U diag(S) V^T (Remark 1: an SVD of the

@@ -12,7 +12,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <fstream>
 #include <map>
+#include <string>
+#include <tuple>
 #include <new>
 #include <vector>
 
@@ -58,6 +61,8 @@ struct rqlp_ctx {
   };
   bool lockstep = true;
   Lockstep* lock = nullptr;
+  // autotuned split-K counts: (element bytes, trans, M, N, K) -> nsplit
+  std::map<std::tuple<int, int, int, int, int>, int> plan;
 };
 
 namespace {
@@ -148,10 +153,26 @@ GemmArgs<T> plan_gemm(int trans, const T* A, int64_t lda, const T* B, int64_t ld
   return g;
 }
 
+// Largest split-K count a plan may take (default or autotuned): enough
+// splits for about four workgroups per CU, none shorter than 256.
+int splitk_cap(int M, int K) {
+  const int64_t mt = ceil_div(M, 128);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(1024 / mt, ceil_div(std::max(K, 1), 256)));
+}
+
+// Split the reduction into (about) ns parts of whole 16-element chunks.
+template <typename T>
+void set_split(GemmArgs<T>& g, int ns) {
+  g.kchunk = (int)round_up(ceil_div(std::max(g.K, 1), std::max(ns, 1)), 16);
+  g.nsplit = (int)ceil_div(std::max(g.K, 1), g.kchunk);
+}
+
+// Partial-slab capacity of the workspaces: enough for any plan up to the cap.
 template <typename T>
 size_t gemm_partial_elems(int M, int K, int dp) {
   GemmArgs<T> g = plan_gemm<T>(0, (const T*)nullptr, 16, (const T*)nullptr, dp, M, dp, K);
-  return g.nsplit > 1 ? (size_t)g.nsplit * M * dp : 0;
+  const int ns = std::max(g.nsplit, splitk_cap(M, K));
+  return ns > 1 ? (size_t)ns * M * dp : 0;
 }
 
 // Layout of the dense / CSR decomposition workspace.
@@ -313,6 +334,8 @@ rqlp_status gemm(rqlp_ctx* c, int trans, const T* A, int64_t lda, int64_t m, int
   // trans = 0: Y (m x nst) = A X (K = n); trans = 1: Y (n x nst) = A^T X (K = m)
   const int M = (int)(trans ? n : m), K = (int)(trans ? m : n);
   GemmArgs<T> g = plan_gemm<T>(trans, A, lda, X, ldx, M, d, K);
+  auto it = c->plan.find(std::make_tuple((int)sizeof(T), trans, M, d, K));
+  if (it != c->plan.end()) set_split(g, std::min(it->second, splitk_cap(M, K)));
   // internal operands have ld = dp and zero padding columns: vector loads
   const int vec = 16 / (int)sizeof(T);
   g.bvec = padded_x && ldx == gemm_block_cols<T>(d) && ldx % vec == 0 && (((uintptr_t)X & 15) == 0);
@@ -705,6 +728,73 @@ rqlp_status svd_like(rqlp_ctx* c, const SvdLayout& Ly, char* b, int64_t m, int64
   return gemm<T>(c, 0, V, d, n, d, Vb, d, d, W, d, d, part, s, false);
 }
 
+// ---- autotuner --------------------------------------------------------------
+
+// Time every split-K candidate of one product shape (Y = op(A) X with d
+// columns, as the decomposition issues it: X and Y with ld dp, zero padding)
+// and keep the fastest in the context's plan table.  Synchronizes.
+template <typename T>
+rqlp_status autotune_product(rqlp_ctx* c, int trans, const T* A, int64_t lda, int64_t m, int64_t n, int d, T* X,
+                             T* Y, T* P, hipStream_t s, int* best_out) {
+  const int dp = padded_d(d);
+  const int M = (int)(trans ? n : m), K = (int)(trans ? m : n);
+  GemmArgs<T> g0 = plan_gemm<T>(trans, A, lda, X, dp, M, d, K);
+  const int vec = 16 / (int)sizeof(T);
+  g0.bvec = dp == gemm_block_cols<T>(d) && dp % vec == 0 && (((uintptr_t)X & 15) == 0);
+  const int cap = splitk_cap(M, K);
+  std::vector<int> cand = {g0.nsplit};
+  for (int ns : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64})
+    if (ns <= cap) cand.push_back(ns);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best_ms = 0.f;
+  int best = g0.nsplit, best_eff = -1;
+  rqlp_status st = RQLP_OK;
+  for (int ns : cand) {
+    GemmArgs<T> g = g0;
+    set_split(g, ns);
+    if (g.nsplit == best_eff) continue;  // the same plan as one already timed
+    float ms = 0.f, t = 0.f;
+    bool ok = true;
+    for (int r = 0; r < 7 && ok; ++r) {  // two warm-ups, then the fastest of five
+      ok = hipEventRecord(e0, s) == hipSuccess && launch_gemm<T>(g, Y, dp, dp, P, s, nullptr, nullptr) == hipSuccess &&
+           hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+           hipEventElapsedTime(&t, e0, e1) == hipSuccess;
+      if (r >= 2) ms = (r == 2) ? t : std::min(ms, t);
+    }
+    if (!ok) { st = RQLP_ERR_HIP; break; }
+    if (best_eff < 0 || ms < best_ms) {
+      best_ms = ms;
+      best = g.nsplit;
+      best_eff = g.nsplit;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != RQLP_OK) return st;
+  c->plan[std::make_tuple((int)sizeof(T), trans, M, d, K)] = best;
+  if (best_out) *best_out = best;
+  return RQLP_OK;
+}
+
+template <typename T>
+rqlp_status autotune_dense(rqlp_ctx* c, const T* A, int64_t m, int64_t n, int64_t lda, int d, hipStream_t s,
+                           int* best_nn, int* best_tn) {
+  const int dp = padded_d(d);
+  const size_t pe = std::max(gemm_partial_elems<T>((int)m, (int)n, dp), gemm_partial_elems<T>((int)n, (int)m, dp));
+  const size_t xb = align256((size_t)std::max(m, n) * dp * sizeof(T));
+  char* base = nullptr;
+  rqlp_status st = get_workspace(c, nullptr, 0, 2 * xb + align256(pe * sizeof(T)) + 256, &base);
+  if (st != RQLP_OK) return st;
+  T* X = (T*)base;
+  T* Y = (T*)(base + xb);
+  T* P = (T*)(base + 2 * xb);
+  HIP_TRY(hipMemsetAsync(X, 0, xb, s));  // operand values do not change the timing
+  if ((st = autotune_product<T>(c, 0, A, lda, m, n, d, X, Y, P, s, best_nn)) != RQLP_OK) return st;
+  return autotune_product<T>(c, 1, A, lda, m, n, d, X, Y, P, s, best_tn);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -858,6 +948,64 @@ rqlp_status rqlp_set_batch_grouping(rqlp_ctx* c, int enabled) {
   if (!c) return RQLP_ERR_INVALID_ARG;
   c->lockstep = enabled != 0;
   c->last_key.clear();
+  return RQLP_OK;
+}
+
+rqlp_status rqlp_autotune(rqlp_ctx* c, const void* A, int64_t m, int64_t n, int64_t lda, int d,
+                          rqlp_precision prec, void* stream, int* nsplit_nn, int* nsplit_tn) {
+  if (!c || !A || m < 1 || n < 1 || d < 1 || lda < n || (prec != RQLP_FP64 && prec != RQLP_FP32))
+    return RQLP_ERR_INVALID_ARG;
+  if (d > kDMax || d > std::min(m, n)) return d > kDMax ? RQLP_ERR_UNSUPPORTED : RQLP_ERR_INVALID_ARG;
+  if (m > INT32_MAX || n > INT32_MAX) return RQLP_ERR_UNSUPPORTED;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == RQLP_FP64)
+    return autotune_dense<double>(c, (const double*)A, m, n, lda, d, s, nsplit_nn, nsplit_tn);
+  return autotune_dense<float>(c, (const float*)A, m, n, lda, d, s, nsplit_nn, nsplit_tn);
+}
+
+rqlp_status rqlp_autotune_clear(rqlp_ctx* c) {
+  if (!c) return RQLP_ERR_INVALID_ARG;
+  c->plan.clear();
+  return RQLP_OK;
+}
+
+rqlp_status rqlp_autotune_save(rqlp_ctx* c, const char* path) {
+  if (!c || !path) return RQLP_ERR_INVALID_ARG;
+  std::ofstream f(path);
+  if (!f) return RQLP_ERR_INVALID_ARG;
+  f << "rqlp-plans 1\n";
+  for (const auto& e : c->plan) {
+    const auto& k = e.first;
+    f << "gemm " << std::get<0>(k) << ' ' << std::get<1>(k) << ' ' << std::get<2>(k) << ' ' << std::get<3>(k) << ' '
+      << std::get<4>(k) << ' ' << e.second << "\n";
+  }
+  return f.good() ? RQLP_OK : RQLP_ERR_INVALID_ARG;
+}
+
+rqlp_status rqlp_autotune_load(rqlp_ctx* c, const char* path) {
+  if (!c || !path) return RQLP_ERR_INVALID_ARG;
+  std::ifstream f(path);
+  if (!f) return RQLP_ERR_INVALID_ARG;
+  std::string tag;
+  int version = 0;
+  if (!(f >> tag >> version) || tag != "rqlp-plans" || version != 1) return RQLP_ERR_INVALID_ARG;
+  std::map<std::tuple<int, int, int, int, int>, int> plan;
+  std::string kind;
+  while (f >> kind) {
+    int es, trans, M, N, K, ns;
+    if (kind != "gemm" || !(f >> es >> trans >> M >> N >> K >> ns) || (es != 4 && es != 8) ||
+        (trans != 0 && trans != 1) || M < 1 || N < 1 || K < 1 || ns < 1)
+      return RQLP_ERR_INVALID_ARG;
+    plan[std::make_tuple(es, trans, M, N, K)] = ns;
+  }
+  for (const auto& e : plan) c->plan[e.first] = e.second;
+  return RQLP_OK;
+}
+
+rqlp_status rqlp_autotune_count(rqlp_ctx* c, int* count) {
+  if (!c || !count) return RQLP_ERR_INVALID_ARG;
+  *count = (int)c->plan.size();
   return RQLP_OK;
 }
 

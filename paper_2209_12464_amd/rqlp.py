@@ -78,6 +78,12 @@ def _lib():
             "rqlp_decompose_batched": (_INT, [_P, _INT, ctypes.POINTER(Problem), _INT, _P, _SZ, _P]),
             "rqlp_set_graphs": (_INT, [_P, _INT]),
             "rqlp_set_batch_grouping": (_INT, [_P, _INT]),
+            "rqlp_autotune": (_INT, [_P, _P, _I64, _I64, _I64, _INT, _INT, _P, ctypes.POINTER(_INT),
+                                     ctypes.POINTER(_INT)]),
+            "rqlp_autotune_clear": (_INT, [_P]),
+            "rqlp_autotune_count": (_INT, [_P, ctypes.POINTER(_INT)]),
+            "rqlp_autotune_save": (_INT, [_P, ctypes.c_char_p]),
+            "rqlp_autotune_load": (_INT, [_P, ctypes.c_char_p]),
             "rqlp_svd_workspace_size": (_SZ, [_INT]),
             "rqlp_svd_small": (_INT, [_P, _P, _INT, _I64, _P, _I64, _P, _P, _I64, _INT, _P, _SZ, _P]),
             "rqlp_workspace_size_svd": (_SZ, [_I64, _I64, _INT, _INT, _INT, _INT]),
@@ -114,6 +120,8 @@ def exported_symbols():
             "rqlp_set_timing", "rqlp_set_timing_mask", "rqlp_get_timing",
             "rqlp_workspace_size_batched", "rqlp_decompose_batched", "rqlp_set_graphs",
             "rqlp_set_batch_grouping", "rqlp_svd_workspace_size", "rqlp_svd_small",
+            "rqlp_autotune", "rqlp_autotune_clear", "rqlp_autotune_count", "rqlp_autotune_save",
+            "rqlp_autotune_load",
             "rqlp_workspace_size_svd", "rqlp_decompose_svd",
             "rqlp_server_create", "rqlp_server_destroy", "rqlp_server_request_bytes", "rqlp_server_submit",
             "rqlp_server_poll", "rqlp_workspace_size_paper", "rqlp_decompose_paper"]
@@ -177,6 +185,30 @@ class Context:
     def set_graphs(self, enabled):
         """Capture a batch submitted twice in a row into a HIP graph and replay it."""
         _check(_lib().rqlp_set_graphs(self._h, 1 if enabled else 0), "rqlp_set_graphs")
+
+    def autotune(self, A, d):
+        """Tune the split-K plans of the products of a decomposition of A
+        with d columns; returns (nsplit of A X, nsplit of A^T X)."""
+        if A.dim() != 2 or A.stride(1) != 1:
+            raise ValueError("A must be a 2-D row-major tensor")
+        nn, tn = _INT(0), _INT(0)
+        _check(_lib().rqlp_autotune(self._h, _ptr(A), A.shape[0], A.shape[1], A.stride(0), d, _prec(A.dtype),
+                                    _stream(A.device), ctypes.byref(nn), ctypes.byref(tn)), "rqlp_autotune")
+        return nn.value, tn.value
+
+    def autotune_count(self):
+        n = _INT(0)
+        _check(_lib().rqlp_autotune_count(self._h, ctypes.byref(n)), "rqlp_autotune_count")
+        return n.value
+
+    def autotune_clear(self):
+        _check(_lib().rqlp_autotune_clear(self._h), "rqlp_autotune_clear")
+
+    def autotune_save(self, path):
+        _check(_lib().rqlp_autotune_save(self._h, str(path).encode()), "rqlp_autotune_save")
+
+    def autotune_load(self, path):
+        _check(_lib().rqlp_autotune_load(self._h, str(path).encode()), "rqlp_autotune_load")
 
     def set_batch_grouping(self, enabled):
         """Grouped (lockstep) factorizations in batches (on by default)."""
