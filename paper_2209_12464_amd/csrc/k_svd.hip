@@ -17,7 +17,10 @@
 // LDS and rotates them, one pair per wave and round: at a sweep's first step
 // every pair of the 16 columns (15 rounds of 8), at later steps only the 64
 // pairs across the two blocks (8 rounds), so that a sweep visits every pair
-// of columns once or twice.  A pair is rotated only when
+// of columns once or twice.  The squared column norms are computed at the
+// start of a step and then carried through its rotations
+// (||x_p||^2 -= t x_p.x_q, ||x_q||^2 += t x_p.x_q), so that a round needs one
+// inner product.  A pair is rotated only when
 // |x_p.x_q| > dp eps ||x_p|| ||x_q||; a sweep without a rotation ends the
 // iteration.  All sweeps run in one cooperative launch (nb / 2 workgroups,
 // a grid barrier after every step).  Finally sigma_j = ||x_j||, the
@@ -34,6 +37,7 @@ namespace rqlp {
 constexpr int kSvW = 8;               // columns per block
 constexpr int kSvCols = 2 * kSvW;     // columns of a block pair
 constexpr int kSvThreads = 64 * kSvW; // one wave per rotation of a round
+constexpr int kSvRows = (kDMax + 63) / 64;  // rows of each half per lane
 
 inline size_t svd_align(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -80,7 +84,7 @@ __global__ __launch_bounds__(256) void svd_init_kernel(const T* __restrict__ M, 
 // when the step rotated a pair.
 __device__ __attribute__((always_inline)) inline void svd_step(double* __restrict__ XV, int dp, int nb, int step,
                                                               int sweep, int32_t* __restrict__ flags, double tol,
-                                                              double* Xs, int& rotated) {
+                                                              double* Xs, double* nrm, int& rotated) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int len = 2 * dp;
@@ -97,6 +101,15 @@ __device__ __attribute__((always_inline)) inline void svd_step(double* __restric
   }
   if (tid == 0) rotated = 0;
   __syncthreads();
+  // squared norms of the pair's columns (two per wave)
+  for (int c = wave; c < kSvCols; c += kSvThreads / 64) {
+    const double* xc = Xs + c * len;
+    double a = 0.0;
+    for (int r = lane; r < dp; r += 64) a = fma(xc[r], xc[r], a);
+    a = wave_sum(a);
+    if (lane == 0) nrm[c] = a;
+  }
+  __syncthreads();
 
   const int rounds = step == 0 ? kSvCols - 1 : kSvW;
   for (int rnd = 0; rnd < rounds; ++rnd) {
@@ -110,26 +123,45 @@ __device__ __attribute__((always_inline)) inline void svd_step(double* __restric
     }
     double* xp = Xs + p * len;
     double* xq = Xs + q * len;
-    double a = 0.0, b = 0.0, g = 0.0;
-    for (int r = lane; r < dp; r += 64) {
-      const double u = xp[r], v = xq[r];
-      a = fma(u, u, a);
-      b = fma(v, v, b);
-      g = fma(u, v, g);
+    const double a = nrm[p], b = nrm[q];
+    // this lane's rows of x_p and x_q, all loaded before the first use
+    double u[kSvRows], v[kSvRows];
+#pragma unroll
+    for (int i = 0; i < kSvRows; ++i) {
+      const int r = lane + 64 * i;
+      u[i] = r < dp ? xp[r] : 0.0;
+      v[i] = r < dp ? xq[r] : 0.0;
     }
-    a = wave_sum(a);  // uniform across the wave: all rows see one rotation
-    b = wave_sum(b);
-    g = wave_sum(g);
-    if (fabs(g) > tol * sqrt(a) * sqrt(b)) {
+    double g = 0.0;
+#pragma unroll
+    for (int i = 0; i < kSvRows; ++i) g = fma(u[i], v[i], g);
+    g = wave_sum(g);  // uniform across the wave: all rows see one rotation
+    if (fabs(g) > tol * sqrt(a * b)) {
       const double zeta = (b - a) / (2.0 * g);
       const double t = fabs(zeta) > 1e150 ? 0.5 / zeta : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
       const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-      for (int r = lane; r < len; r += 64) {  // x and v together
-        const double u = xp[r], v = xq[r];
-        xp[r] = cs * u - sn * v;
-        xq[r] = sn * u + cs * v;
+      double pu[kSvRows], pv[kSvRows];  // the v halves
+#pragma unroll
+      for (int i = 0; i < kSvRows; ++i) {
+        const int r = dp + lane + 64 * i;
+        pu[i] = r < len ? xp[r] : 0.0;
+        pv[i] = r < len ? xq[r] : 0.0;
       }
-      if (lane == 0) rotated = 1;
+#pragma unroll
+      for (int i = 0; i < kSvRows; ++i) {
+        const int r = lane + 64 * i;
+        if (r < dp) {
+          xp[r] = cs * u[i] - sn * v[i];
+          xq[r] = sn * u[i] + cs * v[i];
+          xp[dp + r] = cs * pu[i] - sn * pv[i];
+          xq[dp + r] = sn * pu[i] + cs * pv[i];
+        }
+      }
+      if (lane == 0) {
+        nrm[p] = a - t * g;
+        nrm[q] = b + t * g;
+        rotated = 1;
+      }
     }
     __syncthreads();
   }
@@ -146,11 +178,12 @@ __global__ __launch_bounds__(kSvThreads) void svd_sweeps_kernel(double* __restri
                                                                 int32_t* __restrict__ flags, int max_sweeps,
                                                                 double tol) {
   extern __shared__ double svd_smem[];  // kSvCols columns of length 2 dp
+  __shared__ double nrm[kSvCols];        // squared norms of the x parts
   __shared__ int rotated;
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     for (int step = 0; step < nb - 1; ++step) {
-      svd_step(XV, dp, nb, step, sweep, flags, tol, svd_smem, rotated);
+      svd_step(XV, dp, nb, step, sweep, flags, tol, svd_smem, nrm, rotated);
       grid.sync();  // the next step reads columns other workgroups wrote
     }
     if (flags[sweep] == 0) break;  // the same value for every workgroup after the barrier
