@@ -117,3 +117,36 @@ def test_decompose_svd_is_the_qlv_form_at_full_size(gpu_lib):
     assert (W64.T @ W64 - eye).abs().max().item() <= 1e-5
     s_ref = torch.linalg.svdvals(L64.cpu())
     assert (S.double().cpu() - s_ref).abs().max().item() <= 1e-5 * s_ref[0].item()
+
+
+def test_svd_small_leading_dimensions(gpu_lib):
+    """Strided input and outputs (ld > d): the same values as the packed call."""
+    announce("svd_small leading dimensions")
+    d = 45
+    M = _lower(d, 8)
+    big = np.zeros((d, 64))
+    big[:, :d] = M
+    Mt = to_dev(big)[:, :d]  # row stride 64
+    U = torch.full((d, 50), float("nan"), dtype=torch.float64, device="cuda")[:, :d]
+    V = torch.full((d, 70), float("nan"), dtype=torch.float64, device="cuda")[:, :d]
+    S = torch.empty(d, dtype=torch.float64, device="cuda")
+    gpu_lib.svd_small(Mt, out=(U, S, V))
+    Ur, Sr, Vr = gpu_lib.svd_small(to_dev(M))
+    torch.cuda.synchronize()
+    assert torch.equal(U, Ur) and torch.equal(S, Sr) and torch.equal(V, Vr)
+
+
+def test_decompose_svd_bf16_is_its_qlv_form(gpu_lib):
+    """The bfloat16 form: U diag(S) W^T reproduces the bfloat16 decomposition
+    Q L V^T it is built from (the same launch sequence up to L), to float32
+    rounding of the SVD and the two products."""
+    announce("decompose_svd bf16")
+    m, n, k, p, q = 3000, 2000, 120, 8, 1
+    sigma = workloads.spectrum("polynomial", n)
+    A = to_dev(workloads.dense_fast_orth(m, n, sigma, 5, np.float32))
+    Q, L, V = (to_np(x) for x in gpu_lib.decompose(A, k, p, q, seed=4, bf16=True))
+    U, S, W = (to_np(x) for x in gpu_lib.decompose_svd(A, k, p, q, seed=4, bf16=True))
+    ref = Q @ L @ V.T
+    assert np.linalg.norm(U @ np.diag(S) @ W.T - ref) / np.linalg.norm(ref) <= 1e-5
+    assert np.all(np.diff(S) <= 0)
+    assert np.abs(U.T @ U - np.eye(k + p)).max() <= 1e-5
