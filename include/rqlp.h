@@ -69,6 +69,10 @@ typedef enum {
   RQLP_BF16_REFINED = 2
 } rqlp_precision;
 
+/* A context holds the device info record, an internal workspace, event
+ * pools, batch streams and the autotuned plan table.  Use each context from
+ * one host thread at a time (calls on one context are not synchronized with
+ * each other); separate contexts are independent. */
 typedef struct rqlp_ctx rqlp_ctx;
 
 /* Device-side record of the last call on a context. */
