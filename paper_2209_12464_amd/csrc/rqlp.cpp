@@ -746,8 +746,10 @@ rqlp_status autotune_product(rqlp_ctx* c, int trans, const T* A, int64_t lda, in
   for (int ns : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64})
     if (ns <= cap) cand.push_back(ns);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return RQLP_ERR_HIP;
+  }
   float best_ms = 0.f;
   int best = g0.nsplit, best_eff = -1;
   rqlp_status st = RQLP_OK;
