@@ -91,3 +91,55 @@ def test_planted_philox_mistake_is_caught():
     bg = np.random.Philox(key=np.array([5, 7], np.uint64), counter=np.array([0, 0, 0, 0], np.uint64))
     raw = bg.random_raw(4)
     assert not np.array_equal(bad_block(np.array([[1, 0, 0, 0]], np.uint64), (5, 7))[0], raw)
+
+
+# ---- the SVD-like form (Remark 1) ----
+
+def _svd_small_with(mutation=None):
+    """A copy of oracle.svdlike.svd_small, optionally with one planted mistake."""
+    def svd_small(M):
+        U, s, Vt = np.linalg.svd(M)
+        Vb = Vt.copy() if mutation == "V-bar transposed" else Vt.T.copy()
+        Ub = U.copy()
+        if mutation == "ascending order":
+            Ub, s, Vb = Ub[:, ::-1].copy(), s[::-1].copy(), Vb[:, ::-1].copy()
+        for j in range(M.shape[1]):
+            i = int(np.argmax(np.abs(Vb[:, j])))
+            if Vb[i, j] < 0:
+                Vb[:, j] = -Vb[:, j]
+                if mutation != "sign flipped on V only":
+                    Ub[:, j] = -Ub[:, j]
+            if s[j] == 0.0 and mutation != "zero-sigma left vector kept":
+                Ub[:, j] = 0.0
+        return Ub, s, Vb
+    return svd_small
+
+
+def _svd_pins_pass(svd_small):
+    rng = np.random.default_rng(2)
+    M = np.tril(rng.standard_normal((30, 30))) + 3 * np.eye(30)
+    Ub, s, Vb = svd_small(M)
+    ok = np.all(np.diff(s) <= 0) and np.abs(Ub @ np.diag(s) @ Vb.T - M).max() < 1e-12
+    ok = ok and all(Vb[int(np.argmax(np.abs(Vb[:, j]))), j] > 0 for j in range(30))
+    # the whole form against its Q L V^T
+    A, _, _, _ = workloads.dense_from_spectrum(80, 60, workloads.spectrum("geometric", 60, rho=0.8), 3, trunc=0.0)
+    Q, L, V = oracle.ruqlp(A, 8, 4, 1, seed=5)
+    Ub, s, Vb = svd_small(L)
+    ok = ok and np.abs((Q @ Ub) @ np.diag(s) @ (V @ Vb).T - Q @ L @ V.T).max() < 1e-12
+    # an exactly zero singular value has a zero left vector
+    Ub, s, Vb = svd_small(np.diag([2.0, 0.0, 1.0]))
+    ok = ok and s[-1] == 0.0 and np.all(Ub[:, -1] == 0.0)
+    return bool(ok)
+
+
+def test_svdlike_unmutated_copy_passes():
+    assert _svd_pins_pass(_svd_small_with())
+    M = np.tril(np.random.default_rng(4).standard_normal((12, 12))) + np.eye(12)
+    for a, b in zip(_svd_small_with()(M), oracle.svd_small(M)):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name", ["V-bar transposed", "ascending order", "sign flipped on V only",
+                                  "zero-sigma left vector kept"])
+def test_svdlike_planted_mistake_is_caught(name):
+    assert not _svd_pins_pass(_svd_small_with(name)), name
