@@ -67,6 +67,23 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// 1/x and 1/sqrt(x) for finite positive (rsqrt) or nonzero (rcp) x: the
+// hardware estimates refined by two Newton steps, within an ulp or two, on
+// the critical path of every rotation instead of the longer correctly
+// rounded sequences.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+
 // XV: dp columns of length 2 dp, column j = (M[:, j] zero-padded, e_j).
 template <typename T>
 __global__ __launch_bounds__(256) void svd_init_kernel(const T* __restrict__ M, int64_t ldm, int d, int dp,
@@ -136,10 +153,16 @@ __device__ __attribute__((always_inline)) inline void svd_step(double* __restric
 #pragma unroll
     for (int i = 0; i < kSvRows; ++i) g = fma(u[i], v[i], g);
     g = wave_sum(g);  // uniform across the wave: all rows see one rotation
-    if (fabs(g) > tol * sqrt(a * b)) {
-      const double zeta = (b - a) / (2.0 * g);
-      const double t = fabs(zeta) > 1e150 ? 0.5 / zeta : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-      const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+    if (g * g > tol * tol * (a * b)) {
+      const double zeta = (b - a) * rcp_nr(2.0 * g);
+      double t;
+      if (fabs(zeta) > 1e150) {
+        t = 0.5 * rcp_nr(zeta);
+      } else {
+        const double w = fma(zeta, zeta, 1.0);
+        t = copysign(rcp_nr(fabs(zeta) + w * rsqrt_nr(w)), zeta);
+      }
+      const double cs = rsqrt_nr(fma(t, t, 1.0)), sn = cs * t;
       double pu[kSvRows], pv[kSvRows];  // the v halves
 #pragma unroll
       for (int i = 0; i < kSvRows; ++i) {
