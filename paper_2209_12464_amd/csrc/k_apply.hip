@@ -1,15 +1,15 @@
 // Q = Y R^-1 for the upper-triangular Cholesky factor R (float64), the last
 // step of each CholeskyQR pass.  Arithmetic is float64 whatever the storage
-// type of Y and Q.  Normally R^-1 is available explicitly (the Cholesky's
-// fast path, or the inverse kernel after a full factorization), and every
-// 16 x 16 output block is an independent sum Q[:, J] = sum_{t <= J} Y[:, t]
-// X[t, J]: workgroups take 64 RF rows x 4 column blocks with LDS-staged
-// tiles, each wave RF 16-row fragments (RF = 2 for tall inputs, so that a
-// wave issues 32 MFMAs per staged block row).
-// When the Cholesky marked a dependent column, a blocked substitution runs
-// instead, and those columns are replaced by N(0,1)/sqrt(rows) columns from
-// a Philox stream of their own (completion of a rank-deficient basis);
-// their R rows are zero, so later columns do not depend on them.
+// type of Y and Q.  R^-1 = X is explicit (the Cholesky's fast path, or the
+// inverse kernel after a full factorization), and every 16 x 16 output block
+// is an independent sum Q[:, J] = sum_{t <= J} Y[:, t] X[t, J]: workgroups
+// take 64 RF rows x 4 column blocks with LDS-staged tiles, each wave RF
+// 16-row fragments (RF = 2 for tall inputs, so that a wave issues 32 MFMAs
+// per staged block row).
+// Columns the Cholesky marked dependent are written as N(0,1)/sqrt(rows)
+// columns from a Philox stream of their own (completion of a rank-deficient
+// basis).  Their rows of R are zero (with a unit diagonal), so the other
+// columns of Y R^-1 do not involve them.
 #include "common.h"
 #include "kernels.h"
 
@@ -19,17 +19,13 @@ constexpr int kApCols = 4 * kTile;    // columns per workgroup (4 blocks)
 constexpr int kApXS = kApCols + 16;   // LDS row stride of the X tile (doubles): rows 32 banks apart
 constexpr int kApYS = kTile + 1;      // LDS row stride of the Y tile (doubles)
 
-__host__ __device__ inline size_t apply_lds_doubles(int dp, int rf) {
-  const size_t expl = 2 * (size_t)(kTile * kApXS + 64 * rf * kApYS);
-  const size_t subst = (size_t)kTile * (dp + 1);
-  return expl > subst ? expl : subst;
+__host__ __device__ inline size_t apply_lds_doubles(int rf) {
+  return 2 * (size_t)(kTile * kApXS + 64 * rf * kApYS);
 }
 
 template <typename Tin, typename Tout, int RF>
 __global__ __launch_bounds__(256) void apply_kernel(const Tin* __restrict__ Y, int64_t ldy, int64_t rows,
-                                                    int d, int dp, const double* __restrict__ R,
-                                                    const double* __restrict__ Rinv16,
-                                                    const int32_t* __restrict__ flags,
+                                                    int d, int dp, const int32_t* __restrict__ flags,
                                                     const int32_t* __restrict__ mode,
                                                     const double* __restrict__ Xfull,
                                                     Tout* __restrict__ out1, int64_t ld1, int ncols1,
@@ -43,169 +39,114 @@ __global__ __launch_bounds__(256) void apply_kernel(const Tin* __restrict__ Y, i
   const int64_t r0 = (int64_t)blockIdx.x * kApRows;
   const int T = dp / kTile;
 
-  if (*mode != 0) {
-    // ---- explicit inverse: out[:, J] = sum_{t <= J} Y[:, t] X[t, J] ----
-    // Column blocks J0..J1-1; per block row t the X tile (16 x 64) and the
-    // Y tile (64 x 16, widened to double) are staged in LDS, double
-    // buffered, with the next t held in registers meanwhile.
-    const int J0 = 4 * blockIdx.y;
-    if (J0 >= T) return;
-    const int J1 = min(T, J0 + 4);
-    double* Xs = smem;                           // [2][16][kApXS]
-    double* Ys = smem + 2 * kTile * kApXS;       // [2][64][kApYS]
-    double xr[4];
-    Tin yr[4 * RF];
-    auto load = [&](int t) {
+  // out[:, J] = sum_{t <= J} Y[:, t] X[t, J] for column blocks J0..J1-1;
+  // per block row t the X tile (16 x 64) and the Y tile (64 x 16, widened
+  // to double) are staged in LDS, double buffered, with the next t held in
+  // registers meanwhile.
+  const int J0 = 4 * blockIdx.y;
+  if (J0 >= T) return;
+  const int J1 = min(T, J0 + 4);
+  double* Xs = smem;                           // [2][16][kApXS]
+  double* Ys = smem + 2 * kTile * kApXS;       // [2][64][kApYS]
+  double xr[4];
+  Tin yr[4 * RF];
+  auto load = [&](int t) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = tid + 256 * q;
-        const int kr = e >> 6, c = e & 63;       // X[t*16 + kr][J0*16 + c]
-        const int col = J0 * kTile + c;
-        xr[q] = (col < J1 * kTile) ? Xfull[(int64_t)(t * kTile + kr) * dp + col] : 0.0;
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int kr = e >> 6, c = e & 63;       // X[t*16 + kr][J0*16 + c]
+      const int col = J0 * kTile + c;
+      xr[q] = (col < J1 * kTile) ? Xfull[(int64_t)(t * kTile + kr) * dp + col] : 0.0;
+    }
 #pragma unroll
-      for (int q = 0; q < 4 * RF; ++q) {
-        const int e = tid + 256 * q;
-        const int rr = e >> 4, cc = e & 15;      // Y[r0 + rr][t*16 + cc]
-        const int64_t row = r0 + rr;
-        const int ycol = t * kTile + cc;
-        yr[q] = (row < rows && ycol < d) ? Y[row * ldy + ycol] : (Tin)0;
-      }
-    };
-    auto store = [&](int buf) {
+    for (int q = 0; q < 4 * RF; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e >> 4, cc = e & 15;      // Y[r0 + rr][t*16 + cc]
+      const int64_t row = r0 + rr;
+      const int ycol = t * kTile + cc;
+      yr[q] = (row < rows && ycol < d) ? Y[row * ldy + ycol] : (Tin)0;
+    }
+  };
+  auto store = [&](int buf) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = tid + 256 * q;
-        Xs[buf * kTile * kApXS + (e >> 6) * kApXS + (e & 63)] = xr[q];
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      Xs[buf * kTile * kApXS + (e >> 6) * kApXS + (e & 63)] = xr[q];
+    }
 #pragma unroll
-      for (int q = 0; q < 4 * RF; ++q) {
-        const int e = tid + 256 * q;
-        Ys[buf * kApRows * kApYS + (e >> 4) * kApYS + (e & 15)] = (double)yr[q];
-      }
-    };
-    doublex4 acc[RF][4];
+    for (int q = 0; q < 4 * RF; ++q) {
+      const int e = tid + 256 * q;
+      Ys[buf * kApRows * kApYS + (e >> 4) * kApYS + (e & 15)] = (double)yr[q];
+    }
+  };
+  doublex4 acc[RF][4];
+#pragma unroll
+  for (int f = 0; f < RF; ++f)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[f][u] = Mfma<double>::zero();
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int t = 0; t < J1; ++t) {
+    const bool more = t + 1 < J1;
+    if (more) load(t + 1);
+    const double* xs = Xs + buf * kTile * kApXS;
+    const double* ys = Ys + buf * kApRows * kApYS + (wave * kTile * RF + lc) * kApYS;
+    double a[RF][4];
 #pragma unroll
     for (int f = 0; f < RF; ++f)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[f][u] = Mfma<double>::zero();
-    load(0);
-    store(0);
-    __syncthreads();
-    int buf = 0;
-    for (int t = 0; t < J1; ++t) {
-      const bool more = t + 1 < J1;
-      if (more) load(t + 1);
-      const double* xs = Xs + buf * kTile * kApXS;
-      const double* ys = Ys + buf * kApRows * kApYS + (wave * kTile * RF + lc) * kApYS;
-      double a[RF][4];
-#pragma unroll
-      for (int f = 0; f < RF; ++f)
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks)  // A[m][k] = Y[16 (RF w + f) + m][t*16 + k]
-          a[f][ks] = ys[f * kTile * kApYS + ks * 4 + lr];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (J0 + u >= t && J0 + u < J1) {
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) {
-            const double b = xs[(ks * 4 + lr) * kApXS + u * kTile + lc];
-#pragma unroll
-            for (int f = 0; f < RF; ++f) acc[f][u] = Mfma<double>::mma(a[f][ks], b, acc[f][u]);
-          }
-        }
-      }
-      if (more) store(buf ^ 1);
-      __syncthreads();
-      buf ^= 1;
-    }
+      for (int ks = 0; ks < 4; ++ks)  // A[m][k] = Y[16 (RF w + f) + m][t*16 + k]
+        a[f][ks] = ys[f * kTile * kApYS + ks * 4 + lr];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      if (J0 + u >= J1) break;
-      const int col = (J0 + u) * kTile + lc;
-#pragma unroll
-      for (int f = 0; f < RF; ++f)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t row = r0 + (wave * RF + f) * kTile + lr + 4 * r;
-          if (row < rows) {
-            if (col < ncols1) out1[row * ld1 + col] = (Tout)acc[f][u][r];
-            if (out2 && col < ncols2) out2[row * ld2 + col] = (Tout)acc[f][u][r];
-          }
-        }
-    }
-    return;
-  }
-
-  // ---- blocked substitution (a dependent column was found) ----
-  // Wave 0 of the workgroup of column group g takes the 16-row slabs g,
-  // g + groups, ... of the 64 RF-row block (this path is taken only for
-  // rank-deficient inputs); per slab it goes through the 16-column blocks J in order,
-  //     acc    = Y[:, J] - sum_{t < J} Q[:, t] R[t, J]      (float64 MFMA)
-  //     Q[:,J] = acc * inv(R[J, J])                         (4 MFMAs)
-  // keeping the finished Q blocks in LDS as the A operand of later blocks.
-  if (wave != 0) return;
-  double* Qs = smem;  // [16][dp + 1]
-  const int S = dp + 1;
-  for (int slab = blockIdx.y; slab < kApRows / kTile; slab += gridDim.y) {
-    const int64_t q0 = r0 + slab * kTile;
-    if (q0 >= rows) break;
-    for (int J = 0; J < T; ++J) {
-      doublex4 acc;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = q0 + lr + 4 * r;
-        const int col = J * kTile + lc;
-        acc[r] = (row < rows && col < d) ? (double)Y[row * ldy + col] : 0.0;
-      }
-      doublex4 acc2 = Mfma<double>::zero();
-      for (int t = 0; t < J; ++t) {
+      if (J0 + u >= t && J0 + u < J1) {
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
-          const double a = -Qs[lc * S + t * kTile + ks * 4 + lr];
-          const double b = R[(int64_t)(t * kTile + ks * 4 + lr) * dp + J * kTile + lc];
-          if (t & 1) acc2 = Mfma<double>::mma(a, b, acc2);
-          else acc = Mfma<double>::mma(a, b, acc);
+          const double b = xs[(ks * 4 + lr) * kApXS + u * kTile + lc];
+#pragma unroll
+          for (int f = 0; f < RF; ++f) acc[f][u] = Mfma<double>::mma(a[f][ks], b, acc[f][u]);
         }
       }
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] += acc2[r];
-      // stage acc as an A operand, then multiply by inv(R[J, J])
+  for (int u = 0; u < 4; ++u) {
+    if (J0 + u >= J1) break;
+    const int col = (J0 + u) * kTile + lc;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Qs[(lr + 4 * r) * S + J * kTile + lc] = acc[r];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      doublex4 q = Mfma<double>::zero();
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const double a = Qs[lc * S + J * kTile + ks * 4 + lr];
-        const double b = Rinv16[(int64_t)J * kTile * kTile + (ks * 4 + lr) * kTile + lc];
-        q = Mfma<double>::mma(a, b, q);
-      }
-      const int col = J * kTile + lc;
-      const bool dep = (col < d) && flags[col] != 0;
-      __builtin_amdgcn_wave_barrier();
+    for (int f = 0; f < RF; ++f)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = q0 + lr + 4 * r;
-        double v = q[r];
-        if (dep) v = (row < rows) ? gaussian_at(seed, key1, (uint64_t)col * rows + row) * inv_sqrt_rows : 0.0;
-        Qs[(lr + 4 * r) * S + col] = v;
+        const int64_t row = r0 + (wave * RF + f) * kTile + lr + 4 * r;
         if (row < rows) {
-          if (col < ncols1) out1[row * ld1 + col] = (Tout)v;
-          if (out2 && col < ncols2) out2[row * ld2 + col] = (Tout)v;
+          if (col < ncols1) out1[row * ld1 + col] = (Tout)acc[f][u][r];
+          if (out2 && col < ncols2) out2[row * ld2 + col] = (Tout)acc[f][u][r];
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-    }
+  }
+  // dependent columns (mode 0 only): the same places again, now with the
+  // completion values (one rolled loop, so the generator is inlined once)
+  if (*mode != 0) return;
+  for (int e = 0; e < 4 * RF * 4; ++e) {
+    const int u = e / (RF * 4), f = (e / 4) % RF, r = e % 4;
+    const int col = (J0 + u) * kTile + lc;
+    if (J0 + u >= J1 || col >= d || flags[col] == 0) continue;
+    const int64_t row = r0 + (wave * RF + f) * kTile + lr + 4 * r;
+    if (row >= rows) continue;
+    const double v = gaussian_at(seed, key1, (uint64_t)col * rows + row) * inv_sqrt_rows;
+    if (col < ncols1) out1[row * ld1 + col] = (Tout)v;
+    if (out2 && col < ncols2) out2[row * ld2 + col] = (Tout)v;
   }
 }
 
 template <typename Tin, typename Tout>
-hipError_t launch_apply(const Tin* Y, int64_t ldy, int64_t rows, int d, int dp, const double* R,
-                        const double* Rinv16, const int32_t* flags, const int32_t* mode,
-                        const double* Xfull, Tout* out1, int64_t ld1, int ncols1, Tout* out2,
+hipError_t launch_apply(const Tin* Y, int64_t ldy, int64_t rows, int d, int dp, const int32_t* flags,
+                        const int32_t* mode, const double* Xfull, Tout* out1, int64_t ld1, int ncols1, Tout* out2,
                         int64_t ld2, int ncols2, uint64_t seed, uint64_t key1, hipStream_t s,
                         hipEvent_t ev0, hipEvent_t ev1) {
   if (rows <= 0) return hipSuccess;
@@ -215,29 +156,23 @@ hipError_t launch_apply(const Tin* Y, int64_t ldy, int64_t rows, int d, int dp, 
   // workgroups run long triangular loops) once that still gives about four
   // workgroups per CU; narrow R keeps one (measured faster there)
   const int rf = (groups >= 5 && ceil_div(rows, 128) * groups >= 1024) ? 2 : 1;
-  const size_t shmem = apply_lds_doubles(dp, rf) * sizeof(double);
-  const void* fn = rf == 2 ? reinterpret_cast<const void*>(apply_kernel<Tin, Tout, 2>)
-                           : reinterpret_cast<const void*>(apply_kernel<Tin, Tout, 1>);
-  if (shmem > 65536) {  // the substitution rows of a wide R take more than 64 KB
-    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    if (e != hipSuccess) return e;
-  }
+  const size_t shmem = apply_lds_doubles(rf) * sizeof(double);  // at most 55 KB
   if (ev0) (void)hipEventRecord(ev0, s);
   if (rf == 2)
     hipLaunchKernelGGL((apply_kernel<Tin, Tout, 2>), dim3((unsigned)ceil_div(rows, 128), groups), dim3(256), shmem,
-                       s, Y, ldy, rows, d, dp, R, Rinv16, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2,
+                       s, Y, ldy, rows, d, dp, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2,
                        seed, key1, isr);
   else
     hipLaunchKernelGGL((apply_kernel<Tin, Tout, 1>), dim3((unsigned)ceil_div(rows, 64), groups), dim3(256), shmem,
-                       s, Y, ldy, rows, d, dp, R, Rinv16, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2,
+                       s, Y, ldy, rows, d, dp, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2,
                        seed, key1, isr);
   if (ev1) (void)hipEventRecord(ev1, s);
   return hipGetLastError();
 }
 
 #define RQLP_APPLY_INST(TI, TO)                                                                       \
-  template hipError_t launch_apply<TI, TO>(const TI*, int64_t, int64_t, int, int, const double*,     \
-                                           const double*, const int32_t*, const int32_t*, const double*, \
+  template hipError_t launch_apply<TI, TO>(const TI*, int64_t, int64_t, int, int, const int32_t*,    \
+                                           const int32_t*, const double*,                                 \
                                            TO*, int64_t, int, TO*, int64_t,                               \
                                            int, uint64_t, uint64_t, hipStream_t, hipEvent_t, hipEvent_t);
 RQLP_APPLY_INST(float, double)

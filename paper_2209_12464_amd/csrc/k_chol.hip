@@ -511,7 +511,7 @@ hipError_t launch_chol(double* G, int d, int dp, double* R, double* Rinv16, int3
                           Rinv16 + (int64_t)t0 * kTile * kTile, flags + off, info, pass_id, tol, 0.0, esq, nesq,
                           mode, Xfull, gd0 + off, 1, s);
       if (e == hipSuccess && rest > 0) {
-        e = launch_trinv_block(R + (int64_t)off * dp + off, Rinv16 + (int64_t)t0 * kTile * kTile, dp, tbs, mode, 1,
+        e = launch_trinv_block(R + (int64_t)off * dp + off, Rinv16 + (int64_t)t0 * kTile * kTile, dp, tbs, mode,
                                Xfull + (int64_t)off * dp + off, s);
         if (e != hipSuccess) break;
         hipLaunchKernelGGL(chol_panel_kernel, dim3((unsigned)(tbs * (rest / kTile))), dim3(kWave), 0, s, G, dp, off,

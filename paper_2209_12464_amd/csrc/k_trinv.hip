@@ -10,8 +10,9 @@
 // workgroup barrier per block row).  The step loop is unrolled so that the
 // R tiles of each step can be loaded into a register ring several steps
 // before they are used.  The diagonal-block inverses come from
-// the Cholesky.  Nothing is done when the Cholesky marked a dependent column
-// (the solve then substitutes instead).
+// the Cholesky.  Nothing is done after the Cholesky's fast path, which
+// writes its own inverse.  A dependent column has a unit row in R, so the
+// inverse exists and its other columns do not involve it.
 #include "common.h"
 #include "kernels.h"
 
@@ -27,11 +28,11 @@ namespace rqlp {
 template <int kInvWaves, int kInvT, int kInvAhead>
 __device__ __attribute__((always_inline)) inline void trinv_body(const double* __restrict__ R,
                                                                const double* __restrict__ Rinv16, int dp,
-                                                               const int32_t* __restrict__ mode, int any_factor,
+                                                               const int32_t* __restrict__ mode,
                                                                double* __restrict__ X, const int J) {
   constexpr int kInvRows = (kInvT + kInvWaves - 1) / kInvWaves;  // block rows per wave
   __shared__ double Zs[2][kTile][kTile + 1];
-  if (any_factor ? *mode == 2 : *mode != 1) return;
+  if (*mode == 2) return;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane >> 4, lc = lane & 15;
@@ -118,9 +119,9 @@ __device__ __attribute__((always_inline)) inline void trinv_body(const double* _
 template <int kInvWaves, int kInvT, int kInvAhead>
 __global__ __launch_bounds__(kInvWaves * 64) void trinv_kernel(const double* __restrict__ R,
                                                                const double* __restrict__ Rinv16, int dp,
-                                                               const int32_t* __restrict__ mode, int any_factor,
+                                                               const int32_t* __restrict__ mode,
                                                                double* __restrict__ X) {
-  trinv_body<kInvWaves, kInvT, kInvAhead>(R, Rinv16, dp, mode, any_factor, X, blockIdx.x);
+  trinv_body<kInvWaves, kInvT, kInvAhead>(R, Rinv16, dp, mode, X, blockIdx.x);
 }
 
 // Many matrices in one launch: workgroups start[p] .. start[p + 1] - 1 form
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(8 * 64) void trinv_grouped_kernel(TrinvGroup g) {
   int p = 0;
   while (p + 1 < g.count && g.start[p + 1] <= (int)blockIdx.x) ++p;
   const TrinvArgs& a = g.a[p];
-  trinv_body<8, kCholRegMax / kTile, 4>(a.R, a.Rinv16, a.dp, a.mode, 0, a.X, (int)blockIdx.x - g.start[p]);
+  trinv_body<8, kCholRegMax / kTile, 4>(a.R, a.Rinv16, a.dp, a.mode, a.X, (int)blockIdx.x - g.start[p]);
 }
 
 hipError_t launch_trinv_grouped(const TrinvArgs* args, int count, hipStream_t s) {
@@ -155,17 +156,17 @@ hipError_t launch_trinv_grouped(const TrinvArgs* args, int count, hipStream_t s)
 
 hipError_t launch_trinv(const double* R, const double* Rinv16, int dp, const int32_t* mode, double* X,
                         hipStream_t s) {
-  return launch_trinv_block(R, Rinv16, dp, dp / kTile, mode, 0, X, s);
+  return launch_trinv_block(R, Rinv16, dp, dp / kTile, mode, X, s);
 }
 
 hipError_t launch_trinv_block(const double* R, const double* Rinv16, int ld, int nT, const int32_t* mode,
-                              int any_factor, double* X, hipStream_t s) {
+                              double* X, hipStream_t s) {
   if (nT <= kCholRegMax / kTile)
     hipLaunchKernelGGL((trinv_kernel<8, kCholRegMax / kTile, 4>), dim3((unsigned)nT), dim3(8 * kWave), 0, s, R,
-                       Rinv16, ld, mode, any_factor, X);
+                       Rinv16, ld, mode, X);
   else
     hipLaunchKernelGGL((trinv_kernel<16, kDMax / kTile, 2>), dim3((unsigned)nT), dim3(16 * kWave), 0, s, R,
-                       Rinv16, ld, mode, any_factor, X);
+                       Rinv16, ld, mode, X);
   return hipGetLastError();
 }
 

@@ -73,14 +73,13 @@ int gram_chunks(int64_t rows, int dp);
 
 // X = R^-1 (dp x dp, row-major; the blocks on and above the diagonal are
 // written) from the upper Cholesky factor R and its diagonal-block
-// inverses; does nothing unless *mode == 1 (full factorization, no
-// dependent column).
+// inverses; does nothing when *mode == 2 (the fast path wrote its own
+// inverse).
 hipError_t launch_trinv(const double* R, const double* Rinv16, int dp, const int32_t* mode, double* X,
                         hipStream_t s);
-// The same for the nT x nT block upper-triangular R (row stride ld, as X),
-// run when *mode == 1, or, with any_factor, whenever *mode != 2.
+// The same for the nT x nT block upper-triangular R (row stride ld, as X).
 hipError_t launch_trinv_block(const double* R, const double* Rinv16, int ld, int nT, const int32_t* mode,
-                              int any_factor, double* X, hipStream_t s);
+                              double* X, hipStream_t s);
 int gram_reduce_blocks(int dp);
 
 // ---- float64 Cholesky (k_chol.hip) ----
@@ -91,8 +90,8 @@ int gram_reduce_blocks(int dp);
 // fast_tol > 0: when ||G - I||_F < fast_tol (from the nesq partial sums in
 // esq written by launch_gram), use R = I + F (first order)
 // and write the explicit inverse I - F to Xfull (dp x dp); *mode is set to
-// 2 in that case.  After a full factorization *mode is 1 (launch_trinv then
-// forms Xfull = R^-1), or 0 when a column was dependent.  For dp > 256 the
+// 2 in that case.  After a full factorization *mode is 1, or 0 when a column
+// was dependent; launch_trinv then forms Xfull = R^-1 in both cases.  For dp > 256 the
 // factorization is blocked: it overwrites G's trailing blocks, uses Xfull
 // as scratch, and keeps the original diagonal in gd0 (dp doubles).
 hipError_t launch_chol(double* G, int d, int dp, double* R, double* Rinv16, int32_t* flags,
@@ -159,13 +158,12 @@ hipError_t launch_svd_small(const T* M, int64_t ldm, int d, T* U, int64_t ldu, T
 // ---- triangular solve Q = Y R^-1 (k_apply.hip) ----
 // Y: rows x dp (ldy, type Tin); out1 (ld1, first `ncols1` columns, type
 // Tout) and optional out2 (ld2, first `ncols2` columns).  Dependent columns (flags) are replaced
-// by Gaussian columns of stream (seed, key1) divided by sqrt(rows).
-// mode (device, from launch_chol): nonzero -> Q = Y Xfull (explicit
-// inverse), 0 -> blocked substitution with R and Rinv16.
+// by Gaussian columns of stream (seed, key1) divided by sqrt(rows) when
+// *mode == 0 (device, from launch_chol: a column was dependent); the others
+// are Q = Y Xfull (Xfull = R^-1 from launch_trinv or the fast path).
 template <typename Tin, typename Tout>
-hipError_t launch_apply(const Tin* Y, int64_t ldy, int64_t rows, int d, int dp, const double* R,
-                        const double* Rinv16, const int32_t* flags, const int32_t* mode,
-                        const double* Xfull, Tout* out1, int64_t ld1, int ncols1, Tout* out2,
+hipError_t launch_apply(const Tin* Y, int64_t ldy, int64_t rows, int d, int dp, const int32_t* flags,
+                        const int32_t* mode, const double* Xfull, Tout* out1, int64_t ld1, int ncols1, Tout* out2,
                         int64_t ld2, int ncols2, uint64_t seed, uint64_t key1, hipStream_t s,
                         hipEvent_t ev0, hipEvent_t ev1);
 

@@ -314,16 +314,16 @@ rqlp_status cholqr2(rqlp_ctx* c, const T* Y, int64_t ldy, int64_t rows, int d, c
   HIP_TRY(factor(c, b, b.r1, b.flags, d, dp, orth_index, 0.0, mode, nesq, s));
   if (live(c)) {
     t = timer(c, RQLP_KT_APPLY);
-    HIP_TRY((launch_apply<T, double>(Y, ldy, rows, d, dp, b.r1, b.rinv, b.flags, mode, b.xf, b.q1, dp, dp, nullptr,
-                                     0, 0, seed, completion_key(orth_index, 0), s, t.a, t.b)));
+    HIP_TRY((launch_apply<T, double>(Y, ldy, rows, d, dp, b.flags, mode, b.xf, b.q1, dp, dp, nullptr, 0, 0, seed,
+                                     completion_key(orth_index, 0), s, t.a, t.b)));
     t = timer(c, RQLP_KT_GRAM);
     HIP_TRY(launch_gram<double>(b.q1, dp, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
   }
   HIP_TRY(factor(c, b, b.r2, b.flags + dp, d, dp, orth_index, ftol, mode + 1, nesq, s));
   if (live(c)) {
     t = timer(c, RQLP_KT_APPLY);
-    HIP_TRY((launch_apply<double, T>(b.q1, dp, rows, d, dp, b.r2, b.rinv, b.flags + dp, mode + 1, b.xf, out1, ld1,
-                                     ncols1, out2, ld2, ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b)));
+    HIP_TRY((launch_apply<double, T>(b.q1, dp, rows, d, dp, b.flags + dp, mode + 1, b.xf, out1, ld1, ncols1, out2, ld2,
+                                     ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b)));
   }
   return RQLP_OK;
 }
