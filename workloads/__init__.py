@@ -65,7 +65,9 @@ def spectrum(kind, count, **kw):
         return np.where(i <= k, 1.0, np.maximum(i - k + 1.0, 1.0) ** (-z))
     if kind == "lowrank_linear":
         # Section V-B: decreasing linearly from 1 to 1e-10 over all n
-        # positions, zero after the first k (see the reading in the design doc)
+        # positions, zero after the first k (the paper's wording is ambiguous;
+        # this reading is the one that reproduces its printed Theorem-bound
+        # curves)
         k, n = kw["k"], kw["n"]
         s = np.linspace(1.0, 1e-10, count)
         return np.where(i <= k, s, 0.0)
