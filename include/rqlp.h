@@ -8,10 +8,10 @@
  * Algorithm 1 (Section III-A) with the power iteration of Algorithm 2
  * (Section III-B), applied in the column-sketch orientation:
  *
- *   Omega = randn(n, d)           Gaussian test matrix (Section III-A, step 1)
+ *   Omega = randn(n, d)           Gaussian test matrix (Section III-A, the sketch)
  *   Q     = orth(A Omega)         sketch and orthonormal basis
  *   q times: W = orth(A^T Q); Q = orth(A W)        (Algorithm 2)
- *   B^T   = A^T Q                 projection (Section III-A, step 4)
+ *   B^T   = A^T Q                 projection (Section III-A, the product with A)
  *   [V, Rt] = qr(B^T);  L = Rt^T  unpivoted QR; the L-values diag(L) reveal
  *                                 the numerical rank (Theorem 1, Corollary 1)
  *
@@ -135,7 +135,7 @@ const char* rqlp_status_string(rqlp_status s);
 
 /* ---- Step entry points: each runs one step of the path on its own ---- */
 
-/* Gaussian test matrix (Section III-A step 1; randn of Section II-A).
+/* Gaussian test matrix (the sketch of Section III-A; randn of Section II-A).
  * out: rows x cols, leading dimension ldo >= cols; entries in columns
  * [cols, ldo) are set to zero.  Entry (i, j) has logical index
  * l = j*rows + i; block c = l / 4 is Philox4x64-10 at counter (c, 0, 0, 0)
@@ -206,7 +206,7 @@ rqlp_status rqlp_decompose_paper(rqlp_ctx* ctx, const void* A, int64_t m, int64_
 
 /* Time the split-K candidates of the two products a dense decomposition of
  * this shape issues (Y = A X and Y = A^T X with d columns, float32 or
- * float64 kernel; the products of Section III-A steps 2 and 4) and keep the
+ * float64 kernel; the sketch and projection products of Section III-A) and keep the
  * fastest split count per product shape in the context's plan table; later
  * calls on the context (decompositions, batches, servers, rqlp_gemm) use
  * it.  The default plan fills about two workgroups per CU; candidates go up

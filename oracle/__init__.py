@@ -21,7 +21,7 @@ What it computes follows the paper:
   diagonal in R (Section II-B defines the unpivoted QR; the sign convention
   is this oracle's reading, which makes the factors unique for full column
   rank input).
-* The Gaussian test matrix (Section III-A step 1, randn defined in
+* The Gaussian test matrix (the sketch of Section III-A, randn defined in
   Section II-A) comes from Philox4x64-10 (Salmon et al., SC'11) and the
   Box-Muller transform, so that host and device draw the same numbers.
 

@@ -1,7 +1,7 @@
 """Reconstruction differences and errors, computed blockwise in float64.
 
 Test infrastructure (see the package docstring).  The approximation of
-Algorithm 1 is A-hat = Q L V^T (Section III-A, step 5).  The tolerances
+Algorithm 1 is A-hat = Q L V^T (Section III-A, its final factors).  The tolerances
 compare two approximations by the Frobenius norm of their difference
 (Section II-A defines the norm), never forming an m x n matrix at once.
 

@@ -1,7 +1,7 @@
 """Philox4x64-10 and the Box-Muller normal transform, in plain numpy.
 
 Test infrastructure (see the package docstring).  The paper draws its test
-matrix with randn() (Section II-A, notation; Section III-A step 1) and does
+matrix with randn() (Section II-A, notation; the sketch of Section III-A) and does
 not fix a generator.  Reading used here: a counter-based generator so that
 every entry of the n x d sketch matrix is a function of (seed, index) alone.
 
