@@ -278,7 +278,7 @@ size_t rqlp_workspace_size_batched(int count, const rqlp_problem* problems, rqlp
  * problem is decomposed as by rqlp_decompose, with the same precision
  * (RQLP_FP64, RQLP_FP32 or RQLP_BF16_REFINED; dense A only) and its own
  * slice of the workspace.  The problems' launch sequences are spread over
- * four internal streams forked from and joined back into `stream`, so that
+ * eight internal streams forked from and joined back into `stream`, so that
  * the small products of different problems overlap on the device.  With
  * grouping on (the default, rqlp_set_batch_grouping), the problems advance
  * in lockstep from one Cholesky factorization to the next, and the t-th

@@ -38,7 +38,7 @@ struct rqlp_ctx {
   int64_t launches[RQLP_KT_COUNT] = {0};
   // batches: decompositions spread over lanes (streams at the default
   // priority), forked from and joined back into the caller's stream
-  static constexpr int kLanes = 4;
+  static constexpr int kLanes = 8;
   hipStream_t lanes[kLanes] = {};
   hipStream_t cap = nullptr;  // origin stream of graph captures
   hipEvent_t fork = nullptr, join[kLanes] = {};
