@@ -514,12 +514,22 @@ def main():
 
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
-    if w["kind"] == "batch":
-        run_batch_bench(args, w, rqlp, torch, dev)
-        return
-    if w["kind"] == "serve":
-        run_serve_bench(args, w, rqlp, torch, dev)
-        return
+    try:
+        if w["kind"] == "batch":
+            run_batch_bench(args, w, rqlp, torch, dev)
+        elif w["kind"] == "serve":
+            run_serve_bench(args, w, rqlp, torch, dev)
+        else:
+            run_single_bench(args, w, rqlp, torch, dev)
+    finally:
+        # destroy servers and contexts (device sync, stream and buffer
+        # teardown) while the HIP runtime is certainly still up
+        torch.cuda.synchronize()
+        rqlp.close_all()
+
+
+def run_single_bench(args, w, rqlp, torch, dev):
+    """One decomposition per step of a dense or CSR workload."""
     host = make_inputs(w, args.seed)
     ctx = rqlp.Context(0)
     k, p, q = w["k"], w["p"], w["q"]

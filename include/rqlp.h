@@ -323,15 +323,22 @@ rqlp_status rqlp_server_destroy(rqlp_server* server);
 /* Workspace bytes a request takes from the budget (0 when invalid). */
 size_t rqlp_server_request_bytes(const rqlp_problem* request, rqlp_precision prec);
 
-/* Queue a request; *ticket identifies it in poll's reports.  A request
- * whose workspace exceeds the whole budget is refused (RQLP_ERR_OUT_OF_MEMORY). */
-rqlp_status rqlp_server_submit(rqlp_server* server, const rqlp_problem* request, int64_t* ticket);
+/* Queue a request; *ticket identifies it in poll's reports.  An event is
+ * recorded on `stream` (a hipStream_t as void*, NULL for the default
+ * stream) and the request's launches wait on it, so work the caller
+ * enqueued on that stream before submitting (such as writing A) is complete
+ * before the request reads its inputs.  A request whose workspace exceeds
+ * the whole budget is refused (RQLP_ERR_OUT_OF_MEMORY). */
+rqlp_status rqlp_server_submit(rqlp_server* server, const rqlp_problem* request, void* stream, int64_t* ticket);
 
-/* Report up to max_done finished tickets (their outputs are complete on the
- * device), then admit and launch queued requests.  inflight and queued (may
- * be NULL) receive the counts after the call. */
-rqlp_status rqlp_server_poll(rqlp_server* server, int64_t* done, int max_done, int* ndone, int* inflight,
-                             int* queued);
+/* Report up to max_done finished tickets, then admit and launch queued
+ * requests.  done[i] is a ticket; status[i] (status may be NULL) is RQLP_OK
+ * when its outputs are complete on the device, or the error its launch
+ * returned (the request then ran partly or not at all, and its outputs are
+ * undefined; its workspace was released only after its stream drained).
+ * inflight and queued (may be NULL) receive the counts after the call. */
+rqlp_status rqlp_server_poll(rqlp_server* server, int64_t* done, int32_t* status, int max_done, int* ndone,
+                             int* inflight, int* queued);
 
 /* ---- Timing hooks (benchmarking) ---- */
 

@@ -1333,8 +1333,18 @@ struct rqlp_server {
     int64_t ticket = -1;
     size_t off = 0, size = 0;
   };
+  // A queued request and the event recorded on the submitter's stream at
+  // submit: the slot stream waits on it, so work the caller enqueued before
+  // submitting (writing A, say) is complete before the request reads it.
+  struct Queued {
+    int64_t ticket;
+    rqlp_problem prob;
+    hipEvent_t ready;
+  };
   std::vector<Slot> slots;
-  std::deque<std::pair<int64_t, rqlp_problem>> queue;
+  std::deque<Queued> queue;
+  std::vector<hipEvent_t> event_pool;
+  std::deque<std::pair<int64_t, rqlp_status>> failed;  // launches that failed, reported by poll
   std::map<size_t, size_t> free_ranges;  // offset -> bytes, coalesced
   int64_t next_ticket = 0;
   int64_t inflight_bytes = 0;
@@ -1372,8 +1382,10 @@ void pool_free(rqlp_server* sv, size_t off, size_t bytes) {
   }
 }
 
-rqlp_status launch_request(rqlp_server* sv, rqlp_server::Slot& sl, const rqlp_problem& P) {
+rqlp_status launch_request(rqlp_server* sv, rqlp_server::Slot& sl, const rqlp_server::Queued& rq) {
   rqlp_ctx* c = sv->ctx;
+  const rqlp_problem& P = rq.prob;
+  HIP_TRY(hipStreamWaitEvent(sl.s, rq.ready, 0));
   const uint32_t timing = c->timing;
   c->timing = 0;
   c->reset_info = false;
@@ -1393,6 +1405,17 @@ rqlp_status launch_request(rqlp_server* sv, rqlp_server::Slot& sl, const rqlp_pr
   if (st != RQLP_OK) return st;
   HIP_TRY(hipEventRecord(sl.done, sl.s));
   return RQLP_OK;
+}
+
+hipEvent_t take_server_event(rqlp_server* sv) {
+  if (!sv->event_pool.empty()) {
+    hipEvent_t e = sv->event_pool.back();
+    sv->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
 }
 
 }  // namespace
@@ -1440,6 +1463,8 @@ rqlp_status rqlp_server_destroy(rqlp_server* sv) {
     if (sl.done) hipEventDestroy(sl.done);
     if (sl.s) hipStreamDestroy(sl.s);
   }
+  for (auto& rq : sv->queue) hipEventDestroy(rq.ready);
+  for (hipEvent_t e : sv->event_pool) hipEventDestroy(e);
   if (sv->pool) hipFree(sv->pool);
   delete sv;
   return RQLP_OK;
@@ -1450,22 +1475,35 @@ size_t rqlp_server_request_bytes(const rqlp_problem* req, rqlp_precision prec) {
   return problem_ws_bytes(*req, prec);
 }
 
-rqlp_status rqlp_server_submit(rqlp_server* sv, const rqlp_problem* req, int64_t* ticket) {
+rqlp_status rqlp_server_submit(rqlp_server* sv, const rqlp_problem* req, void* stream, int64_t* ticket) {
   if (!sv || !req || !ticket) return RQLP_ERR_INVALID_ARG;
   rqlp_status st = check_problem(*req, sv->prec);
   if (st != RQLP_OK) return st;
   if (problem_ws_bytes(*req, sv->prec) > sv->budget) return RQLP_ERR_OUT_OF_MEMORY;
+  if (hipSetDevice(sv->ctx->device) != hipSuccess) return RQLP_ERR_HIP;
+  hipEvent_t ready = take_server_event(sv);
+  if (!ready) return RQLP_ERR_HIP;
+  if (hipEventRecord(ready, (hipStream_t)stream) != hipSuccess) {
+    sv->event_pool.push_back(ready);
+    return RQLP_ERR_HIP;
+  }
   *ticket = sv->next_ticket++;
-  sv->queue.emplace_back(*ticket, *req);
+  sv->queue.push_back({*ticket, *req, ready});
   return RQLP_OK;
 }
 
-rqlp_status rqlp_server_poll(rqlp_server* sv, int64_t* done, int max_done, int* ndone, int* inflight,
-                             int* queued) {
+rqlp_status rqlp_server_poll(rqlp_server* sv, int64_t* done, int32_t* status, int max_done, int* ndone,
+                             int* inflight, int* queued) {
   if (!sv || !ndone || (max_done > 0 && !done)) return RQLP_ERR_INVALID_ARG;
   if (hipSetDevice(sv->ctx->device) != hipSuccess) return RQLP_ERR_HIP;
   *ndone = 0;
-  // completions (reported up to max_done per call; the rest on later calls)
+  // requests whose launch failed earlier, then completions (up to max_done
+  // per call; the rest on later calls)
+  while (!sv->failed.empty() && *ndone < max_done) {
+    if (status) status[*ndone] = (int32_t)sv->failed.front().second;
+    done[(*ndone)++] = sv->failed.front().first;
+    sv->failed.pop_front();
+  }
   for (auto& sl : sv->slots) {
     if (!sl.busy || *ndone >= max_done) continue;
     const hipError_t q = hipEventQuery(sl.done);
@@ -1473,24 +1511,31 @@ rqlp_status rqlp_server_poll(rqlp_server* sv, int64_t* done, int max_done, int* 
     if (q != hipSuccess) return RQLP_ERR_HIP;
     sl.busy = false;
     pool_free(sv, sl.off, sl.size);
+    if (status) status[*ndone] = RQLP_OK;
     done[(*ndone)++] = sl.ticket;
   }
   // admissions, in arrival order: the head waits until it fits
   for (auto& sl : sv->slots) {
     if (sl.busy) continue;
     if (sv->queue.empty()) break;
-    const rqlp_problem P = sv->queue.front().second;
-    const size_t need = problem_ws_bytes(P, sv->prec);
+    const rqlp_server::Queued rq = sv->queue.front();
+    const size_t need = problem_ws_bytes(rq.prob, sv->prec);
     size_t off = 0;
     if (!pool_alloc(sv, need, &off)) break;
     sl.off = off;
     sl.size = need;
-    sl.ticket = sv->queue.front().first;
+    sl.ticket = rq.ticket;
     sv->queue.pop_front();
-    rqlp_status st = launch_request(sv, sl, P);
+    const rqlp_status st = launch_request(sv, sl, rq);
+    sv->event_pool.push_back(rq.ready);  // the slot's wait on it is already enqueued
     if (st != RQLP_OK) {
+      // part of the request may already be on the slot's stream: let it
+      // drain before its workspace goes back to the pool, and report the
+      // ticket as failed
+      if (hipStreamSynchronize(sl.s) != hipSuccess) return RQLP_ERR_HIP;
       pool_free(sv, off, need);
-      return st;
+      sv->failed.emplace_back(rq.ticket, st);
+      continue;
     }
     sl.busy = true;
   }

@@ -5,8 +5,10 @@ current HIP stream; every step runs in the library's HIP kernels.  Loading
 fails loudly when the library is missing -- there is no fallback path.
 """
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import torch
 
@@ -95,9 +97,9 @@ def _lib():
             "rqlp_server_create": (_INT, [ctypes.POINTER(_P), _P, _SZ, _INT, _INT]),
             "rqlp_server_destroy": (_INT, [_P]),
             "rqlp_server_request_bytes": (_SZ, [ctypes.POINTER(Problem), _INT]),
-            "rqlp_server_submit": (_INT, [_P, ctypes.POINTER(Problem), ctypes.POINTER(_I64)]),
-            "rqlp_server_poll": (_INT, [_P, ctypes.POINTER(_I64), _INT, ctypes.POINTER(_INT),
-                                        ctypes.POINTER(_INT), ctypes.POINTER(_INT)]),
+            "rqlp_server_submit": (_INT, [_P, ctypes.POINTER(Problem), _P, ctypes.POINTER(_I64)]),
+            "rqlp_server_poll": (_INT, [_P, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32), _INT,
+                                        ctypes.POINTER(_INT), ctypes.POINTER(_INT), ctypes.POINTER(_INT)]),
             "rqlp_set_timing": (_INT, [_P, _INT]),
             "rqlp_set_timing_mask": (_INT, [_P, ctypes.c_uint32]),
             "rqlp_get_timing": (_INT, [_P, _INT, ctypes.POINTER(ctypes.c_double),
@@ -152,6 +154,22 @@ def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+# Every live Context and Server, so that they can be destroyed at
+# interpreter exit while the HIP runtime is still up (not from __del__
+# during module teardown, when the runtime may already be gone).
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def close_all():
+    """Destroy every live server, then every live context."""
+    for obj in [o for o in list(_LIVE) if isinstance(o, Server)]:
+        obj.close()
+    for obj in list(_LIVE):
+        obj.close()
+    _DEFAULT.clear()
+
+
 class Context:
     """Owns an rqlp_ctx on one device (and its info record)."""
 
@@ -160,6 +178,13 @@ class Context:
         h = ctypes.c_void_p()
         _check(_lib().rqlp_create(ctypes.byref(h), self.device.index or 0), "rqlp_create")
         self._h = h
+        _LIVE.add(self)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def close(self):
         if getattr(self, "_h", None):
@@ -424,9 +449,18 @@ class Server:
                                          self._prec), "rqlp_server_create")
         self._h = h
         self._done = (ctypes.c_int64 * 256)()
+        self._status = (ctypes.c_int32 * 256)()
+        self.failed = {}  # ticket -> status of requests whose launch failed
+        _LIVE.add(self)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def close(self):
-        if self._h:
+        if getattr(self, "_h", None):
             _lib().rqlp_server_destroy(self._h)
             self._h = None
 
@@ -437,18 +471,27 @@ class Server:
             pass
 
     def submit(self, A, k, p, q, seed, out):
+        """Queue a request; its launches wait for the work enqueued so far on
+        the current stream of A's device."""
         Q, L, V = out
         pr = Problem(_ptr(A), A.shape[0], A.shape[1], A.stride(0), k, p, q, seed, _ptr(Q), _ptr(L), _ptr(V))
         t = ctypes.c_int64()
-        _check(_lib().rqlp_server_submit(self._h, ctypes.byref(pr), ctypes.byref(t)), "rqlp_server_submit")
+        _check(_lib().rqlp_server_submit(self._h, ctypes.byref(pr), _stream(A.device), ctypes.byref(t)),
+               "rqlp_server_submit")
         return t.value
 
     def poll(self):
-        """(finished tickets, in flight, queued)."""
+        """(finished tickets, in flight, queued).  Tickets whose launch failed
+        are reported too and recorded in self.failed (ticket -> status)."""
         nd, inf, qd = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(_lib().rqlp_server_poll(self._h, self._done, len(self._done), ctypes.byref(nd), ctypes.byref(inf),
-                                       ctypes.byref(qd)), "rqlp_server_poll")
-        return [self._done[i] for i in range(nd.value)], inf.value, qd.value
+        _check(_lib().rqlp_server_poll(self._h, self._done, self._status, len(self._done), ctypes.byref(nd),
+                                       ctypes.byref(inf), ctypes.byref(qd)), "rqlp_server_poll")
+        out = []
+        for i in range(nd.value):
+            out.append(self._done[i])
+            if self._status[i] != RQLP_OK:
+                self.failed[self._done[i]] = self._status[i]
+        return out, inf.value, qd.value
 
 
 def decompose_csr(rowptr, colidx, vals, m, n, k, p, q=0, seed=0, ctx=None, workspace=None, out=None):

@@ -1,6 +1,15 @@
 """Parity of the whole method (rqlp_decompose / rqlp_decompose_csr) with the
 oracle.  Delta = ||Q L V^T - Qo Lo Vo^T||_F / ||A||_F must be <= 1e-12 on the
-float64 path and <= 1e-5 on the float32 path."""
+float64 path and <= 1e-5 on the float32 path.
+
+Where the sketch has full column rank the factors are unique (unpivoted QR
+with a positive diagonal), so Q, L and V are also compared with the oracle's
+factor by factor, against the sensitivity of each factor to the working
+precision's accumulation error (tests/fp32_model.py): Q and V column by
+column, L entry by entry.  That covers the L-values diag(L), the
+rank-revealing output of Algorithm 1 (Section III-A, Corollary 1), which the
+norm Delta cannot see (a sign flip shared by a column of Q and a row of L
+leaves Q L V^T unchanged)."""
 import numpy as np
 import pytest
 import torch
@@ -9,6 +18,7 @@ import oracle
 from oracle.metrics import recon_diff, recon_error, orth_error
 import workloads
 from tests import pins
+from tests.fp32_model import factor_deviation, ruqlp_model
 from tests.gpu_util import announce, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
@@ -26,6 +36,16 @@ def _omega_dtype(dtype):
     return "f32" if dtype == torch.float32 else "f64"
 
 
+def _orth_tol(dtype, d):
+    """||Q^T Q - I||_F bound.  Float32: the second CholeskyQR pass runs in
+    float64 and Q is rounded once to float32, which perturbs Q^T Q - I by
+    about d u32 / sqrt(rows) <= sqrt(d) u32; allow 16 sqrt(d) u32.  Float64:
+    CholeskyQR2's own orthogonality error, 100 d u64-ish."""
+    if dtype == torch.float32:
+        return 16.0 * np.sqrt(d) * 2.0 ** -24
+    return 100 * d * 1e-15
+
+
 def _check_against_oracle(A_np, Qg, Lg, Vg, k, p, q, seed, dtype, factors=True):
     A64 = A_np.astype(np.float64)
     Qo, Lo, Vo = oracle.ruqlp(A64, k, p, q, seed, omega_dtype=_omega_dtype(dtype))
@@ -34,9 +54,18 @@ def _check_against_oracle(A_np, Qg, Lg, Vg, k, p, q, seed, dtype, factors=True):
     tol = TOL[dtype]
     d = k + p
     assert delta <= tol, f"Delta {delta:.3e} > {tol}"
-    assert orth_error(Qg) <= 100 * d * (tol if dtype == torch.float32 else 1e-15)
-    assert orth_error(Vg) <= 100 * d * (tol if dtype == torch.float32 else 1e-15)
+    eq, ev = orth_error(Qg), orth_error(Vg)
+    assert eq <= _orth_tol(dtype, d) and ev <= _orth_tol(dtype, d), (eq, ev)
     assert np.all(np.triu(Lg, 1) == 0.0)
+    assert np.all(np.diag(Lg) >= 0.0)
+    if factors:
+        model = ruqlp_model(A64, k, p, q, seed, dtype=_omega_dtype(dtype))
+        rep = factor_deviation((Qg, Lg, Vg), (Qo, Lo, Vo), model, dtype=_omega_dtype(dtype))
+        print(f"factors {A_np.shape} k={k} p={p} q={q} {dtype}: Delta={delta:.3e} orth Q {eq:.2e} V {ev:.2e} "
+              f"ratios Q {rep['Q']['max_ratio']:.3f} V {rep['V']['max_ratio']:.3f} L {rep['L']['max_ratio']:.3f} "
+              f"informative cols Q {rep['Q']['informative_cols']}/{d} V {rep['V']['informative_cols']}/{d} "
+              f"max|dL| {rep['L']['max_err']:.2e} max|d diag L| {rep['L']['diag_max_err']:.2e}", flush=True)
+        assert rep["ok"], rep
     return delta, (Qo, Lo, Vo)
 
 
@@ -76,7 +105,7 @@ def test_gapped_fp32_midsize(gpu_lib, q):
     announce("decompose gapped fp32 midsize", q)
     c = workloads.cfg_gapped_fp32(seed=5, m=3000, n=2500, q=q)
     Qg, Lg, Vg = _run(gpu_lib, c["A"], 200, 10, q, 8, torch.float32)
-    _check_against_oracle(c["A"], Qg, Lg, Vg, 200, 10, q, 8, torch.float32, factors=False)
+    _check_against_oracle(c["A"], Qg, Lg, Vg, 200, 10, q, 8, torch.float32)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -133,59 +162,76 @@ def test_bitwise_deterministic(gpu_lib):
         assert torch.equal(a, b)
 
 
-def test_full_size_gapped_fp32(gpu_lib):
-    """8000 x 8000 FP32, gapped spectrum, k = 200, p = 10, q = 1: the
-    benchmark workload, in the launch configuration the benchmark uses."""
-    announce("decompose full 8000^2 fp32 q=1")
-    c = workloads.cfg_gapped_fp32(seed=2, q=1)
-    Qg, Lg, Vg = _run(gpu_lib, c["A"], 200, 10, 1, 2024, torch.float32)
-    _check_against_oracle(c["A"], Qg, Lg, Vg, 200, 10, 1, 2024, torch.float32, factors=False)
+@pytest.mark.parametrize("q", [1, 0])
+def test_full_size_gapped_fp32(gpu_lib, q):
+    """8000 x 8000 FP32, gapped spectrum, k = 200, p = 10, q in {1, 0}: the
+    benchmark workload, in the launch configuration the benchmark uses.
+    Beyond Delta, the factors are compared with the oracle's (the sketch has
+    full rank), diag(L) >= 0, and the L-values reveal the gap: the first 200
+    are ~1 and the last 10 ~ sigma_201 = 1e-3."""
+    announce("decompose full 8000^2 fp32", q)
+    c = workloads.cfg_gapped_fp32(seed=2, q=q)
+    Qg, Lg, Vg = _run(gpu_lib, c["A"], 200, 10, q, 2024, torch.float32)
+    _, (Qo, Lo, Vo) = _check_against_oracle(c["A"], Qg, Lg, Vg, 200, 10, q, 2024, torch.float32)
+    dg = np.diag(Lg)
+    assert dg[:200].min() > 100.0 * dg[200:].max()
+    # sigma_i(L) <= sigma_i(A), up to the float32 rounding of A and of the factors
+    ok, info = pins.check_sv_interlacing(c["sigma"], Lg, rel=1e-5)
+    assert ok, info
 
 
 # ---------------------------------------------------------------- bfloat16 products
-# Stated tolerances of the bfloat16 form (RQLP_BF16_REFINED):
-#  - against the oracle with the same bfloat16 rounding of the product
-#    operands (operand_dtype="bf16"): Delta <= 5e-4.  The GPU accumulates in
-#    float32 and rounds its float32 Q to bfloat16, so an operand within
-#    float32 noise (~1e-7) of a rounding boundary (spacing 2^-8) can round
-#    to the neighbour: about 2.5e-5 of the operands move by one bfloat16
-#    ulp, a ~2e-5 relative change of each product, which the power steps
-#    carry into the basis (measured: 5e-5 to 1.3e-4).
-#  - against the plain float64 oracle: Delta <= 2e-2, and the error
-#    e = ||A - Q L V^T||_F / ||A||_F at most the float64 method's plus the
-#    rounding noise that survives the projections (below).
+# Stated tolerances of the bfloat16 form (RQLP_BF16_REFINED), all against
+# the oracle with the same bfloat16 rounding of the product operands
+# (operand_dtype="bf16": A, Omega, Q and W rounded to bfloat16, products
+# then exact):
+#  - Delta <= 5e-4.  The device accumulates in float32 and rounds its
+#    float32 Q to bfloat16, so an operand within float32 noise of a rounding
+#    boundary (spacing 2^-8) can round to the neighbour.  The float32
+#    accumulation model of tests/fp32_model.py applied to the bfloat16
+#    operands moves the reconstruction by 1.8e-4 to 3.2e-4 at these shapes.
+#  - the error e = ||A - Q L V^T||_F / ||A||_F within 0.5 % of the emulated
+#    oracle's own e.  The same model moves e by at most 0.08 % (relative).
+#  - against the plain float64 oracle (context, the price of bfloat16
+#    operands): Delta <= 2e-2.
 TOL_BF16_EMUL = 5e-4
+TOL_BF16_E_REL = 5e-3
 TOL_BF16_F64 = 2e-2
 
 
 @pytest.mark.parametrize("m,n,k,p,q", [(2000, 1500, 100, 20, 1), (1200, 1500, 60, 10, 0), (1000, 3000, 150, 20, 1),
-                                       (4000, 3000, 280, 20, 1)])
+                                       (4000, 3000, 280, 20, 1),
+                                       # the 20000 x 15000 workload's shape class: d = 520, q = 1
+                                       (6000, 4500, 500, 20, 1)])
 def test_bf16_products(gpu_lib, m, n, k, p, q):
     announce("decompose bf16", m, n, k, p, q)
     sigma = workloads.spectrum("polynomial", min(m, n), power=1.5)
-    A, _, _, _ = workloads.dense_from_spectrum(m, n, sigma, seed=m + 2 * n, dtype=np.float32, trunc=0.0)
+    big = k + p > 512
+    if big:  # the structured orthogonal factors of the full-size workload (exact spectrum, seconds)
+        A = workloads.dense_fast_orth(m, n, sigma, seed=m + 2 * n, dtype=np.float32)
+    else:
+        A, _, _, _ = workloads.dense_from_spectrum(m, n, sigma, seed=m + 2 * n, dtype=np.float32, trunc=0.0)
     seed = 11
     Q, L, V = gpu_lib.decompose(to_dev(A), k, p, q, seed=seed, bf16=True)
     Qg, Lg, Vg = to_np(Q), to_np(L), to_np(V)
     A64 = A.astype(np.float64)
     nA = np.linalg.norm(A64)
     Qe, Le, Ve = oracle.ruqlp(A64, k, p, q, seed, omega_dtype="bf16", operand_dtype="bf16")
-    Qd, Ld, Vd = oracle.ruqlp(A64, k, p, q, seed, omega_dtype="f64")
     d_emul = recon_diff(Qg, Lg, Vg, Qe, Le, Ve) / nA
-    d_f64 = recon_diff(Qg, Lg, Vg, Qd, Ld, Vd) / nA
     e_gpu = recon_error(A64, Qg, Lg, Vg)
-    e_f64 = recon_error(A64, Qd, Ld, Vd)
-    print(f"bf16 {m}x{n} k={k} p={p} q={q}: Delta(emulated)={d_emul:.3e} Delta(f64)={d_f64:.3e} "
-          f"e={e_gpu:.4e} e_f64={e_f64:.4e}", flush=True)
+    e_emul = recon_error(A64, Qe, Le, Ve)
+    print(f"bf16 {m}x{n} k={k} p={p} q={q}: Delta(emulated)={d_emul:.3e} "
+          f"e={e_gpu:.5e} e_emul={e_emul:.5e} (rel {(e_gpu - e_emul) / e_emul:+.2e})", flush=True)
     assert d_emul <= TOL_BF16_EMUL
-    assert d_f64 <= TOL_BF16_F64
-    # bfloat16 rounding of A and of the right-hand factors adds noise of
-    # relative size ~2^-9 per entry, of which the projections Q Q^T keep a
-    # fraction ~sqrt(2 d / min(m, n)); allow that much (or 5 %) above e_f64
-    allow = max(0.05 * e_f64, 2.0 ** -9 * np.sqrt(2.0 * (k + p) / min(m, n)))
-    assert e_gpu <= e_f64 + allow
-    assert orth_error(Qg) <= 1e-4 and orth_error(Vg) <= 1e-4
-    assert np.all(np.triu(Lg, 1) == 0.0)
+    assert abs(e_gpu - e_emul) <= TOL_BF16_E_REL * e_emul
+    if not big:  # context: the distance to the float64 method (the largest case skips this second oracle run)
+        Qd, Ld, Vd = oracle.ruqlp(A64, k, p, q, seed, omega_dtype="f64")
+        d_f64 = recon_diff(Qg, Lg, Vg, Qd, Ld, Vd) / nA
+        print(f"  Delta(f64)={d_f64:.3e} e_f64={recon_error(A64, Qd, Ld, Vd):.5e}", flush=True)
+        assert d_f64 <= TOL_BF16_F64
+    d = k + p
+    assert orth_error(Qg) <= _orth_tol(torch.float32, d) and orth_error(Vg) <= _orth_tol(torch.float32, d)
+    assert np.all(np.triu(Lg, 1) == 0.0) and np.all(np.diag(Lg) >= 0.0)
 
 
 # ---------------------------------------------------------------- CSR
