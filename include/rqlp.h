@@ -116,6 +116,26 @@ rqlp_status rqlp_decompose(rqlp_ctx* ctx, const void* A, int64_t m, int64_t n, i
                            void* Q, void* L, void* V, void* workspace, size_t ws_bytes,
                            void* stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * rqlp_decompose with the workspace taken from a fixed device array of
+ * RQLP_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU it
+ * runs on until the process ends (the array is located once per device by
+ * rqlp_create).  The call allocates nothing and calls no allocating
+ * routine; event timing (rqlp_set_timing) is ignored for it.  Arguments and
+ * results as for rqlp_decompose (the same launch sequence, so the same
+ * bits).  Returns RQLP_ERR_OUT_OF_MEMORY, enqueuing nothing, when the
+ * problem's workspace (rqlp_workspace_size) exceeds the array.  Every call
+ * on a GPU uses that GPU's one array: calls whose work overlaps on the
+ * device (other streams, other contexts, other host threads) race and give
+ * undefined results; calls ordered on one stream are safe.  The array keeps
+ * the last call's contents; nothing in the method reads workspace it has
+ * not written in the same call. */
+#define RQLP_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+rqlp_status rqlp_decompose_noalloc(rqlp_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda, int k, int p,
+                                   int q, rqlp_precision prec, uint64_t seed, void* Q, void* L, void* V,
+                                   void* stream);
+
 /* RU-QLP of a CSR matrix A (m x n) with nnz stored entries (Section III-D:
  * O(nnz d) work per pass).  rowptr: m+1 int32, colidx: nnz int32 (column
  * indices, no duplicates within a row), vals: nnz values in the working

@@ -14,6 +14,7 @@
 #include <deque>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <new>
@@ -799,6 +800,38 @@ rqlp_status autotune_dense(rqlp_ctx* c, const T* A, int64_t m, int64_t n, int64_
 
 }  // namespace
 
+// ---- scratch memory of the no-allocation entry point -------------------------
+// One copy of this array lives on every GPU the library runs on, from the
+// first use of this file's code object on that GPU until the process ends.
+// Host code never uses the array's name as an address (on the host it is
+// only a stand-in): the device address of each GPU's copy is looked up once
+// per device at rqlp_create and kept in g_scratch.
+static __device__ __align__(256) char scratch[RQLP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Resolve this device's copy of `scratch` (the device must be current).
+rqlp_status scratch_setup(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return RQLP_ERR_UNSUPPORTED;
+  if (g_scratch[device]) return RQLP_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return RQLP_ERR_HIP;
+  g_scratch[device] = ptr;
+  return RQLP_OK;
+}
+
+void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_scratch[device] : nullptr;
+}
+
+}  // namespace
+
 // ===========================================================================
 extern "C" {
 
@@ -809,6 +842,8 @@ rqlp_status rqlp_create(rqlp_ctx** ctx, int device) {
   if (hipGetDeviceCount(&count) != hipSuccess) return RQLP_ERR_HIP;
   if (device < 0 || device >= count) return RQLP_ERR_INVALID_ARG;
   if (hipSetDevice(device) != hipSuccess) return RQLP_ERR_HIP;
+  const rqlp_status sst = scratch_setup(device);
+  if (sst != RQLP_OK) return sst;
   rqlp_ctx* c = new (std::nothrow) rqlp_ctx();
   if (!c) return RQLP_ERR_OUT_OF_MEMORY;
   c->device = device;
@@ -874,6 +909,37 @@ rqlp_status rqlp_decompose(rqlp_ctx* c, const void* A, int64_t m, int64_t n, int
                                 ws_bytes, s);
   return decompose_dense<float>(c, (const float*)A, m, n, lda, k, p, q, seed, (float*)Q, (float*)L, (float*)V,
                                 ws, ws_bytes, s);
+}
+
+rqlp_status rqlp_decompose_noalloc(rqlp_ctx* c, const void* A, int64_t m, int64_t n, int64_t lda, int k, int p,
+                                   int q, rqlp_precision prec, uint64_t seed, void* Q, void* L, void* V,
+                                   void* stream) {
+  if (!c || !A || !Q || !L || !V) return RQLP_ERR_INVALID_ARG;
+  rqlp_status st = check_common(m, n, k, p, q, prec);
+  if (st != RQLP_OK) return st;
+  if (lda < n) return RQLP_ERR_INVALID_ARG;
+  const size_t need = prec == RQLP_FP64 ? layout<double>(m, n, k + p, false, 0).total
+                                        : layout<float>(m, n, k + p, false, 0, prec == RQLP_BF16_REFINED).total;
+  if (need > RQLP_NOALLOC_SCRATCH_BYTES) return RQLP_ERR_OUT_OF_MEMORY;
+  if (hipSetDevice(c->device) != hipSuccess) return RQLP_ERR_HIP;
+  void* ws = scratch_ptr(c->device);
+  if (!ws) return RQLP_ERR_HIP;
+  // the same launch sequence as rqlp_decompose on the scratch array; event
+  // timing (which may create events) is off for the call
+  const uint32_t timing = c->timing;
+  c->timing = 0;
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == RQLP_FP64)
+    st = decompose_dense<double>(c, (const double*)A, m, n, lda, k, p, q, seed, (double*)Q, (double*)L, (double*)V,
+                                 ws, RQLP_NOALLOC_SCRATCH_BYTES, s);
+  else if (prec == RQLP_BF16_REFINED)
+    st = decompose_dense_bf16(c, (const float*)A, m, n, lda, k, p, q, seed, (float*)Q, (float*)L, (float*)V, ws,
+                              RQLP_NOALLOC_SCRATCH_BYTES, s);
+  else
+    st = decompose_dense<float>(c, (const float*)A, m, n, lda, k, p, q, seed, (float*)Q, (float*)L, (float*)V, ws,
+                                RQLP_NOALLOC_SCRATCH_BYTES, s);
+  c->timing = timing;
+  return st;
 }
 
 size_t rqlp_workspace_size_batched(int count, const rqlp_problem* probs, rqlp_precision prec) {

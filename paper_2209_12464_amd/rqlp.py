@@ -62,6 +62,8 @@ def _lib():
             "rqlp_workspace_size_csr": (_SZ, [_I64, _I64, _I64, _INT, _INT, _INT, _INT]),
             "rqlp_decompose": (_INT, [_P, _P, _I64, _I64, _I64, _INT, _INT, _INT, _INT, _U64,
                                       _P, _P, _P, _P, _SZ, _P]),
+            "rqlp_decompose_noalloc": (_INT, [_P, _P, _I64, _I64, _I64, _INT, _INT, _INT, _INT, _U64,
+                                              _P, _P, _P, _P]),
             "rqlp_decompose_csr": (_INT, [_P, _P, _P, _P, _I64, _I64, _I64, _INT, _INT, _INT, _INT,
                                           _U64, _P, _P, _P, _P, _SZ, _P]),
             "rqlp_get_info": (_INT, [_P, ctypes.POINTER(Info)]),
@@ -116,7 +118,7 @@ def _lib():
 def exported_symbols():
     """Names of the C ABI functions this binding expects."""
     return ["rqlp_create", "rqlp_destroy", "rqlp_workspace_size", "rqlp_workspace_size_csr",
-            "rqlp_decompose", "rqlp_decompose_csr", "rqlp_get_info", "rqlp_status_string",
+            "rqlp_decompose", "rqlp_decompose_noalloc", "rqlp_decompose_csr", "rqlp_get_info", "rqlp_status_string",
             "rqlp_gaussian", "rqlp_gemm_workspace_size", "rqlp_gemm", "rqlp_orth_workspace_size",
             "rqlp_orth", "rqlp_spmm", "rqlp_csr_transpose_workspace_size", "rqlp_csr_transpose",
             "rqlp_set_timing", "rqlp_set_timing_mask", "rqlp_get_timing",
@@ -305,6 +307,27 @@ def decompose(A, k, p, q=0, seed=0, ctx=None, workspace=None, out=None, bf16=Fal
     _check(_lib().rqlp_decompose(ctx.handle, _ptr(A), m, n, A.stride(0), k, p, q, prec, seed,
                                  _ptr(Q), _ptr(L), _ptr(V), ws_ptr, ws_bytes, _stream(A.device)),
            "rqlp_decompose")
+    return Q, L, V
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20  # RQLP_NOALLOC_SCRATCH_BYTES
+
+
+def decompose_noalloc(A, k, p, q=0, seed=0, ctx=None, out=None, bf16=False):
+    """rqlp_decompose_noalloc: decompose() with the library's fixed scratch
+    array as workspace (no device allocation by the library; pass `out` to
+    avoid torch's allocations too)."""
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D row-major tensor")
+    ctx = ctx or default_context(A.device.index or 0)
+    m, n = A.shape
+    d = k + p
+    if out is None:
+        out = (torch.empty((m, d), dtype=A.dtype, device=A.device), torch.empty((d, d), dtype=A.dtype, device=A.device),
+               torch.empty((n, d), dtype=A.dtype, device=A.device))
+    Q, L, V = out
+    _check(_lib().rqlp_decompose_noalloc(ctx.handle, _ptr(A), m, n, A.stride(0), k, p, q, _prec(A.dtype, bf16), seed,
+                                         _ptr(Q), _ptr(L), _ptr(V), _stream(A.device)), "rqlp_decompose_noalloc")
     return Q, L, V
 
 

@@ -72,6 +72,9 @@ def test_null_context_is_rejected(lib):
                                 2, 1, 0, 1, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
                                 nul, 0, nul)
     assert st == 1
+    st = lib.rqlp_decompose_noalloc(nul, ctypes.c_void_p(16), 10, 10, 10, 2, 1, 0, 1, 0, ctypes.c_void_p(16),
+                                    ctypes.c_void_p(16), ctypes.c_void_p(16), nul)
+    assert st == 1
     assert lib.rqlp_create(None, 0) == 1
     assert lib.rqlp_destroy(nul) == 0
     assert lib.rqlp_set_timing(nul, 1) == 1
