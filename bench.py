@@ -108,6 +108,55 @@ def load_traffic(workload, kernel):
     return ent.get("bytes_per_launch")
 
 
+def load_mfma_util(workload, kernel):
+    """MFMA utilization (fraction of SIMD cycles with the matrix core busy)
+    of `kernel` from the rocprofv3 SQ_VALU_MFMA_BUSY_CYCLES / GRBM_GUI_ACTIVE
+    run recorded in profiles/mfma.json, if taken on the kernel's current
+    sources; else None."""
+    path = os.path.join(ROOT, "profiles", "mfma.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(workload, {}).get(kernel)
+    if not ent or ent.get("source_hash") != kernel_source_hash(kernel):
+        return None
+    return ent.get("mfma_util")
+
+
+def record_mfma(workload, pmc_csv, simds=1024, xcds=8):
+    """MFMA utilization per dispatch of the timed product kernels from a
+    rocprofv3 counter CSV holding SQ_VALU_MFMA_BUSY_CYCLES (summed over all
+    SIMDs) and GRBM_GUI_ACTIVE (summed over the XCDs): busy / (active / xcds
+    * simds); stored in profiles/mfma.json with the kernel's source hash."""
+    busy = read_counter(pmc_csv, "SQ_VALU_MFMA_BUSY_CYCLES")
+    active = read_counter(pmc_csv, "GRBM_GUI_ACTIVE")
+    mops = read_counter(pmc_csv, "SQ_INSTS_VALU_MFMA_MOPS_F32")
+    path = os.path.join(ROOT, "profiles", "mfma.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        rec = {}
+    out = {}
+    for name, bv in busy.items():
+        cls = kernel_class(name)
+        if cls is None or name not in active:
+            continue
+        util = [b / (a / xcds * simds) for b, a in zip(bv, active[name])]
+        ent = {"mfma_util": float(np.mean(util)), "dispatches": len(util),
+               "busy_cycles": float(np.mean(bv)), "gui_active_per_xcd": float(np.mean(active[name])) / xcds,
+               "source_hash": kernel_source_hash(cls)}
+        if name in mops:
+            ent["mfma_flops_f32"] = float(np.mean(mops[name])) * 512.0
+        out[cls] = ent
+    rec[workload] = out
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    print(json.dumps({workload: out}, indent=1), flush=True)
+
+
 def make_inputs(w, seed):
     import workloads
     if w["kind"] == "dense":
@@ -495,10 +544,15 @@ def main():
                     help="run only a plain 1 GiB device copy (x5), to scale FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV"),
                     help="write profiles/traffic.json for --workload from rocprofv3 counter CSVs (no GPU use)")
+    ap.add_argument("--record-mfma", metavar="PMC_CSV",
+                    help="write profiles/mfma.json for --workload from a rocprofv3 counter CSV (no GPU use)")
     args = ap.parse_args()
 
     if args.record_traffic:
         record_traffic(args.workload, *args.record_traffic, cal_bytes=float(1 << 30))
+        return
+    if args.record_mfma:
+        record_mfma(args.workload, args.record_mfma)
         return
 
     if args.gpus != 1:
@@ -619,16 +673,24 @@ def run_single_bench(args, w, rqlp, torch, dev):
             achieved = dom_flops[kname] / step_s / 1e12
             traffic = load_traffic(args.workload, kname)
             roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                        "frac": achieved / peak, "traffic": traffic, "kernel": kname}
+                        "frac": achieved / peak, "traffic": traffic, "kernel": kname,
+                        "mfma_util": load_mfma_util(args.workload, kname),
+                        "timed": "product kernel and its split-K reduction, HIP events on the launch stream"}
         else:
             # gather-inclusive bytes of one A X product: indices+values, row
             # pointers, one gathered X row per entry, the output rows
             es = 4
             byts = nnz * (4 + es) + (m + 1) * 4 + nnz * d * es + m * d * es
+            # compulsory bytes: every input read once (A, row pointers, X) and Y written
+            comp = nnz * (4 + es) + (m + 1) * 4 + n * d * es + m * d * es
             achieved = byts / avg_s / 1e9
             traffic = load_traffic(args.workload, kname)
             roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
-                        "frac": achieved / PEAK["hbm_gbs"], "traffic": traffic, "kernel": kname}
+                        "frac": achieved / PEAK["hbm_gbs"], "traffic": traffic, "kernel": kname,
+                        "achieved_is": "effective bandwidth counting every gathered X row (gather-inclusive bytes)",
+                        "compulsory_gbs": comp / avg_s / 1e9,
+                        "compulsory_frac": comp / avg_s / 1e9 / PEAK["hbm_gbs"],
+                        "compulsory_bytes": comp, "gather_inclusive_bytes": byts}
 
     vs_fp32 = None
     if bf16 and not args.no_compare:

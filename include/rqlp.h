@@ -365,8 +365,8 @@ rqlp_status rqlp_server_poll(rqlp_server* server, int64_t* done, int32_t* status
 /* Kernel classes whose launches can be timed with HIP events recorded on
  * the call's stream around each launch. */
 typedef enum {
-  RQLP_KT_GEMM_NN = 0,   /* dense A X main kernel      */
-  RQLP_KT_GEMM_TN = 1,   /* dense A^T X main kernel    */
+  RQLP_KT_GEMM_NN = 0,   /* dense A X product, split-K reduction included   */
+  RQLP_KT_GEMM_TN = 1,   /* dense A^T X product, split-K reduction included */
   RQLP_KT_SPMM = 2,      /* CSR times dense            */
   RQLP_KT_GRAM = 3,      /* float64 Gram partials      */
   RQLP_KT_CHOL = 4,      /* float64 Cholesky           */

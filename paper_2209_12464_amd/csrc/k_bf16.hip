@@ -315,8 +315,12 @@ hipError_t launch_gemm_bf16(const uint16_t* A, int64_t lda, const uint16_t* Xt, 
     }
   }
 #undef RQLP_BF_LAUNCH
+  if (nsplit > 1) {
+    const hipError_t e = launch_splitk_reduce_f32(P, nsplit, M, nst, Y, ldy, s);
+    if (e != hipSuccess) return e;
+  }
+  // the timed interval covers the product and its split-K reduction
   if (ev1) (void)hipEventRecord(ev1, s);
-  if (nsplit > 1) return launch_splitk_reduce_f32(P, nsplit, M, nst, Y, ldy, s);
   return hipGetLastError();
 }
 

@@ -384,7 +384,6 @@ hipError_t launch_gemm(GemmArgs<T> g, T* Y, int64_t ldy, int nst, T* P, hipStrea
       else dispatch_nb<T, false>(gc, s, grid, P + c0, ldp, pslice, nst_c);
     }
   }
-  if (ev1) (void)hipEventRecord(ev1, s);
   if (g.nsplit > 1) {
     const bool vec4 = sizeof(T) == 4 && nst % 4 == 0 && ldy % 4 == 0 && ((uintptr_t)Y & 15) == 0 &&
                       ((uintptr_t)P & 15) == 0;
@@ -397,6 +396,8 @@ hipError_t launch_gemm(GemmArgs<T> g, T* Y, int64_t ldy, int nst, T* P, hipStrea
       hipLaunchKernelGGL(splitk_reduce_kernel<T>, dim3((unsigned)(gr < 8192 ? gr : 8192)), dim3(256), 0,
                          s, P, (int64_t)nst, (int64_t)g.M * nst, g.nsplit, Y, ldy, g.M, nst);
   }
+  // the timed interval covers the product and its split-K reduction
+  if (ev1) (void)hipEventRecord(ev1, s);
   return hipGetLastError();
 }
 hipError_t launch_splitk_reduce_f32(const float* P, int nsplit, int M, int nst, float* Y, int64_t ldy,

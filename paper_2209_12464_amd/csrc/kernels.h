@@ -34,7 +34,7 @@ template <typename T> int gemm_block_rows();
 template <typename T> int gemm_block_cols(int N);
 // Y (M x nst, ldy) = op(A) B; columns [N, nst) of Y are written as zero.
 // P: partial buffer of nsplit * M * nst elements (unused when nsplit == 1).
-// ev0/ev1 (may be null) are recorded around the main kernel.
+// ev0/ev1 (may be null) are recorded around the product and its reduction.
 template <typename T>
 hipError_t launch_gemm(GemmArgs<T> g, T* Y, int64_t ldy, int nst, T* P, hipStream_t s,
                        hipEvent_t ev0, hipEvent_t ev1);
