@@ -47,7 +47,7 @@ WORKLOADS = {
                           svd=True),
     "batch64": dict(kind="batch", count=64, q=1, dtype="f32"),
     # the serving stream: 4096 Poisson-arrival requests over 64 distinct matrices
-    "serve4096": dict(kind="serve", count=4096, pool=64, q=1, dtype="f32", slots=8, budget_gb=8.0),
+    "serve4096": dict(kind="serve", count=4096, pool=64, q=1, dtype="f32", slots=4, tick=16, budget_gb=8.0),
     # bfloat16 products with float32 accumulation, float64 Gram and Cholesky
     "bf16_20000x15000": dict(kind="dense", m=20000, n=15000, k=500, p=20, q=1, dtype="f32",
                              spectrum="polynomial", bf16=True),
@@ -241,7 +241,9 @@ def run_serve_bench(args, w, rqlp, torch, dev):
                      torch.empty((r["n"], d), device=dev)))
     flops = sum(f_alg(pool[j]["m"], pool[j]["n"], pool[j]["k"], pool[j]["p"], q) for j, _ in req)
     ctx = rqlp.Context(0)
-    srv = rqlp.Server(int(w["budget_gb"] * 2 ** 30), slots=w["slots"], ctx=ctx)
+    slots = args.slots or w["slots"]
+    tick = args.tick or w["tick"]
+    srv = rqlp.Server(int(w["budget_gb"] * 2 ** 30), slots=slots, ctx=ctx, max_tick=tick)
 
     def run(arrivals):
         """Submit request i at arrivals[i] (seconds from the start); return
@@ -287,7 +289,7 @@ def run_serve_bench(args, w, rqlp, torch, dev):
         "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "requests": n_req, "distinct_matrices": w["pool"], "q": q,
-                   "slots": w["slots"], "hbm_budget_gb": w["budget_gb"], "m_range": [512, 8192],
+                   "slots": slots, "max_tick": tick, "hbm_budget_gb": w["budget_gb"], "m_range": [512, 8192],
                    "n_range": [256, 4096], "k_range": [8, 256], "p": 10},
         "saturated": {"requests_per_s": sat_rps, "p50_ms": float(np.percentile(lat, 50) * 1e3),
                       "p99_ms": float(np.percentile(lat, 99) * 1e3)},
@@ -361,14 +363,16 @@ def run_batch_bench(args, w, rqlp, torch, dev):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps
 
-    # eager: grouped factorizations (lockstep), then every problem's
-    # sequence on its own stream; graph replay (ungrouped form)
-    eager_ms = timed(lambda: rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs), args.steps)
+    # one step: the batch as grouped launches (every phase of every problem
+    # in one launch per kernel variant, argument tables cached on the device)
+    ms = timed(lambda: rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs), args.steps)
+    # for comparison: every problem's sequence on its own lane stream, eager
+    # and replayed from a captured graph
     ctx.set_batch_grouping(False)
     ungrouped_ms = timed(lambda: rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs), args.steps)
     ctx.set_batch_grouping(True)
     ctx.set_graphs(True)
-    ms = timed(lambda: rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs), args.steps)
+    graph_ms = timed(lambda: rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs), args.steps)
     ctx.set_graphs(False)
     solo_ws = rqlp.alloc_workspace(max(rqlp.workspace_size(r["m"], r["n"], r["k"], r["p"], w["q"], torch.float32)
                                        for r in reqs), dev)
@@ -386,7 +390,7 @@ def run_batch_bench(args, w, rqlp, torch, dev):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "count": w["count"], "q": w["q"], "flops_per_step": flops,
                    "m_range": [512, 8192], "n_range": [256, 4096], "k_range": [8, 256], "p": 10},
-        "batched_eager_ms": eager_ms, "ungrouped_eager_ms": ungrouped_ms, "sequential_ms": seq_ms,
+        "lanes_eager_ms": ungrouped_ms, "lanes_graph_replay_ms": graph_ms, "sequential_ms": seq_ms,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
@@ -536,6 +540,8 @@ def main():
     ap.add_argument("--workload", default="dense8000", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--slots", type=int, default=0, help="serving: tick streams (default: the workload's)")
+    ap.add_argument("--tick", type=int, default=0, help="serving: requests per tick (default: the workload's)")
     ap.add_argument("--no-compare", action="store_true",
                     help="bfloat16 workload: skip the float32 comparison run")
     ap.add_argument("--no-svd-split", action="store_true",

@@ -297,18 +297,21 @@ size_t rqlp_workspace_size_batched(int count, const rqlp_problem* problems, rqlp
 /* Batched RU-QLP (the compute side of serving many uneven requests): every
  * problem is decomposed as by rqlp_decompose, with the same precision
  * (RQLP_FP64, RQLP_FP32 or RQLP_BF16_REFINED; dense A only) and its own
- * slice of the workspace.  The problems' launch sequences are spread over
- * eight internal streams forked from and joined back into `stream`, so that
- * the small products of different problems overlap on the device.  With
- * grouping on (the default, rqlp_set_batch_grouping), the problems advance
- * in lockstep from one Cholesky factorization to the next, and the t-th
- * factorizations (and explicit inverses) of all problems go out together as
- * a few grouped launches, one workgroup (or 16, for the second pass's
- * first-order form) per matrix.  Each result is bitwise the result of
- * rqlp_decompose on the same problem.  With rqlp_set_graphs enabled, a batch
- * submitted twice in a row with identical descriptors and workspace is
- * captured into a HIP graph (ungrouped form) on its second submission and
- * replayed on later ones.  The info record covers the whole batch.  `problems` is read
+ * slice of the workspace.  With grouping on (the default,
+ * rqlp_set_batch_grouping) and RQLP_FP64 or RQLP_FP32, every problem's
+ * launch sequence is recorded once on the host and the batch runs as
+ * grouped launches on `stream`: phase by phase (each Cholesky factorization
+ * is a phase of its own), one launch per kernel variant runs that step for
+ * all problems, each workgroup working on its problem exactly as in the
+ * problem's own launch.  The argument tables of a batch are kept in device
+ * memory and reused when the same batch (descriptors and workspace) comes
+ * again.  With grouping off, or for RQLP_BF16_REFINED, the problems' launch
+ * sequences are spread over eight internal streams forked from and joined
+ * back into `stream`.  Either way each result is bitwise the result of
+ * rqlp_decompose on the same problem.  With rqlp_set_graphs enabled, a
+ * batch takes the lane form, and a batch submitted twice in a row with
+ * identical descriptors and workspace is captured into a HIP graph on its
+ * second submission and replayed on later ones.  The info record covers the whole batch.  `problems` is read
  * during the call only. */
 rqlp_status rqlp_decompose_batched(rqlp_ctx* ctx, int count, const rqlp_problem* problems,
                                    rqlp_precision prec, void* workspace, size_t ws_bytes, void* stream);
@@ -316,29 +319,38 @@ rqlp_status rqlp_decompose_batched(rqlp_ctx* ctx, int count, const rqlp_problem*
 /* Turn graph capture and replay of repeated batches on (1) or off (0). */
 rqlp_status rqlp_set_graphs(rqlp_ctx* ctx, int enabled);
 
-/* Turn the grouped (lockstep) factorizations of batches on (1, default) or
- * off (0: every problem's launch sequence runs on its stream unchanged).
- * The results are the same bits either way.  A batch captured into a graph
- * (rqlp_set_graphs) always takes the ungrouped form. */
+/* Turn grouped batches on (1, default) or off (0: every problem's launch
+ * sequence runs on a lane stream unchanged).  The results are the same bits
+ * either way. */
 rqlp_status rqlp_set_batch_grouping(rqlp_ctx* ctx, int enabled);
 
 /* ---- Serving: continuous batching of requests ---- */
 
 /* A server owns an HBM budget (one device allocation of hbm_budget bytes,
- * sub-allocated first-fit for the requests' workspaces) and `slots`
+ * sub-allocated first-fit for the requests' workspaces) and `slots` tick
  * streams at the default priority.  Requests (rqlp_problem, caller-owned
  * device buffers, precision fixed per server) are queued by submit; poll
- * reports finished requests and admits queued ones in arrival order as soon
- * as a slot is free and the head request's workspace fits, launching each on
- * its slot's stream, so requests admitted while others run overlap with
- * them on the device.  Each result is bitwise the rqlp_decompose result of
- * the same request.  Single-threaded use; the context must outlive the
- * server; its info record accumulates over everything the server runs. */
+ * reports finished requests and, for every free tick stream, admits queued
+ * requests in arrival order (the head waits until its workspace fits) and
+ * launches them together as one tick; the queue is shared out over the free
+ * tick streams (a tick takes about queued / free slots requests, at most
+ * rqlp_server_set_tick's limit), so requests run alone while the queue is
+ * short and are grouped when a backlog builds up.  A tick runs the grouped
+ * launches of rqlp_decompose_batched (RQLP_FP64, RQLP_FP32) or the requests' own
+ * sequences (RQLP_BF16_REFINED) on the tick's stream.  Requests admitted
+ * while earlier ticks run overlap with them on the device.  Each result is
+ * bitwise the rqlp_decompose result of the same request.  Single-threaded
+ * use; the context must outlive the server; its info record accumulates
+ * over everything the server runs. */
 typedef struct rqlp_server rqlp_server;
 
 rqlp_status rqlp_server_create(rqlp_server** server, rqlp_ctx* ctx, size_t hbm_budget, int slots,
                                rqlp_precision prec);
 rqlp_status rqlp_server_destroy(rqlp_server* server);
+
+/* Largest number of requests admitted into one tick (1 .. 1024; default
+ * 64).  A tick of one request runs its own launch sequence. */
+rqlp_status rqlp_server_set_tick(rqlp_server* server, int max_requests);
 
 /* Workspace bytes a request takes from the budget (0 when invalid). */
 size_t rqlp_server_request_bytes(const rqlp_problem* request, rqlp_precision prec);
@@ -351,12 +363,13 @@ size_t rqlp_server_request_bytes(const rqlp_problem* request, rqlp_precision pre
  * the whole budget is refused (RQLP_ERR_OUT_OF_MEMORY). */
 rqlp_status rqlp_server_submit(rqlp_server* server, const rqlp_problem* request, void* stream, int64_t* ticket);
 
-/* Report up to max_done finished tickets, then admit and launch queued
- * requests.  done[i] is a ticket; status[i] (status may be NULL) is RQLP_OK
+/* Report finished tickets (whole ticks, at most max_done), then admit and
+ * launch queued requests.  done[i] is a ticket; status[i] (status may be NULL) is RQLP_OK
  * when its outputs are complete on the device, or the error its launch
  * returned (the request then ran partly or not at all, and its outputs are
  * undefined; its workspace was released only after its stream drained).
- * inflight and queued (may be NULL) receive the counts after the call. */
+ * inflight (requests in running ticks) and queued (may be NULL) receive the
+ * counts after the call. */
 rqlp_status rqlp_server_poll(rqlp_server* server, int64_t* done, int32_t* status, int max_done, int* ndone,
                              int* inflight, int* queued);
 

@@ -11,6 +11,7 @@
 // basis).  Their rows of R are zero (with a unit diagonal), so the other
 // columns of Y R^-1 do not involve them.
 #include "common.h"
+#include "grouped.h"
 #include "kernels.h"
 
 namespace rqlp {
@@ -23,27 +24,29 @@ __host__ __device__ inline size_t apply_lds_doubles(int rf) {
   return 2 * (size_t)(kTile * kApXS + 64 * rf * kApYS);
 }
 
+// Workgroup (bx, by): rows bx * 64 RF .. and column blocks 4 by .. 4 by + 3.
 template <typename Tin, typename Tout, int RF>
-__global__ __launch_bounds__(256) void apply_kernel(const Tin* __restrict__ Y, int64_t ldy, int64_t rows,
-                                                    int d, int dp, const int32_t* __restrict__ flags,
-                                                    const int32_t* __restrict__ mode,
-                                                    const double* __restrict__ Xfull,
-                                                    Tout* __restrict__ out1, int64_t ld1, int ncols1,
-                                                    Tout* __restrict__ out2, int64_t ld2, int ncols2,
-                                                    uint64_t seed, uint64_t key1, double inv_sqrt_rows) {
+__device__ __attribute__((always_inline)) inline void apply_body(const Tin* __restrict__ Y, int64_t ldy, int64_t rows,
+                                                                 int d, int dp, const int32_t* __restrict__ flags,
+                                                                 const int32_t* __restrict__ mode,
+                                                                 const double* __restrict__ Xfull,
+                                                                 Tout* __restrict__ out1, int64_t ld1, int ncols1,
+                                                                 Tout* __restrict__ out2, int64_t ld2, int ncols2,
+                                                                 uint64_t seed, uint64_t key1, double inv_sqrt_rows,
+                                                                 int bx, int by) {
   constexpr int kApRows = 64 * RF;  // rows per workgroup (16 RF per wave)
   extern __shared__ double smem[];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane >> 4, lc = lane & 15;
-  const int64_t r0 = (int64_t)blockIdx.x * kApRows;
+  const int64_t r0 = (int64_t)bx * kApRows;
   const int T = dp / kTile;
 
   // out[:, J] = sum_{t <= J} Y[:, t] X[t, J] for column blocks J0..J1-1;
   // per block row t the X tile (16 x 64) and the Y tile (64 x 16, widened
   // to double) are staged in LDS, double buffered, with the next t held in
   // registers meanwhile.
-  const int J0 = 4 * blockIdx.y;
+  const int J0 = 4 * by;
   if (J0 >= T) return;
   const int J1 = min(T, J0 + 4);
   double* Xs = smem;                           // [2][16][kApXS]
@@ -144,6 +147,45 @@ __global__ __launch_bounds__(256) void apply_kernel(const Tin* __restrict__ Y, i
   }
 }
 
+template <typename Tin, typename Tout, int RF>
+__global__ __launch_bounds__(256) void apply_kernel(const Tin* __restrict__ Y, int64_t ldy, int64_t rows, int d, int dp,
+                                                    const int32_t* __restrict__ flags, const int32_t* __restrict__ mode,
+                                                    const double* __restrict__ Xfull, Tout* __restrict__ out1,
+                                                    int64_t ld1, int ncols1, Tout* __restrict__ out2, int64_t ld2,
+                                                    int ncols2, uint64_t seed, uint64_t key1, double inv_sqrt_rows) {
+  apply_body<Tin, Tout, RF>(Y, ldy, rows, d, dp, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2, seed, key1,
+                            inv_sqrt_rows, blockIdx.x, blockIdx.y);
+}
+
+struct ApplyArgs {
+  const void* Y;
+  const int32_t* flags;
+  const int32_t* mode;
+  const double* X;
+  void* out1;
+  void* out2;
+  int64_t ldy, rows, ld1, ld2;
+  uint64_t seed, key1;
+  double isr;
+  int d, dp, ncols1, ncols2, gx;
+};
+
+template <typename Tin, typename Tout, int RF>
+__global__ __launch_bounds__(256) void apply_grouped(const ApplyArgs* __restrict__ a, const int* __restrict__ start,
+                                                     int count) {
+  const int p = group_find(start, count, blockIdx.x);
+  const ApplyArgs g = a[p];
+  const int b = (int)blockIdx.x - start[p];
+  apply_body<Tin, Tout, RF>((const Tin*)g.Y, g.ldy, g.rows, g.d, g.dp, g.flags, g.mode, g.X, (Tout*)g.out1, g.ld1,
+                            g.ncols1, (Tout*)g.out2, g.ld2, g.ncols2, g.seed, g.key1, g.isr, b % g.gx, b / g.gx);
+}
+
+template <typename Tin, typename Tout, int RF>
+void apply_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL((apply_grouped<Tin, Tout, RF>), dim3(blocks), dim3(256), apply_lds_doubles(RF) * sizeof(double),
+                     s, (const ApplyArgs*)args, start, count);
+}
+
 template <typename Tin, typename Tout>
 hipError_t launch_apply(const Tin* Y, int64_t ldy, int64_t rows, int d, int dp, const int32_t* flags,
                         const int32_t* mode, const double* Xfull, Tout* out1, int64_t ld1, int ncols1, Tout* out2,
@@ -158,14 +200,18 @@ hipError_t launch_apply(const Tin* Y, int64_t ldy, int64_t rows, int d, int dp, 
   const int rf = (groups >= 5 && ceil_div(rows, 128) * groups >= 1024) ? 2 : 1;
   const size_t shmem = apply_lds_doubles(rf) * sizeof(double);  // at most 55 KB
   if (ev0) (void)hipEventRecord(ev0, s);
-  if (rf == 2)
-    hipLaunchKernelGGL((apply_kernel<Tin, Tout, 2>), dim3((unsigned)ceil_div(rows, 128), groups), dim3(256), shmem,
-                       s, Y, ldy, rows, d, dp, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2,
-                       seed, key1, isr);
-  else
-    hipLaunchKernelGGL((apply_kernel<Tin, Tout, 1>), dim3((unsigned)ceil_div(rows, 64), groups), dim3(256), shmem,
-                       s, Y, ldy, rows, d, dp, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2,
-                       seed, key1, isr);
+  const unsigned gx = (unsigned)ceil_div(rows, 64 * rf);
+  const ApplyArgs a{Y, flags, mode, Xfull, out1, out2, ldy, rows, ld1, ld2, seed, key1, isr, d, dp, ncols1, ncols2,
+                    (int)gx};
+  if (rf == 2) {
+    if (!record_launch(&apply_grouped_launch<Tin, Tout, 2>, a, gx * groups))
+      hipLaunchKernelGGL((apply_kernel<Tin, Tout, 2>), dim3(gx, groups), dim3(256), shmem, s, Y, ldy, rows, d, dp,
+                         flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2, seed, key1, isr);
+  } else {
+    if (!record_launch(&apply_grouped_launch<Tin, Tout, 1>, a, gx * groups))
+      hipLaunchKernelGGL((apply_kernel<Tin, Tout, 1>), dim3(gx, groups), dim3(256), shmem, s, Y, ldy, rows, d, dp,
+                         flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2, seed, key1, isr);
+  }
   if (ev1) (void)hipEventRecord(ev1, s);
   return hipGetLastError();
 }

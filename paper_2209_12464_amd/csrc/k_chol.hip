@@ -25,6 +25,7 @@
 // this below the output precision; then R = I + F, R^-1 = I - F (to the same
 // order) is written explicitly and the solve becomes a plain product.
 #include "common.h"
+#include "grouped.h"
 #include "kernels.h"
 
 #include <algorithm>
@@ -370,14 +371,35 @@ __global__ __launch_bounds__(NW * 64) void chol_kernel(const double* __restrict_
                        block, blockIdx.x, gridDim.x);
 }
 
-// Many independent matrices (dp <= 256, one register-slot class) in one
-// launch: matrix blockIdx.x / g.per, its workgroup blockIdx.x % g.per.
+// Many independent matrices in one launch (argument table in device
+// memory): workgroups start[p] .. start[p + 1] - 1 belong to matrix p.
+struct CholRecArgs {
+  const double* G;
+  double* R;
+  double* Rinv16;
+  int32_t* flags;
+  DevInfo* info;
+  const double* esq;
+  int32_t* mode;
+  double* Xfull;
+  const double* gdiag0;
+  double tol, fast_tol;
+  int ld, d, dp, pass_id, nesq, block;
+};
+
 template <int NW, int SLOTS>
-__global__ __launch_bounds__(NW * 64) void chol_grouped_kernel(CholGroup g) {
-  const int p = blockIdx.x / g.per;
-  const CholArgs& a = g.a[p];
-  chol_body<NW, SLOTS>(a.G, a.dp, a.d, a.dp, a.R, a.Rinv16, a.flags, (DevInfo*)a.info, a.pass_id, a.tol, a.fast_tol,
-                       a.esq, a.nesq, a.mode, a.Xfull, nullptr, 0, blockIdx.x - p * g.per, g.per);
+__global__ __launch_bounds__(NW * 64) void chol_grouped(const CholRecArgs* __restrict__ a,
+                                                        const int* __restrict__ start, int count) {
+  const int p = group_find(start, count, blockIdx.x);
+  const CholRecArgs g = a[p];
+  chol_body<NW, SLOTS>(g.G, g.ld, g.d, g.dp, g.R, g.Rinv16, g.flags, g.info, g.pass_id, g.tol, g.fast_tol, g.esq,
+                       g.nesq, g.mode, g.Xfull, g.gdiag0, g.block, (int)blockIdx.x - start[p], start[p + 1] - start[p]);
+}
+
+template <int NW, int SLOTS>
+void chol_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL((chol_grouped<NW, SLOTS>), dim3(blocks), dim3(NW * kWave), 0, s, (const CholRecArgs*)args,
+                     start, count);
 }
 
 // ---------------- d > 256: blocked over register-sized diagonal blocks ----------------
@@ -391,31 +413,67 @@ __global__ __launch_bounds__(NW * 64) void chol_grouped_kernel(CholGroup g) {
 
 // Fast path of the second pass (all workgroups), else the original diagonal
 // into gd0 (for the dependence test of later blocks) and *mode = 1.
+__device__ __attribute__((always_inline)) inline void chol_prep_body(const double* __restrict__ G, int d, int dp,
+                                                                     double* __restrict__ R,
+                                                                     double* __restrict__ Rinv16,
+                                                                     int32_t* __restrict__ flags, double fast_tol,
+                                                                     const double* __restrict__ esq, int nesq,
+                                                                     int32_t* __restrict__ mode,
+                                                                     double* __restrict__ Xfull,
+                                                                     double* __restrict__ gd0, int bid, int nblk) {
+  __shared__ double red[16];
+  if (fast_tol > 0.0 && chol_fast_path(G, d, dp, R, Rinv16, flags, fast_tol, esq, nesq, mode, Xfull, red, 16, bid, nblk))
+    return;
+  if (bid != 0) return;
+  for (int i = threadIdx.x; i < dp; i += blockDim.x) gd0[i] = (i < d) ? G[(int64_t)i * dp + i] : 1.0;
+  if (threadIdx.x == 0) *mode = 1;
+}
+
 __global__ __launch_bounds__(1024) void chol_prep_kernel(const double* __restrict__ G, int d, int dp,
                                                       double* __restrict__ R, double* __restrict__ Rinv16,
                                                       int32_t* __restrict__ flags, double fast_tol,
                                                       const double* __restrict__ esq, int nesq,
                                                       int32_t* __restrict__ mode, double* __restrict__ Xfull,
                                                       double* __restrict__ gd0) {
-  __shared__ double red[16];
-  if (fast_tol > 0.0 &&
-      chol_fast_path(G, d, dp, R, Rinv16, flags, fast_tol, esq, nesq, mode, Xfull, red, 16, blockIdx.x, gridDim.x))
-    return;
-  if (blockIdx.x != 0) return;
-  for (int i = threadIdx.x; i < dp; i += blockDim.x) gd0[i] = (i < d) ? G[(int64_t)i * dp + i] : 1.0;
-  if (threadIdx.x == 0) *mode = 1;
+  chol_prep_body(G, d, dp, R, Rinv16, flags, fast_tol, esq, nesq, mode, Xfull, gd0, blockIdx.x, gridDim.x);
+}
+
+struct CholPrepArgs {
+  const double* G;
+  double* R;
+  double* Rinv16;
+  int32_t* flags;
+  const double* esq;
+  int32_t* mode;
+  double* Xfull;
+  double* gd0;
+  double fast_tol;
+  int d, dp, nesq;
+};
+
+__global__ __launch_bounds__(1024) void chol_prep_grouped(const CholPrepArgs* __restrict__ a,
+                                                       const int* __restrict__ start, int count) {
+  const int p = group_find(start, count, blockIdx.x);
+  const CholPrepArgs g = a[p];
+  chol_prep_body(g.G, g.d, g.dp, g.R, g.Rinv16, g.flags, g.fast_tol, g.esq, g.nesq, g.mode, g.Xfull, g.gd0,
+                 (int)blockIdx.x - start[p], start[p + 1] - start[p]);
+}
+
+void chol_prep_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL(chol_prep_grouped, dim3(blocks), dim3(1024), 0, s, (const CholPrepArgs*)args, start, count);
 }
 
 // R[b, r] = X_bb^T G[b, r] (one wave per 16 x 16 output tile, float64 MFMA)
 // and R[r, b] = 0; X_bb is upper triangular, so tile row I needs only the
 // first 16 (I + 1) rows of X_bb and G.
-__global__ __launch_bounds__(64) void chol_panel_kernel(const double* __restrict__ G, int ld, int off, int db,
-                                                     int rest, const double* __restrict__ X,
-                                                     double* __restrict__ R, const int32_t* __restrict__ flags,
-                                                     const int32_t* __restrict__ mode) {
+__device__ __attribute__((always_inline)) inline void chol_panel_body(const double* __restrict__ G, int ld, int off,
+                                                                      int db, int rest, const double* __restrict__ X,
+                                                                      double* __restrict__ R,
+                                                                      const int32_t* __restrict__ flags,
+                                                                      const int32_t* __restrict__ mode, int bid) {
   if (*mode == 2) return;
   const int nI = db / kTile;
-  const int I = blockIdx.x % nI, J = blockIdx.x / nI;
+  const int I = bid % nI, J = bid / nI;
   const int lane = threadIdx.x, lr = lane >> 4, lc = lane & 15;
   const double* Xb = X + (int64_t)off * ld + off;
   const double* Gb = G + (int64_t)off * ld + off + db;
@@ -440,14 +498,41 @@ __global__ __launch_bounds__(64) void chol_panel_kernel(const double* __restrict
   }
 }
 
+__global__ __launch_bounds__(64) void chol_panel_kernel(const double* __restrict__ G, int ld, int off, int db,
+                                                     int rest, const double* __restrict__ X,
+                                                     double* __restrict__ R, const int32_t* __restrict__ flags,
+                                                     const int32_t* __restrict__ mode) {
+  chol_panel_body(G, ld, off, db, rest, X, R, flags, mode, blockIdx.x);
+}
+
+struct CholPanelArgs {
+  const double* G;
+  const double* X;
+  double* R;
+  const int32_t* flags;
+  const int32_t* mode;
+  int ld, off, db, rest;
+};
+
+__global__ __launch_bounds__(64) void chol_panel_grouped(const CholPanelArgs* __restrict__ a,
+                                                      const int* __restrict__ start, int count) {
+  const int p = group_find(start, count, blockIdx.x);
+  const CholPanelArgs g = a[p];
+  chol_panel_body(g.G, g.ld, g.off, g.db, g.rest, g.X, g.R, g.flags, g.mode, (int)blockIdx.x - start[p]);
+}
+
+void chol_panel_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL(chol_panel_grouped, dim3(blocks), dim3(64), 0, s, (const CholPanelArgs*)args, start, count);
+}
+
 // G[r, r] -= R[b, r]^T R[b, r] (one wave per 16 x 16 tile of the square
 // trailing block, K = db)
-__global__ __launch_bounds__(64) void chol_syrk_kernel(double* __restrict__ G, int ld, int off, int db, int rest,
-                                                    const double* __restrict__ R,
-                                                    const int32_t* __restrict__ mode) {
+__device__ __attribute__((always_inline)) inline void chol_syrk_body(double* __restrict__ G, int ld, int off, int db,
+                                                                     int rest, const double* __restrict__ R,
+                                                                     const int32_t* __restrict__ mode, int bid) {
   if (*mode == 2) return;
   const int nI = rest / kTile;
-  const int I = blockIdx.x % nI, J = blockIdx.x / nI;
+  const int I = bid % nI, J = bid / nI;
   const int lane = threadIdx.x, lr = lane >> 4, lc = lane & 15;
   const double* Rb = R + (int64_t)off * ld + off + db;
   doublex4 acc[4];
@@ -467,6 +552,29 @@ __global__ __launch_bounds__(64) void chol_syrk_kernel(double* __restrict__ G, i
     Gt[(int64_t)(lr + 4 * r) * ld + lc] -= ((acc[0][r] + acc[1][r]) + acc[2][r]) + acc[3][r];
 }
 
+__global__ __launch_bounds__(64) void chol_syrk_kernel(double* __restrict__ G, int ld, int off, int db, int rest,
+                                                    const double* __restrict__ R, const int32_t* __restrict__ mode) {
+  chol_syrk_body(G, ld, off, db, rest, R, mode, blockIdx.x);
+}
+
+struct CholSyrkArgs {
+  double* G;
+  const double* R;
+  const int32_t* mode;
+  int ld, off, db, rest;
+};
+
+__global__ __launch_bounds__(64) void chol_syrk_grouped(const CholSyrkArgs* __restrict__ a,
+                                                     const int* __restrict__ start, int count) {
+  const int p = group_find(start, count, blockIdx.x);
+  const CholSyrkArgs g = a[p];
+  chol_syrk_body(g.G, g.ld, g.off, g.db, g.rest, g.R, g.mode, (int)blockIdx.x - start[p]);
+}
+
+void chol_syrk_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL(chol_syrk_grouped, dim3(blocks), dim3(64), 0, s, (const CholSyrkArgs*)args, start, count);
+}
+
 // register slots per wave for the t (t + 1) / 2 lower tiles of a block of t
 // tile columns (8 waves; slots chosen so that tiles and the diagonal-block
 // code fit in registers)
@@ -477,9 +585,14 @@ static hipError_t launch_chol_reg(const double* G, int ld, int d, int db, double
   const int T = db / kTile;
   const int tiles = T * (T + 1) / 2;
   const unsigned grid = (!block && fast_tol > 0.0) ? 16 : 1;  // extra workgroups only help the fast path
-#define RQLP_CHOL_LAUNCH(S)                                                                                   \
-  hipLaunchKernelGGL((chol_kernel<8, S>), dim3(grid), dim3(8 * kWave), 0, s, G, ld, d, db, R, Rinv16, flags, \
-                     (DevInfo*)info, pass_id, tol, fast_tol, esq, nesq, mode, Xfull, gdiag0, block)
+  const CholRecArgs a{G, R, Rinv16, flags, (DevInfo*)info, esq, mode, Xfull, gdiag0, tol, fast_tol, ld, d, db, pass_id,
+                      nesq, block};
+#define RQLP_CHOL_LAUNCH(S)                                                                                        \
+  do {                                                                                                             \
+    if (!record_launch(&chol_grouped_launch<8, S>, a, grid))                                                       \
+      hipLaunchKernelGGL((chol_kernel<8, S>), dim3(grid), dim3(8 * kWave), 0, s, G, ld, d, db, R, Rinv16, flags,    \
+                         (DevInfo*)info, pass_id, tol, fast_tol, esq, nesq, mode, Xfull, gdiag0, block);             \
+  } while (0)
   if (tiles <= 8 * 7) RQLP_CHOL_LAUNCH(7);
   else if (tiles <= 8 * 14) RQLP_CHOL_LAUNCH(14);
   else RQLP_CHOL_LAUNCH(17);
@@ -497,8 +610,11 @@ hipError_t launch_chol(double* G, int d, int dp, double* R, double* Rinv16, int3
     e = launch_chol_reg(G, dp, d, dp, R, Rinv16, flags, info, pass_id, tol, fast_tol, esq, nesq, mode, Xfull,
                         nullptr, 0, s);
   } else {
-    hipLaunchKernelGGL(chol_prep_kernel, dim3(fast_tol > 0.0 ? 16 : 1), dim3(1024), 0, s, G, d, dp, R, Rinv16,
-                       flags, fast_tol, esq, nesq, mode, Xfull, gd0);
+    const unsigned pg = fast_tol > 0.0 ? 16 : 1;
+    if (!record_launch(&chol_prep_grouped_launch,
+                       CholPrepArgs{G, R, Rinv16, flags, esq, mode, Xfull, gd0, fast_tol, d, dp, nesq}, pg))
+      hipLaunchKernelGGL(chol_prep_kernel, dim3(pg), dim3(1024), 0, s, G, d, dp, R, Rinv16, flags, fast_tol, esq, nesq,
+                         mode, Xfull, gd0);
     const int T = dp / kTile;
     const int nb = (int)ceil_div(T, kCholRegMax / kTile);
     int t0 = 0;
@@ -514,10 +630,12 @@ hipError_t launch_chol(double* G, int d, int dp, double* R, double* Rinv16, int3
         e = launch_trinv_block(R + (int64_t)off * dp + off, Rinv16 + (int64_t)t0 * kTile * kTile, dp, tbs, mode,
                                Xfull + (int64_t)off * dp + off, s);
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL(chol_panel_kernel, dim3((unsigned)(tbs * (rest / kTile))), dim3(kWave), 0, s, G, dp, off,
-                           db, rest, Xfull, R, flags, mode);
-        hipLaunchKernelGGL(chol_syrk_kernel, dim3((unsigned)((rest / kTile) * (rest / kTile))), dim3(kWave), 0, s,
-                           G, dp, off, db, rest, R, mode);
+        const unsigned npb = (unsigned)(tbs * (rest / kTile)), nsb = (unsigned)((rest / kTile) * (rest / kTile));
+        if (!record_launch(&chol_panel_grouped_launch, CholPanelArgs{G, Xfull, R, flags, mode, dp, off, db, rest}, npb))
+          hipLaunchKernelGGL(chol_panel_kernel, dim3(npb), dim3(kWave), 0, s, G, dp, off, db, rest, Xfull, R, flags,
+                             mode);
+        if (!record_launch(&chol_syrk_grouped_launch, CholSyrkArgs{G, R, mode, dp, off, db, rest}, nsb))
+          hipLaunchKernelGGL(chol_syrk_kernel, dim3(nsb), dim3(kWave), 0, s, G, dp, off, db, rest, R, mode);
         e = hipGetLastError();
       }
       t0 += tbs;
@@ -532,31 +650,6 @@ int chol_slot_class(int dp) {
   const int T = dp / kTile;
   const int tiles = T * (T + 1) / 2;
   return tiles <= 8 * 7 ? 7 : (tiles <= 8 * 14 ? 14 : 17);
-}
-
-hipError_t launch_chol_grouped(const CholArgs* args, int count, hipStream_t s) {
-  for (const int cls : {7, 14, 17})
-  for (const int per : {1, 16}) {  // extra workgroups per matrix only help the fast path
-    CholGroup g;
-    g.count = 0;
-    g.per = per;
-    auto flush = [&]() {
-      if (g.count == 0) return;
-      const dim3 grid((unsigned)(g.count * g.per));
-      if (cls == 7) hipLaunchKernelGGL((chol_grouped_kernel<8, 7>), grid, dim3(8 * kWave), 0, s, g);
-      else if (cls == 14) hipLaunchKernelGGL((chol_grouped_kernel<8, 14>), grid, dim3(8 * kWave), 0, s, g);
-      else hipLaunchKernelGGL((chol_grouped_kernel<8, 17>), grid, dim3(8 * kWave), 0, s, g);
-      g.count = 0;
-    };
-    for (int i = 0; i < count; ++i) {
-      if (args[i].dp > kCholRegMax) return hipErrorInvalidValue;
-      if (chol_slot_class(args[i].dp) != cls || (args[i].fast_tol > 0.0 ? 16 : 1) != per) continue;
-      g.a[g.count++] = args[i];
-      if (g.count == kCholGroup) flush();
-    }
-    flush();
-  }
-  return hipGetLastError();
 }
 
 }  // namespace rqlp

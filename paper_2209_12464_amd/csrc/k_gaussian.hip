@@ -3,18 +3,24 @@
 // (seed, key1); columns [cols, ldo) are zeroed.  One thread per Philox block
 // (four consecutive logical indices).
 #include "common.h"
+#include "grouped.h"
 #include "kernels.h"
 
 namespace rqlp {
 
+struct GaussianArgs {
+  uint64_t seed, key1;
+  int64_t rows, cols, ldo;
+  void* out;
+};
+
 template <typename T>
-__global__ __launch_bounds__(256) void gaussian_kernel(uint64_t seed, uint64_t key1, int64_t rows,
-                                                       int64_t cols, T* __restrict__ out,
-                                                       int64_t ldo) {
+__device__ __attribute__((always_inline)) inline void gaussian_body(uint64_t seed, uint64_t key1, int64_t rows,
+                                                                    int64_t cols, T* __restrict__ out, int64_t ldo,
+                                                                    int bid, int nblk_grid) {
   const int64_t total = rows * cols;
   const int64_t nblk = (total + 3) >> 2;
-  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nblk;
-       c += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t c = bid * (int64_t)blockDim.x + threadIdx.x; c < nblk; c += (int64_t)nblk_grid * blockDim.x) {
     u64x4 ctr = {(uint64_t)c, 0, 0, 0};
     const u64x4 w = philox4x64_10(ctr, seed, key1);
     double z[4];
@@ -32,15 +38,65 @@ __global__ __launch_bounds__(256) void gaussian_kernel(uint64_t seed, uint64_t k
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void zero_cols_kernel(T* __restrict__ out, int64_t rows,
-                                                        int64_t c0, int64_t c1, int64_t ld) {
+__global__ __launch_bounds__(256) void gaussian_kernel(uint64_t seed, uint64_t key1, int64_t rows, int64_t cols,
+                                                       T* __restrict__ out, int64_t ldo) {
+  gaussian_body<T>(seed, key1, rows, cols, out, ldo, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gaussian_grouped(const GaussianArgs* __restrict__ a,
+                                                        const int* __restrict__ start, int count) {
+  const int p = group_find(start, count, blockIdx.x);
+  const GaussianArgs g = a[p];
+  gaussian_body<T>(g.seed, g.key1, g.rows, g.cols, (T*)g.out, g.ldo, blockIdx.x - start[p], start[p + 1] - start[p]);
+}
+
+template <typename T>
+void gaussian_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL(gaussian_grouped<T>, dim3(blocks), dim3(256), 0, s, (const GaussianArgs*)args, start, count);
+}
+
+struct ZeroColsArgs {
+  int64_t rows, c0, c1, ld;
+  void* out;
+};
+
+template <typename T>
+__device__ __attribute__((always_inline)) inline void zero_cols_body(T* __restrict__ out, int64_t rows, int64_t c0,
+                                                                     int64_t c1, int64_t ld, int bid, int nblk) {
   const int64_t w = c1 - c0;
   const int64_t total = rows * w;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = bid * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)nblk * blockDim.x) {
     const int64_t i = e / w, j = c0 + (e - i * w);
     out[i * ld + j] = (T)0;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void zero_cols_kernel(T* __restrict__ out, int64_t rows, int64_t c0, int64_t c1,
+                                                        int64_t ld) {
+  zero_cols_body<T>(out, rows, c0, c1, ld, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void zero_cols_grouped(const ZeroColsArgs* __restrict__ a,
+                                                         const int* __restrict__ start, int count) {
+  const int p = group_find(start, count, blockIdx.x);
+  const ZeroColsArgs g = a[p];
+  zero_cols_body<T>((T*)g.out, g.rows, g.c0, g.c1, g.ld, blockIdx.x - start[p], start[p + 1] - start[p]);
+}
+
+template <typename T>
+void zero_cols_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL(zero_cols_grouped<T>, dim3(blocks), dim3(256), 0, s, (const ZeroColsArgs*)args, start, count);
+}
+
+template <typename T>
+static void zero_cols_dispatch(T* out, int64_t rows, int64_t c0, int64_t c1, int64_t ld, hipStream_t s) {
+  const int64_t g = ceil_div(rows * (c1 - c0), 256);
+  const unsigned blocks = (unsigned)(g < 65536 ? g : 65536);
+  if (!record_launch(&zero_cols_grouped_launch<T>, ZeroColsArgs{rows, c0, c1, ld, out}, blocks))
+    hipLaunchKernelGGL(zero_cols_kernel<T>, dim3(blocks), dim3(256), 0, s, out, rows, c0, c1, ld);
 }
 
 template <typename T>
@@ -49,15 +105,11 @@ hipError_t launch_gaussian(uint64_t seed, uint64_t key1, int64_t rows, int64_t c
   const int64_t nblk = (rows * cols + 3) / 4;
   if (nblk > 0) {
     const int64_t g = ceil_div(nblk, 256);
-    hipLaunchKernelGGL(gaussian_kernel<T>, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s,
-                       seed, key1, rows, cols, out, ldo);
+    const unsigned blocks = (unsigned)(g < 65536 ? g : 65536);
+    if (!record_launch(&gaussian_grouped_launch<T>, GaussianArgs{seed, key1, rows, cols, ldo, out}, blocks))
+      hipLaunchKernelGGL(gaussian_kernel<T>, dim3(blocks), dim3(256), 0, s, seed, key1, rows, cols, out, ldo);
   }
-  if (ldo > cols && rows > 0) {
-    const int64_t tot = rows * (ldo - cols);
-    const int64_t g = ceil_div(tot, 256);
-    hipLaunchKernelGGL(zero_cols_kernel<T>, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s,
-                       out, rows, cols, ldo, ldo);
-  }
+  if (ldo > cols && rows > 0) zero_cols_dispatch<T>(out, rows, cols, ldo, ldo, s);
   return hipGetLastError();
 }
 
@@ -67,9 +119,7 @@ template hipError_t launch_gaussian<double>(uint64_t, uint64_t, int64_t, int64_t
 template <typename T>
 hipError_t launch_zero_cols(T* out, int64_t rows, int64_t c0, int64_t c1, int64_t ld, hipStream_t s) {
   if (c1 <= c0 || rows <= 0) return hipSuccess;
-  const int64_t g = ceil_div(rows * (c1 - c0), 256);
-  hipLaunchKernelGGL(zero_cols_kernel<T>, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s,
-                     out, rows, c0, c1, ld);
+  zero_cols_dispatch<T>(out, rows, c0, c1, ld, s);
   return hipGetLastError();
 }
 template hipError_t launch_zero_cols<float>(float*, int64_t, int64_t, int64_t, int64_t, hipStream_t);

@@ -15,6 +15,7 @@
 // and X tiles are staged through LDS, double buffered with register
 // prefetch, one barrier per K step.
 #include "common.h"
+#include "grouped.h"
 #include "kernels.h"
 
 #include <algorithm>
@@ -24,11 +25,12 @@ namespace rqlp {
 constexpr int kGemmThreads = 512;
 constexpr int kBK = 16;
 
+// One workgroup's share: tile `logical` = split * mtiles + slab.
 template <typename T, int NBW, bool TRANS, bool AVEC, bool BVEC>
-__global__ __launch_bounds__(kGemmThreads) void gemm_kernel(
+__device__ __attribute__((always_inline)) inline void gemm_body(
     const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
     T* __restrict__ C, int64_t ldc, int64_t cslice, int M, int N, int K, int kchunk, int mtiles,
-    int nst) {
+    int nst, int logical) {
   typedef Mfma<T> MF;
   constexpr int BM = 128;                  // 4 row groups x 32 rows
   constexpr int BN = 32 * NBW;             // 2 column halves x NBW blocks of 16
@@ -49,7 +51,6 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave & 3, wn = wave >> 2;
-  const int logical = xcd_remap(blockIdx.x, gridDim.x);
   const int split = logical / mtiles;
   const int mt = logical - split * mtiles;
   const int m0 = mt * BM;
@@ -280,14 +281,46 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(
     }
 }
 
+template <typename T, int NBW, bool TRANS, bool AVEC, bool BVEC>
+__global__ __launch_bounds__(kGemmThreads) void gemm_kernel(
+    const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
+    T* __restrict__ C, int64_t ldc, int64_t cslice, int M, int N, int K, int kchunk, int mtiles,
+    int nst) {
+  gemm_body<T, NBW, TRANS, AVEC, BVEC>(A, lda, B, ldb, C, ldc, cslice, M, N, K, kchunk, mtiles, nst,
+                                       xcd_remap(blockIdx.x, gridDim.x));
+}
+
+struct GemmRecArgs {
+  const void* A;
+  const void* B;
+  void* C;
+  int64_t lda, ldb, ldc, cslice;
+  int M, N, K, kchunk, mtiles, nst;
+};
+
+template <typename T, int NBW, bool TRANS, bool AVEC, bool BVEC>
+__global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmRecArgs* __restrict__ a,
+                                                             const int* __restrict__ start, int count) {
+  const int p = group_find(start, count, blockIdx.x);
+  const GemmRecArgs g = a[p];
+  gemm_body<T, NBW, TRANS, AVEC, BVEC>((const T*)g.A, g.lda, (const T*)g.B, g.ldb, (T*)g.C, g.ldc, g.cslice, g.M,
+                                       g.N, g.K, g.kchunk, g.mtiles, g.nst, (int)blockIdx.x - start[p]);
+}
+
+template <typename T, int NBW, bool TRANS, bool AVEC, bool BVEC>
+void gemm_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_grouped<T, NBW, TRANS, AVEC, BVEC>), dim3(blocks), dim3(kGemmThreads), 0, s,
+                     (const GemmRecArgs*)args, start, count);
+}
+
 // Y[i][j] = sum_s P[s][i][j] in order s = 0..nsplit-1 (i < M, j < nst).
 template <typename T>
-__global__ __launch_bounds__(256) void splitk_reduce_kernel(const T* __restrict__ P, int64_t ldp,
-                                                            int64_t pslice, int nsplit, T* __restrict__ Y,
-                                                            int64_t ldy, int M, int nst) {
+__device__ __attribute__((always_inline)) inline void splitk_reduce_body(const T* __restrict__ P, int64_t ldp,
+                                                                         int64_t pslice, int nsplit,
+                                                                         T* __restrict__ Y, int64_t ldy, int M,
+                                                                         int nst, int bid, int nblk) {
   const int64_t total = (int64_t)M * nst;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = bid * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)nblk * blockDim.x) {
     const int64_t i = e / nst, j = e - i * nst;
     T s = P[i * ldp + j];
     for (int t = 1; t < nsplit; ++t) s += P[t * pslice + i * ldp + j];
@@ -295,15 +328,22 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const T* __restrict_
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const T* __restrict__ P, int64_t ldp, int64_t pslice,
+                                                            int nsplit, T* __restrict__ Y, int64_t ldy, int M,
+                                                            int nst) {
+  splitk_reduce_body<T>(P, ldp, pslice, nsplit, Y, ldy, M, nst, blockIdx.x, gridDim.x);
+}
+
 // The same sum, four consecutive outputs per thread with 16-byte accesses
 // (float; rows of P and Y 16-byte aligned, nst a multiple of 4).  The
 // additions run in the same order, so the results are the same bits.
-__global__ __launch_bounds__(256) void splitk_reduce4_kernel(const float* __restrict__ P, int64_t ldp,
-                                                             int64_t pslice, int nsplit, float* __restrict__ Y,
-                                                             int64_t ldy, int M, int nst) {
+__device__ __attribute__((always_inline)) inline void splitk_reduce4_body(const float* __restrict__ P, int64_t ldp,
+                                                                          int64_t pslice, int nsplit,
+                                                                          float* __restrict__ Y, int64_t ldy, int M,
+                                                                          int nst, int bid, int nblk) {
   const int64_t total = (int64_t)M * (nst / 4);
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = bid * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)nblk * blockDim.x) {
     const int64_t i = e / (nst / 4), j = (e - i * (nst / 4)) * 4;
     floatx4 s = *reinterpret_cast<const floatx4*>(P + i * ldp + j);
     for (int t = 1; t < nsplit; ++t) {
@@ -315,12 +355,69 @@ __global__ __launch_bounds__(256) void splitk_reduce4_kernel(const float* __rest
   }
 }
 
+__global__ __launch_bounds__(256) void splitk_reduce4_kernel(const float* __restrict__ P, int64_t ldp,
+                                                             int64_t pslice, int nsplit, float* __restrict__ Y,
+                                                             int64_t ldy, int M, int nst) {
+  splitk_reduce4_body(P, ldp, pslice, nsplit, Y, ldy, M, nst, blockIdx.x, gridDim.x);
+}
+
+struct SplitkArgs {
+  const void* P;
+  void* Y;
+  int64_t ldp, pslice, ldy;
+  int nsplit, M, nst;
+};
+
+template <typename T, bool V4>
+__global__ __launch_bounds__(256) void splitk_grouped(const SplitkArgs* __restrict__ a, const int* __restrict__ start,
+                                                      int count) {
+  const int p = group_find(start, count, blockIdx.x);
+  const SplitkArgs g = a[p];
+  const int bid = (int)blockIdx.x - start[p], nb = start[p + 1] - start[p];
+  if constexpr (V4)
+    splitk_reduce4_body((const float*)g.P, g.ldp, g.pslice, g.nsplit, (float*)g.Y, g.ldy, g.M, g.nst, bid, nb);
+  else
+    splitk_reduce_body<T>((const T*)g.P, g.ldp, g.pslice, g.nsplit, (T*)g.Y, g.ldy, g.M, g.nst, bid, nb);
+}
+
+template <typename T, bool V4>
+void splitk_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL((splitk_grouped<T, V4>), dim3(blocks), dim3(256), 0, s, (const SplitkArgs*)args, start, count);
+}
+
+// The ordered reduction of nsplit slabs (4-wide when the layout allows).
+template <typename T>
+static void splitk_dispatch(const T* P, int nsplit, int M, int nst, T* Y, int64_t ldy, hipStream_t s) {
+  const bool vec4 = sizeof(T) == 4 && nst % 4 == 0 && ldy % 4 == 0 && ((uintptr_t)Y & 15) == 0 &&
+                    ((uintptr_t)P & 15) == 0;
+  const int64_t total = (int64_t)M * (vec4 ? nst / 4 : nst);
+  const int64_t gr = ceil_div(total, 256);
+  // every output is summed by one thread in a fixed order, so the block
+  // count only sets how many outputs a thread takes in turn
+  const unsigned blocks = (unsigned)(gr < 2048 ? gr : 2048);
+  const SplitkArgs a{P, Y, (int64_t)nst, (int64_t)M * nst, ldy, nsplit, M, nst};
+  if (vec4) {
+    if (!record_launch(&splitk_grouped_launch<float, true>, a, blocks))
+      hipLaunchKernelGGL(splitk_reduce4_kernel, dim3(blocks), dim3(256), 0, s, (const float*)P, (int64_t)nst,
+                         (int64_t)M * nst, nsplit, (float*)Y, ldy, M, nst);
+  } else {
+    if (!record_launch(&splitk_grouped_launch<T, false>, a, blocks))
+      hipLaunchKernelGGL(splitk_reduce_kernel<T>, dim3(blocks), dim3(256), 0, s, P, (int64_t)nst, (int64_t)M * nst,
+                         nsplit, Y, ldy, M, nst);
+  }
+}
+
 template <typename T, int NBW, bool TRANS>
 static void launch_nb(const GemmArgs<T>& g, hipStream_t s, int grid, T* C, int64_t ldc,
                       int64_t cslice, int nst) {
-#define RQLP_GEMM_LAUNCH(AV, BV)                                                                       \
-  hipLaunchKernelGGL((gemm_kernel<T, NBW, TRANS, AV, BV>), dim3(grid), dim3(kGemmThreads), 0, s, g.A, g.lda, \
-                     g.B, g.ldb, C, ldc, cslice, g.M, g.N, g.K, g.kchunk, g.mtiles, nst)
+#define RQLP_GEMM_LAUNCH(AV, BV)                                                                                 \
+  do {                                                                                                             \
+    if (!record_launch(&gemm_grouped_launch<T, NBW, TRANS, AV, BV>,                                                \
+                       GemmRecArgs{g.A, g.B, C, g.lda, g.ldb, ldc, cslice, g.M, g.N, g.K, g.kchunk, g.mtiles, nst}, \
+                       (unsigned)grid))                                                                            \
+      hipLaunchKernelGGL((gemm_kernel<T, NBW, TRANS, AV, BV>), dim3(grid), dim3(kGemmThreads), 0, s, g.A, g.lda,    \
+                         g.B, g.ldb, C, ldc, cslice, g.M, g.N, g.K, g.kchunk, g.mtiles, nst);                      \
+  } while (0)
   if (g.avec && g.bvec) RQLP_GEMM_LAUNCH(true, true);
   else if (g.avec) RQLP_GEMM_LAUNCH(true, false);
   else if (g.bvec) RQLP_GEMM_LAUNCH(false, true);
@@ -384,33 +481,14 @@ hipError_t launch_gemm(GemmArgs<T> g, T* Y, int64_t ldy, int nst, T* P, hipStrea
       else dispatch_nb<T, false>(gc, s, grid, P + c0, ldp, pslice, nst_c);
     }
   }
-  if (g.nsplit > 1) {
-    const bool vec4 = sizeof(T) == 4 && nst % 4 == 0 && ldy % 4 == 0 && ((uintptr_t)Y & 15) == 0 &&
-                      ((uintptr_t)P & 15) == 0;
-    const int64_t total = (int64_t)g.M * (vec4 ? nst / 4 : nst);
-    const int64_t gr = ceil_div(total, 256);
-    if (vec4)
-      hipLaunchKernelGGL(splitk_reduce4_kernel, dim3((unsigned)(gr < 8192 ? gr : 8192)), dim3(256), 0, s,
-                         (const float*)P, (int64_t)nst, (int64_t)g.M * nst, g.nsplit, (float*)Y, ldy, g.M, nst);
-    else
-      hipLaunchKernelGGL(splitk_reduce_kernel<T>, dim3((unsigned)(gr < 8192 ? gr : 8192)), dim3(256), 0,
-                         s, P, (int64_t)nst, (int64_t)g.M * nst, g.nsplit, Y, ldy, g.M, nst);
-  }
+  if (g.nsplit > 1) splitk_dispatch<T>(P, g.nsplit, g.M, nst, Y, ldy, s);
   // the timed interval covers the product and its split-K reduction
   if (ev1) (void)hipEventRecord(ev1, s);
   return hipGetLastError();
 }
 hipError_t launch_splitk_reduce_f32(const float* P, int nsplit, int M, int nst, float* Y, int64_t ldy,
                                     hipStream_t s) {
-  const bool vec4 = nst % 4 == 0 && ldy % 4 == 0 && ((uintptr_t)Y & 15) == 0 && ((uintptr_t)P & 15) == 0;
-  const int64_t total = (int64_t)M * (vec4 ? nst / 4 : nst);
-  const int64_t gr = ceil_div(total, 256);
-  if (vec4)
-    hipLaunchKernelGGL(splitk_reduce4_kernel, dim3((unsigned)(gr < 8192 ? gr : 8192)), dim3(256), 0, s, P,
-                       (int64_t)nst, (int64_t)M * nst, nsplit, Y, ldy, M, nst);
-  else
-    hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3((unsigned)(gr < 8192 ? gr : 8192)), dim3(256), 0, s, P,
-                       (int64_t)nst, (int64_t)M * nst, nsplit, Y, ldy, M, nst);
+  splitk_dispatch<float>(P, nsplit, M, nst, Y, ldy, s);
   return hipGetLastError();
 }
 

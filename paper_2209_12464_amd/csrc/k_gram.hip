@@ -6,7 +6,10 @@
 // adds the chunk partials in a fixed order (deterministic) and mirrors the
 // result into the lower triangle.
 #include "common.h"
+#include "grouped.h"
 #include "kernels.h"
+
+#include <algorithm>
 
 namespace rqlp {
 
@@ -24,16 +27,16 @@ __device__ inline void tile_pair(int p, int& I, int& J) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__ Y, int64_t ldy,
-                                                           int64_t rows, int d, int dp,
-                                                           int64_t chunk_rows, int npairs,
-                                                           double* __restrict__ P) {
+__device__ __attribute__((always_inline)) inline void gram_partial_body(const T* __restrict__ Y, int64_t ldy,
+                                                                        int64_t rows, int d, int dp,
+                                                                        int64_t chunk_rows, int npairs,
+                                                                        double* __restrict__ P, int bid) {
   __shared__ double YI[2][kGK][kGT + 1];
   __shared__ double YJ[2][kGK][kGT + 1];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int pair = blockIdx.x % npairs;
-  const int chunk = blockIdx.x / npairs;
+  const int pair = bid % npairs;
+  const int chunk = bid / npairs;
   int I, J;
   tile_pair(pair, I, J);
   const int64_t r0 = (int64_t)chunk * chunk_rows;
@@ -106,19 +109,48 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
       }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__ Y, int64_t ldy, int64_t rows, int d,
+                                                           int dp, int64_t chunk_rows, int npairs,
+                                                           double* __restrict__ P) {
+  gram_partial_body<T>(Y, ldy, rows, d, dp, chunk_rows, npairs, P, blockIdx.x);
+}
+
+struct GramPartialArgs {
+  const void* Y;
+  double* P;
+  int64_t ldy, rows, chunk_rows;
+  int d, dp, npairs;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void gram_partial_grouped(const GramPartialArgs* __restrict__ a,
+                                                            const int* __restrict__ start, int count) {
+  const int p = group_find(start, count, blockIdx.x);
+  const GramPartialArgs g = a[p];
+  gram_partial_body<T>((const T*)g.Y, g.ldy, g.rows, g.d, g.dp, g.chunk_rows, g.npairs, g.P,
+                       (int)blockIdx.x - start[p]);
+}
+
+template <typename T>
+void gram_partial_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL(gram_partial_grouped<T>, dim3(blocks), dim3(256), 0, s, (const GramPartialArgs*)args, start,
+                     count);
+}
+
 // G[i][j] = G[j][i] = sum over chunks of P[c][i][j] for i <= j (fixed order).
 // Each block also writes esq[block] = its share of ||G - I||_F^2 over the
 // d x d part (fixed-order reduction; NaN propagates), which the Cholesky
 // sums in a fixed order to decide on its fast path.
-__global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ P, int nchunks,
-                                                          int d, int dp, double* __restrict__ G,
-                                                          double* __restrict__ esq, DevInfo* info) {
+__device__ __attribute__((always_inline)) inline void gram_reduce_body(const double* __restrict__ P, int nchunks,
+                                                                       int d, int dp, double* __restrict__ G,
+                                                                       double* __restrict__ esq, DevInfo* info,
+                                                                       int bid, int nblk) {
   __shared__ double red[4];
   const int64_t total = (int64_t)dp * dp;
   bool bad = false;
   double e2 = 0.0;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = bid * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)nblk * blockDim.x) {
     const int i = (int)(e / dp), j = (int)(e % dp);
     if (i > j) continue;
     // (i, j) lies in tile (i/64, j/64) with i/64 <= j/64: written by every chunk
@@ -145,7 +177,32 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restri
   for (int off = 32; off > 0; off >>= 1) e2 += __shfl_xor(e2, off);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e2;
   __syncthreads();
-  if (threadIdx.x == 0) esq[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  if (threadIdx.x == 0) esq[bid] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ P, int nchunks, int d, int dp,
+                                                          double* __restrict__ G, double* __restrict__ esq,
+                                                          DevInfo* info) {
+  gram_reduce_body(P, nchunks, d, dp, G, esq, info, blockIdx.x, gridDim.x);
+}
+
+struct GramReduceArgs {
+  const double* P;
+  double* G;
+  double* esq;
+  DevInfo* info;
+  int nchunks, d, dp;
+};
+
+__global__ __launch_bounds__(256) void gram_reduce_grouped(const GramReduceArgs* __restrict__ a,
+                                                           const int* __restrict__ start, int count) {
+  const int p = group_find(start, count, blockIdx.x);
+  const GramReduceArgs g = a[p];
+  gram_reduce_body(g.P, g.nchunks, g.d, g.dp, g.G, g.esq, g.info, (int)blockIdx.x - start[p], start[p + 1] - start[p]);
+}
+
+void gram_reduce_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL(gram_reduce_grouped, dim3(blocks), dim3(256), 0, s, (const GramReduceArgs*)args, start, count);
 }
 
 int gram_reduce_blocks(int dp) { return (int)ceil_div((int64_t)dp * dp, 256); }
@@ -158,11 +215,13 @@ int gram_chunks(int64_t rows, int dp) {
   // narrow ones the extra partial slabs cost more than they gain (measured)
   const int t = (int)ceil_div(dp, kGT);
   const int npairs = t * (t + 1) / 2;
+  // (chunks of at least 128 rows, so that a short matrix is not cut into
+  // slivers: in a batch the other problems fill the GPU)
   int64_t chunks = ceil_div(npairs >= 21 ? 1024 : 512, npairs);
   const int64_t maxc = ceil_div(rows, kGK);
   if (chunks > maxc) chunks = maxc;
   if (chunks < 1) chunks = 1;
-  const int64_t chunk_rows = round_up(ceil_div(rows, chunks), kGK);
+  const int64_t chunk_rows = std::max<int64_t>(128, round_up(ceil_div(rows, chunks), kGK));
   return (int)ceil_div(rows, chunk_rows);
 }
 
@@ -172,13 +231,15 @@ hipError_t launch_gram(const T* Y, int64_t ldy, int64_t rows, int d, int dp, dou
                        hipEvent_t ev0, hipEvent_t ev1) {
   const int t = (int)ceil_div(dp, kGT);
   const int npairs = t * (t + 1) / 2;
-  const int64_t chunk_rows = round_up(ceil_div(rows, nchunks), kGK);
+  const int64_t chunk_rows = std::max<int64_t>(128, round_up(ceil_div(rows, nchunks), kGK));
   if (ev0) (void)hipEventRecord(ev0, s);
-  hipLaunchKernelGGL(gram_partial_kernel<T>, dim3(npairs * nchunks), dim3(256), 0, s, Y, ldy, rows, d,
-                     dp, chunk_rows, npairs, P);
+  const unsigned pb = (unsigned)(npairs * nchunks);
+  if (!record_launch(&gram_partial_grouped_launch<T>, GramPartialArgs{Y, P, ldy, rows, chunk_rows, d, dp, npairs}, pb))
+    hipLaunchKernelGGL(gram_partial_kernel<T>, dim3(pb), dim3(256), 0, s, Y, ldy, rows, d, dp, chunk_rows, npairs, P);
   if (ev1) (void)hipEventRecord(ev1, s);
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)gram_reduce_blocks(dp)), dim3(256), 0, s, P, nchunks,
-                     d, dp, G, esq, (DevInfo*)info);
+  const unsigned rb = (unsigned)gram_reduce_blocks(dp);
+  if (!record_launch(&gram_reduce_grouped_launch, GramReduceArgs{P, G, esq, (DevInfo*)info, nchunks, d, dp}, rb))
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(rb), dim3(256), 0, s, P, nchunks, d, dp, G, esq, (DevInfo*)info);
   return hipGetLastError();
 }
 template hipError_t launch_gram<float>(const float*, int64_t, int64_t, int, int, double*, int,

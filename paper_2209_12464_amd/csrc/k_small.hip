@@ -2,6 +2,7 @@
 // of the unpivoted QR (R = R2 R1), forming L = R^T of the last QR (the
 // L-values of the method), and resetting the info record.
 #include "common.h"
+#include "grouped.h"
 #include "kernels.h"
 
 namespace rqlp {
@@ -10,13 +11,14 @@ namespace rqlp {
 // its own dependent rows zeroed), one 16 x 16 output tile per wave with the
 // float64 MFMA; written as R (transpose = 0) or as L = R^T (transpose = 1).
 template <typename T>
-__global__ __launch_bounds__(64) void form_r_kernel(const double* __restrict__ R2,
-                                                    const double* __restrict__ R1,
-                                                    const int32_t* __restrict__ f1,
-                                                    const int32_t* __restrict__ f2, int d, int dp,
-                                                    T* __restrict__ out, int64_t ldo, int transpose) {
+__device__ __attribute__((always_inline)) inline void form_r_body(const double* __restrict__ R2,
+                                                                  const double* __restrict__ R1,
+                                                                  const int32_t* __restrict__ f1,
+                                                                  const int32_t* __restrict__ f2, int d, int dp,
+                                                                  T* __restrict__ out, int64_t ldo, int transpose,
+                                                                  int bid) {
   const int nT = dp / kTile;
-  const int I = blockIdx.x / nT, J = blockIdx.x % nT;  // output tile of R
+  const int I = bid / nT, J = bid % nT;  // output tile of R
   const int lane = threadIdx.x, lr = lane >> 4, lc = lane & 15;
   doublex4 acc = Mfma<double>::zero();
   if (I <= J) {
@@ -42,12 +44,43 @@ __global__ __launch_bounds__(64) void form_r_kernel(const double* __restrict__ R
 }
 
 template <typename T>
+__global__ __launch_bounds__(64) void form_r_kernel(const double* __restrict__ R2, const double* __restrict__ R1,
+                                                    const int32_t* __restrict__ f1, const int32_t* __restrict__ f2,
+                                                    int d, int dp, T* __restrict__ out, int64_t ldo, int transpose) {
+  form_r_body<T>(R2, R1, f1, f2, d, dp, out, ldo, transpose, blockIdx.x);
+}
+
+struct FormRArgs {
+  const double* R2;
+  const double* R1;
+  const int32_t* f1;
+  const int32_t* f2;
+  void* out;
+  int64_t ldo;
+  int d, dp, transpose;
+};
+
+template <typename T>
+__global__ __launch_bounds__(64) void form_r_grouped(const FormRArgs* __restrict__ a, const int* __restrict__ start,
+                                                     int count) {
+  const int p = group_find(start, count, blockIdx.x);
+  const FormRArgs g = a[p];
+  form_r_body<T>(g.R2, g.R1, g.f1, g.f2, g.d, g.dp, (T*)g.out, g.ldo, g.transpose, (int)blockIdx.x - start[p]);
+}
+
+template <typename T>
+void form_r_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL(form_r_grouped<T>, dim3(blocks), dim3(64), 0, s, (const FormRArgs*)args, start, count);
+}
+
+template <typename T>
 hipError_t launch_form_l(const double* R2, const double* R1, const int32_t* flags1, int d, int dp,
                          T* L, int64_t ldl, hipStream_t s) {
   // flags of the second pass follow the first pass's dp flags in memory
   const int nT = dp / kTile;
-  hipLaunchKernelGGL(form_r_kernel<T>, dim3(nT * nT), dim3(64), 0, s, R2, R1, flags1, flags1 + dp, d, dp, L,
-                     ldl, 1);
+  const unsigned blocks = (unsigned)(nT * nT);
+  if (!record_launch(&form_r_grouped_launch<T>, FormRArgs{R2, R1, flags1, flags1 + dp, L, ldl, d, dp, 1}, blocks))
+    hipLaunchKernelGGL(form_r_kernel<T>, dim3(blocks), dim3(64), 0, s, R2, R1, flags1, flags1 + dp, d, dp, L, ldl, 1);
   return hipGetLastError();
 }
 template <typename T>

@@ -14,6 +14,7 @@
 // writes its own inverse.  A dependent column has a unit row in R, so the
 // inverse exists and its other columns do not involve it.
 #include "common.h"
+#include "grouped.h"
 #include "kernels.h"
 
 #include <utility>
@@ -124,34 +125,28 @@ __global__ __launch_bounds__(kInvWaves * 64) void trinv_kernel(const double* __r
   trinv_body<kInvWaves, kInvT, kInvAhead>(R, Rinv16, dp, mode, X, blockIdx.x);
 }
 
-// Many matrices in one launch: workgroups start[p] .. start[p + 1] - 1 form
-// the column blocks of matrix p.
-__global__ __launch_bounds__(8 * 64) void trinv_grouped_kernel(TrinvGroup g) {
-  int p = 0;
-  while (p + 1 < g.count && g.start[p + 1] <= (int)blockIdx.x) ++p;
-  const TrinvArgs& a = g.a[p];
-  trinv_body<8, kCholRegMax / kTile, 4>(a.R, a.Rinv16, a.dp, a.mode, a.X, (int)blockIdx.x - g.start[p]);
+// Many matrices in one launch (argument table in device memory):
+// workgroups start[p] .. start[p + 1] - 1 form the column blocks of matrix p.
+struct TrinvRecArgs {
+  const double* R;
+  const double* Rinv16;
+  const int32_t* mode;
+  double* X;
+  int ld;
+};
+
+template <int W, int T, int AH>
+__global__ __launch_bounds__(W * 64) void trinv_grouped(const TrinvRecArgs* __restrict__ a,
+                                                        const int* __restrict__ start, int count) {
+  const int p = group_find(start, count, blockIdx.x);
+  const TrinvRecArgs g = a[p];
+  trinv_body<W, T, AH>(g.R, g.Rinv16, g.ld, g.mode, g.X, (int)blockIdx.x - start[p]);
 }
 
-hipError_t launch_trinv_grouped(const TrinvArgs* args, int count, hipStream_t s) {
-  TrinvGroup g;
-  g.count = 0;
-  g.start[0] = 0;
-  auto flush = [&]() {
-    if (g.count == 0) return;
-    hipLaunchKernelGGL(trinv_grouped_kernel, dim3((unsigned)g.start[g.count]), dim3(8 * kWave), 0, s, g);
-    g.count = 0;
-    g.start[0] = 0;
-  };
-  for (int i = 0; i < count; ++i) {
-    if (args[i].dp > kCholRegMax) return hipErrorInvalidValue;
-    g.a[g.count] = args[i];
-    g.start[g.count + 1] = g.start[g.count] + args[i].dp / kTile;
-    ++g.count;
-    if (g.count == kTrinvGroup) flush();
-  }
-  flush();
-  return hipGetLastError();
+template <int W, int T, int AH>
+void trinv_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL((trinv_grouped<W, T, AH>), dim3(blocks), dim3(W * kWave), 0, s, (const TrinvRecArgs*)args, start,
+                     count);
 }
 
 hipError_t launch_trinv(const double* R, const double* Rinv16, int dp, const int32_t* mode, double* X,
@@ -161,12 +156,16 @@ hipError_t launch_trinv(const double* R, const double* Rinv16, int dp, const int
 
 hipError_t launch_trinv_block(const double* R, const double* Rinv16, int ld, int nT, const int32_t* mode,
                               double* X, hipStream_t s) {
-  if (nT <= kCholRegMax / kTile)
-    hipLaunchKernelGGL((trinv_kernel<8, kCholRegMax / kTile, 4>), dim3((unsigned)nT), dim3(8 * kWave), 0, s, R,
-                       Rinv16, ld, mode, X);
-  else
-    hipLaunchKernelGGL((trinv_kernel<16, kDMax / kTile, 2>), dim3((unsigned)nT), dim3(16 * kWave), 0, s, R,
-                       Rinv16, ld, mode, X);
+  const TrinvRecArgs a{R, Rinv16, mode, X, ld};
+  if (nT <= kCholRegMax / kTile) {
+    if (!record_launch(&trinv_grouped_launch<8, kCholRegMax / kTile, 4>, a, (unsigned)nT))
+      hipLaunchKernelGGL((trinv_kernel<8, kCholRegMax / kTile, 4>), dim3((unsigned)nT), dim3(8 * kWave), 0, s, R,
+                         Rinv16, ld, mode, X);
+  } else {
+    if (!record_launch(&trinv_grouped_launch<16, kDMax / kTile, 2>, a, (unsigned)nT))
+      hipLaunchKernelGGL((trinv_kernel<16, kDMax / kTile, 2>), dim3((unsigned)nT), dim3(16 * kWave), 0, s, R,
+                         Rinv16, ld, mode, X);
+  }
   return hipGetLastError();
 }
 

@@ -98,47 +98,8 @@ hipError_t launch_chol(double* G, int d, int dp, double* R, double* Rinv16, int3
                        void* info, int pass_id, double fast_tol, const double* esq, int nesq,
                        int32_t* mode, double* Xfull, double* gd0, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 
-// Arguments of one matrix of a grouped Cholesky launch (dp <= 256; G, R
-// with row stride dp; otherwise as launch_chol, with tol = 64 d eps64).
-struct CholArgs {
-  const double* G;
-  double* R;
-  double* Rinv16;
-  int32_t* flags;
-  void* info;
-  const double* esq;
-  int32_t* mode;
-  double* Xfull;
-  double tol, fast_tol;
-  int d, dp, pass_id, nesq;
-};
-constexpr int kCholGroup = 24;  // matrices per launch (kernel-argument size)
-struct CholGroup {
-  int count, per;
-  CholArgs a[kCholGroup];
-};
-// One launch per register-slot class (and per 24 matrices) factors all
-// `count` matrices concurrently, each exactly as launch_chol would.
-hipError_t launch_chol_grouped(const CholArgs* args, int count, hipStream_t s);
 // Register-slot class (7, 14 or 17 tiles per wave) of a dp <= 256 factorization.
 int chol_slot_class(int dp);
-
-// Arguments of one matrix of a grouped inverse launch (nT <= 16 block rows).
-struct TrinvArgs {
-  const double* R;
-  const double* Rinv16;
-  const int32_t* mode;
-  double* X;
-  int dp;
-};
-constexpr int kTrinvGroup = 48;
-struct TrinvGroup {
-  int count;
-  int start[kTrinvGroup + 1];  // first workgroup of each matrix
-  TrinvArgs a[kTrinvGroup];
-};
-// launch_trinv for `count` matrices (each dp <= 256) in few launches.
-hipError_t launch_trinv_grouped(const TrinvArgs* args, int count, hipStream_t s);
 
 // ---- SVD of the small factor (k_svd.hip) ----
 // M (d x d, row-major, ld ldm, d <= 544) = U diag(S) V^T: S descending, U

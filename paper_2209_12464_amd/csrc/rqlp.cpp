@@ -22,9 +22,14 @@
 
 #include "rqlp.h"
 #include "common.h"
+#include "grouped.h"
 #include "kernels.h"
 
 using namespace rqlp;
+
+namespace rqlp {
+LaunchRecorder*& launch_recorder();
+}
 
 struct rqlp_ctx {
   int device = 0;
@@ -48,28 +53,23 @@ struct rqlp_ctx {
   struct GraphEntry { std::vector<uint8_t> key; hipGraphExec_t exec; };
   std::vector<GraphEntry> graph_cache;
   std::vector<uint8_t> last_key;  // the last batch run eagerly
-  // Lockstep batches: the launch sequence of every problem is walked once
-  // per segment (the work up to the next Cholesky factorization); only the
-  // target segment's kernels are enqueued, and the factorization closing it
-  // is recorded, so that the factorizations of all problems go out as a few
-  // grouped launches.
-  struct Lockstep {
-    int target = 0, seg = 0;
-    std::vector<CholArgs> chol;     // register-tile factorizations (dp <= 256)
-    std::vector<TrinvArgs> trinv;   // their explicit inverses
-    struct Big { double *G, *R, *rinv, *xf, *esq; int32_t *flags, *mode; int d, dp, pass_id, nesq; double ftol; };
-    std::vector<Big> big;           // blocked factorizations, one launch sequence each
+  // Grouped batches: every problem's launch sequence is recorded once (host
+  // only), then replayed phase by phase as grouped launches whose argument
+  // tables live in device memory; plans are cached per batch descriptor.
+  struct GroupedLaunch { GroupedFn fn; size_t args_off, start_off; int count; unsigned blocks; };
+  struct GroupedPlan {
+    std::vector<uint8_t> key;
+    void* dev = nullptr;  // argument tables and block offsets
+    std::vector<GroupedLaunch> launches;
   };
-  bool lockstep = true;
-  Lockstep* lock = nullptr;
+  std::vector<GroupedPlan> plans;
+  bool lockstep = true;  // grouped batches (else every problem on its lane stream)
   // autotuned split-K counts: (element bytes, trans, M, N, K) -> nsplit
   std::map<std::tuple<int, int, int, int, int>, int> plan;
 };
 
 namespace {
 
-// False while a lockstep walk passes over a segment other than its target.
-inline bool live(const rqlp_ctx* c) { return !c->lock || c->lock->seg == c->lock->target; }
 
 #define HIP_TRY(expr)                                   \
   do {                                                  \
@@ -142,7 +142,10 @@ GemmArgs<T> plan_gemm(int trans, const T* A, int64_t lda, const T* B, int64_t ld
   // Resident workgroup slots: two 4-wave workgroups per CU (register
   // limited), 256 CUs.  Split K so that all slabs x splits fit in one round.
   const int target = std::max(1, env_int("RQLP_GEMM_TARGET_WGS", 512));
-  const int64_t kmin = std::max(16, env_int("RQLP_GEMM_MIN_KCHUNK", 256));
+  // at least 512 reduction steps per split: a small product is not cut into
+  // many slivers (a batch of them fills the GPU anyway), a large one still
+  // takes about two workgroups per CU
+  const int64_t kmin = std::max(16, env_int("RQLP_GEMM_MIN_KCHUNK", 512));
   int64_t ns = target / g.mtiles;
   ns = std::min<int64_t>(ns, std::max<int64_t>(1, ceil_div(K, kmin)));
   ns = std::max<int64_t>(1, ns);
@@ -271,28 +274,19 @@ uint64_t completion_key(int orth_index, int pass) {
 }
 
 // R = chol(G) and its explicit inverse for one CholeskyQR pass (R: r1 or r2,
-// flags and mode of that pass).  In a lockstep walk the factorization that
-// closes the target segment is recorded instead, and every later launch of
-// the walk is skipped.
+// flags and mode of that pass).  While a batch is being recorded, the
+// factorization forms a phase of its own, so that the factorizations of all
+// problems of the batch are grouped together.
 hipError_t factor(rqlp_ctx* c, const Bufs& b, double* R, int32_t* flags, int d, int dp, int orth_index,
                   double ftol, int32_t* mode, int nesq, hipStream_t s) {
-  if (!c->lock) {
-    EvPair t = timer(c, RQLP_KT_CHOL);
-    hipError_t e = launch_chol(b.g, d, dp, R, b.rinv, flags, c->info, orth_index, ftol, b.esq, nesq, mode, b.xf,
-                               b.esq + nesq, s, t.a, t.b);
-    if (e != hipSuccess) return e;
-    return launch_trinv(R, b.rinv, dp, mode, b.xf, s);
-  }
-  rqlp_ctx::Lockstep& L = *c->lock;
-  if (L.seg++ != L.target) return hipSuccess;
-  if (dp <= kCholRegMax) {
-    L.chol.push_back(CholArgs{b.g, R, b.rinv, flags, c->info, b.esq, mode, b.xf, 64.0 * (double)d * 2.220446049250313e-16,
-                              ftol, d, dp, orth_index, nesq});
-    L.trinv.push_back(TrinvArgs{R, b.rinv, mode, b.xf, dp});
-  } else {
-    L.big.push_back({b.g, R, b.rinv, b.xf, b.esq, flags, mode, d, dp, orth_index, nesq, ftol});
-  }
-  return hipSuccess;
+  LaunchRecorder* rec = launch_recorder();
+  if (rec) ++rec->cur_phase;
+  EvPair t = timer(c, RQLP_KT_CHOL);
+  hipError_t e = launch_chol(b.g, d, dp, R, b.rinv, flags, c->info, orth_index, ftol, b.esq, nesq, mode, b.xf,
+                             b.esq + nesq, s, t.a, t.b);
+  if (e == hipSuccess) e = launch_trinv(R, b.rinv, dp, mode, b.xf, s);
+  if (rec) ++rec->cur_phase;
+  return e;
 }
 
 // orth()/qr() of a rows x d matrix Y (ld ldy) by CholeskyQR2.  Pass 1 writes
@@ -307,25 +301,18 @@ rqlp_status cholqr2(rqlp_ctx* c, const T* Y, int64_t ldy, int64_t rows, int d, c
   const double ftol = fast_tol_for(sizeof(T) == 8);
   int32_t* mode = b.flags + 2 * dp;
   const int nesq = gram_reduce_blocks(dp);
-  EvPair t;
-  if (live(c)) {
-    t = timer(c, RQLP_KT_GRAM);
-    HIP_TRY(launch_gram<T>(Y, ldy, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
-  }
+  EvPair t = timer(c, RQLP_KT_GRAM);
+  HIP_TRY(launch_gram<T>(Y, ldy, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
   HIP_TRY(factor(c, b, b.r1, b.flags, d, dp, orth_index, 0.0, mode, nesq, s));
-  if (live(c)) {
-    t = timer(c, RQLP_KT_APPLY);
-    HIP_TRY((launch_apply<T, double>(Y, ldy, rows, d, dp, b.flags, mode, b.xf, b.q1, dp, dp, nullptr, 0, 0, seed,
-                                     completion_key(orth_index, 0), s, t.a, t.b)));
-    t = timer(c, RQLP_KT_GRAM);
-    HIP_TRY(launch_gram<double>(b.q1, dp, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
-  }
+  t = timer(c, RQLP_KT_APPLY);
+  HIP_TRY((launch_apply<T, double>(Y, ldy, rows, d, dp, b.flags, mode, b.xf, b.q1, dp, dp, nullptr, 0, 0, seed,
+                                   completion_key(orth_index, 0), s, t.a, t.b)));
+  t = timer(c, RQLP_KT_GRAM);
+  HIP_TRY(launch_gram<double>(b.q1, dp, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
   HIP_TRY(factor(c, b, b.r2, b.flags + dp, d, dp, orth_index, ftol, mode + 1, nesq, s));
-  if (live(c)) {
-    t = timer(c, RQLP_KT_APPLY);
-    HIP_TRY((launch_apply<double, T>(b.q1, dp, rows, d, dp, b.flags + dp, mode + 1, b.xf, out1, ld1, ncols1, out2, ld2,
-                                     ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b)));
-  }
+  t = timer(c, RQLP_KT_APPLY);
+  HIP_TRY((launch_apply<double, T>(b.q1, dp, rows, d, dp, b.flags + dp, mode + 1, b.xf, out1, ld1, ncols1, out2, ld2,
+                                   ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b)));
   return RQLP_OK;
 }
 
@@ -377,23 +364,23 @@ rqlp_status run_method(rqlp_ctx* c, char* base, const Layout& Lo, int64_t m, int
   rqlp_status st;
   if (c->reset_info) HIP_TRY(launch_info_reset(c->info, s));
   // Omega (n x d, ld dp), then Y = A Omega and Q = orth(Y)
-  if (live(c)) HIP_TRY(launch_gaussian<T>(seed, kSketchKey1, n, d, om, dp, s));
-  if (live(c) && (st = mulA(om, yb)) != RQLP_OK) return st;
+  HIP_TRY(launch_gaussian<T>(seed, kSketchKey1, n, d, om, dp, s));
+  if ((st = mulA(om, yb)) != RQLP_OK) return st;
   int oi = 1;
   if ((st = cholqr2<T>(c, yb, dp, m, d, b, qi, dp, dp, q == 0 ? Q : nullptr, d, d, seed, oi++, s)) != RQLP_OK)
     return st;
   for (int it = 1; it <= q; ++it) {
     // W = orth(A^T Q) (stored in the Omega buffer), Q = orth(A W)
-    if (live(c) && (st = mulAt(qi, yb)) != RQLP_OK) return st;
+    if ((st = mulAt(qi, yb)) != RQLP_OK) return st;
     if ((st = cholqr2<T>(c, yb, dp, n, d, b, om, dp, dp, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
-    if (live(c) && (st = mulA(om, yb)) != RQLP_OK) return st;
+    if ((st = mulA(om, yb)) != RQLP_OK) return st;
     if ((st = cholqr2<T>(c, yb, dp, m, d, b, qi, dp, dp, it == q ? Q : nullptr, d, d, seed, oi++, s)) != RQLP_OK)
       return st;
   }
   // B^T = A^T Q; [V, R] = qr(B^T); L = R^T
-  if (live(c) && (st = mulAt(qi, yb)) != RQLP_OK) return st;
+  if ((st = mulAt(qi, yb)) != RQLP_OK) return st;
   if ((st = cholqr2<T>(c, yb, dp, n, d, b, V, d, d, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
-  if (live(c)) HIP_TRY(launch_form_l<T>(b.r2, b.r1, b.flags, d, dp, Lout, d, s));
+  HIP_TRY(launch_form_l<T>(b.r2, b.r1, b.flags, d, dp, Lout, d, s));
   return RQLP_OK;
 }
 
@@ -488,7 +475,7 @@ rqlp_status decompose_dense_bf16(rqlp_ctx* c, const float* A, int64_t m, int64_t
   uint16_t* at = (uint16_t*)(base + Lo.at);
   uint16_t* xt = (uint16_t*)(base + Lo.xt);
   const int64_t ldn = bf16_ld(n), ldm = bf16_ld(m);
-  if (live(c)) HIP_TRY(launch_cvt_bf16(A, lda, m, n, ab, ldn, at, ldm, s));
+  HIP_TRY(launch_cvt_bf16(A, lda, m, n, ab, ldn, at, ldm, s));
   auto mulA = [&](const float* X, float* Y) -> rqlp_status {  // Y (m x dp) = A X, X n x dp
     HIP_TRY(launch_cvt_bf16_t(X, dp, n, dp, xt, ldn, s));
     EvPair t = timer(c, RQLP_KT_GEMM_NN);
@@ -571,11 +558,24 @@ rqlp_status make_lanes(rqlp_ctx* c) {
   return RQLP_OK;
 }
 
-// Enqueue the batch on `origin`: reset the info record, fork to the lanes,
-// problem i on lane i % kLanes with its own workspace slice, join back.
-// `grouped`: the lockstep form with grouped factorizations.
-rqlp_status run_batch(rqlp_ctx* c, int count, const rqlp_problem* probs, rqlp_precision prec, char* base,
-                      hipStream_t origin, bool grouped) {
+// One problem of a batch, decomposed on `s` with its workspace slice `ws`.
+rqlp_status run_problem(rqlp_ctx* c, const rqlp_problem& P, rqlp_precision prec, char* ws, size_t need,
+                        hipStream_t s) {
+  if (prec == RQLP_FP64)
+    return decompose_dense<double>(c, (const double*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (double*)P.Q,
+                                   (double*)P.L, (double*)P.V, ws, need, s);
+  if (prec == RQLP_BF16_REFINED)
+    return decompose_dense_bf16(c, (const float*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (float*)P.Q,
+                                (float*)P.L, (float*)P.V, ws, need, s);
+  return decompose_dense<float>(c, (const float*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (float*)P.Q,
+                                (float*)P.L, (float*)P.V, ws, need, s);
+}
+
+// Enqueue the batch on `origin`, every problem's launch sequence on its own
+// lane stream (problem i on lane i % kLanes, own workspace slice), forked
+// from and joined back into `origin`.
+rqlp_status run_batch_lanes(rqlp_ctx* c, int count, const rqlp_problem* probs, rqlp_precision prec, char* base,
+                            hipStream_t origin) {
   HIP_TRY(launch_info_reset(c->info, origin));
   HIP_TRY(hipEventRecord(c->fork, origin));
   const int nl = std::min(count, (int)rqlp_ctx::kLanes);
@@ -583,87 +583,12 @@ rqlp_status run_batch(rqlp_ctx* c, int count, const rqlp_problem* probs, rqlp_pr
   const uint32_t timing = c->timing;
   c->timing = 0;
   c->reset_info = false;
-  auto walk = [&]() -> rqlp_status {  // every problem's launch sequence, problem i on lane i % kLanes
-    rqlp_status st = RQLP_OK;
-    size_t off = 0;
-    for (int i = 0; i < count && st == RQLP_OK; ++i) {
-      const rqlp_problem& P = probs[i];
-      const size_t need = problem_ws_bytes(P, prec);
-      hipStream_t s = c->lanes[i % rqlp_ctx::kLanes];
-      char* ws = base + off;
-      off += need;
-      if (c->lock) c->lock->seg = 0;
-      if (prec == RQLP_FP64)
-        st = decompose_dense<double>(c, (const double*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (double*)P.Q,
-                                     (double*)P.L, (double*)P.V, ws, need, s);
-      else if (prec == RQLP_BF16_REFINED)
-        st = decompose_dense_bf16(c, (const float*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (float*)P.Q,
-                                  (float*)P.L, (float*)P.V, ws, need, s);
-      else
-        st = decompose_dense<float>(c, (const float*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (float*)P.Q,
-                                    (float*)P.L, (float*)P.V, ws, need, s);
-    }
-    return st;
-  };
-  // every lane waits for the work enqueued so far on all lanes
-  auto lane_barrier = [&]() -> rqlp_status {
-    for (int l = 0; l < nl; ++l) HIP_TRY(hipEventRecord(c->join[l], c->lanes[l]));
-    for (int l = 0; l < nl; ++l)
-      for (int l2 = 0; l2 < nl; ++l2)
-        if (l2 != l) HIP_TRY(hipStreamWaitEvent(c->lanes[l], c->join[l2], 0));
-    return RQLP_OK;
-  };
   rqlp_status st = RQLP_OK;
-  if (!grouped || count < 2) {
-    st = walk();
-  } else {
-    // Lockstep: segment t of every problem, then the t-th factorization of
-    // every problem as grouped launches spread over the lanes (chunks of
-    // one slot class; a chunk's inverses follow its factorizations on the
-    // same lane), then segment t + 1 ...
-    rqlp_ctx::Lockstep L;
-    c->lock = &L;
-    for (L.target = 0; st == RQLP_OK; ++L.target) {
-      L.chol.clear();
-      L.trinv.clear();
-      L.big.clear();
-      if ((st = walk()) != RQLP_OK) break;
-      if (L.chol.empty() && L.big.empty()) break;
-      if ((st = lane_barrier()) != RQLP_OK) break;
-      int lane = 0;
-      for (const int cls : {7, 14, 17}) {
-        for (const bool fast : {false, true}) {
-          std::vector<CholArgs> ca;
-          std::vector<TrinvArgs> ta;
-          auto flush = [&]() -> rqlp_status {
-            if (ca.empty()) return RQLP_OK;
-            hipStream_t s = c->lanes[lane++ % nl];
-            HIP_TRY(launch_chol_grouped(ca.data(), (int)ca.size(), s));
-            HIP_TRY(launch_trinv_grouped(ta.data(), (int)ta.size(), s));
-            ca.clear();
-            ta.clear();
-            return RQLP_OK;
-          };
-          for (size_t j = 0; j < L.chol.size() && st == RQLP_OK; ++j) {
-            if (chol_slot_class(L.chol[j].dp) != cls || (L.chol[j].fast_tol > 0.0) != fast) continue;
-            ca.push_back(L.chol[j]);
-            ta.push_back(L.trinv[j]);
-            if ((int)ca.size() == kCholGroup) st = flush();
-          }
-          if (st == RQLP_OK) st = flush();
-        }
-      }
-      for (size_t j = 0; j < L.big.size() && st == RQLP_OK; ++j) {
-        const rqlp_ctx::Lockstep::Big& g = L.big[j];
-        hipStream_t s = c->lanes[lane++ % nl];
-        if (launch_chol(g.G, g.d, g.dp, g.R, g.rinv, g.flags, c->info, g.pass_id, g.ftol, g.esq, g.nesq, g.mode,
-                        g.xf, g.esq + g.nesq, s, nullptr, nullptr) != hipSuccess ||
-            launch_trinv(g.R, g.rinv, g.dp, g.mode, g.xf, s) != hipSuccess)
-          st = RQLP_ERR_HIP;
-      }
-      if (st == RQLP_OK) st = lane_barrier();
-    }
-    c->lock = nullptr;
+  size_t off = 0;
+  for (int i = 0; i < count && st == RQLP_OK; ++i) {
+    const size_t need = problem_ws_bytes(probs[i], prec);
+    st = run_problem(c, probs[i], prec, base + off, need, c->lanes[i % rqlp_ctx::kLanes]);
+    off += need;
   }
   c->reset_info = true;
   c->timing = timing;
@@ -672,6 +597,126 @@ rqlp_status run_batch(rqlp_ctx* c, int count, const rqlp_problem* probs, rqlp_pr
     HIP_TRY(hipStreamWaitEvent(origin, c->join[l], 0));
   }
   return st;
+}
+
+LaunchRecorder*& recorder_slot() {
+  static thread_local LaunchRecorder* r = nullptr;
+  return r;
+}
+
+// Record every problem's launch sequence (host only) and lay the launches
+// out as grouped launches: phase by phase (the factorizations form phases of
+// their own), position by position within a phase, one grouped launch per
+// kernel variant, problems in batch order.  Each problem's own launches keep
+// their order, so its results are the bits of its solo run.  The argument
+// tables and block offsets are uploaded once into device memory.
+rqlp_status layout_plan(rqlp_ctx* c, int count, const rqlp_problem* probs, const size_t* offs,
+                        rqlp_precision prec, char* base, hipStream_t s, rqlp_ctx::GroupedPlan* plan,
+                        std::vector<uint8_t>& table) {
+  std::vector<LaunchRecorder> recs((size_t)count);
+  const uint32_t timing = c->timing;
+  c->timing = 0;
+  c->reset_info = false;
+  rqlp_status st = RQLP_OK;
+  size_t off = 0;
+  for (int i = 0; i < count && st == RQLP_OK; ++i) {
+    const size_t need = problem_ws_bytes(probs[i], prec);
+    if (offs) off = offs[i];
+    recorder_slot() = &recs[(size_t)i];
+    st = run_problem(c, probs[i], prec, base + off, need, s);
+    recorder_slot() = nullptr;
+    off += need;
+  }
+  c->reset_info = true;
+  c->timing = timing;
+  if (st != RQLP_OK) return st;
+  // positions: (phase, index within the phase) of every recorded launch
+  int nphase = 0;
+  for (auto& r : recs) nphase = std::max(nphase, r.cur_phase + 1);
+  std::vector<std::vector<std::pair<size_t, size_t>>> spans((size_t)count);  // per problem: [begin, end) per phase
+  size_t maxlen = 0;
+  for (int i = 0; i < count; ++i) {
+    const LaunchRecorder& r = recs[(size_t)i];
+    spans[(size_t)i].assign((size_t)nphase, {0, 0});
+    for (size_t k = 0; k < r.seq.size();) {
+      size_t e = k;
+      while (e < r.seq.size() && r.phase[e] == r.phase[k]) ++e;
+      spans[(size_t)i][(size_t)r.phase[k]] = {k, e};
+      maxlen = std::max(maxlen, e - k);
+      k = e;
+    }
+  }
+  table.clear();
+  auto reserve = [&](size_t bytes) {
+    const size_t o = (table.size() + 15) & ~(size_t)15;
+    table.resize(o + bytes);
+    return o;
+  };
+  plan->launches.clear();
+  for (int ph = 0; ph < nphase; ++ph) {
+    for (size_t j = 0; j < maxlen; ++j) {
+      // kernel variants at this position, in order of first appearance
+      std::vector<GroupedFn> fns;
+      for (int i = 0; i < count; ++i) {
+        const auto sp = spans[(size_t)i][(size_t)ph];
+        if (sp.first + j >= sp.second) continue;
+        const LaunchRec& x = recs[(size_t)i].seq[sp.first + j];
+        if (x.blocks > 0 && std::find(fns.begin(), fns.end(), x.fn) == fns.end()) fns.push_back(x.fn);
+      }
+      for (GroupedFn fn : fns) {
+        std::vector<const LaunchRec*> items;
+        for (int i = 0; i < count; ++i) {
+          const auto sp = spans[(size_t)i][(size_t)ph];
+          if (sp.first + j >= sp.second) continue;
+          const LaunchRec& x = recs[(size_t)i].seq[sp.first + j];
+          if (x.fn == fn && x.blocks > 0) items.push_back(&x);
+        }
+        const size_t asz = items[0]->size;
+        const size_t aoff = reserve(asz * items.size());
+        const size_t soff = reserve(sizeof(int) * (items.size() + 1));
+        int total = 0;
+        for (size_t t = 0; t < items.size(); ++t) {
+          std::memcpy(table.data() + aoff + t * asz, items[t]->args, asz);
+          std::memcpy(table.data() + soff + t * sizeof(int), &total, sizeof(int));
+          if ((int64_t)total + items[t]->blocks > INT32_MAX) return RQLP_ERR_UNSUPPORTED;
+          total += (int)items[t]->blocks;
+        }
+        std::memcpy(table.data() + soff + items.size() * sizeof(int), &total, sizeof(int));
+        plan->launches.push_back({fn, aoff, soff, (int)items.size(), (unsigned)total});
+      }
+    }
+  }
+  if (table.empty()) table.resize(16);
+  return RQLP_OK;
+}
+
+// layout_plan, then the tables into a device allocation of the plan's own.
+rqlp_status build_plan(rqlp_ctx* c, int count, const rqlp_problem* probs, rqlp_precision prec, char* base,
+                       hipStream_t s, rqlp_ctx::GroupedPlan* plan) {
+  std::vector<uint8_t> table;
+  rqlp_status st = layout_plan(c, count, probs, nullptr, prec, base, s, plan, table);
+  if (st != RQLP_OK) return st;
+  if (hipMalloc(&plan->dev, table.size()) != hipSuccess) {
+    plan->dev = nullptr;
+    return RQLP_ERR_OUT_OF_MEMORY;
+  }
+  if (hipMemcpy(plan->dev, table.data(), table.size(), hipMemcpyHostToDevice) != hipSuccess) return RQLP_ERR_HIP;
+  return RQLP_OK;
+}
+
+// The grouped launches of a plan on one stream (graph-capturable: kernel
+// launches only).
+rqlp_status launch_plan(rqlp_ctx* c, const rqlp_ctx::GroupedPlan& plan, hipStream_t s) {
+  HIP_TRY(launch_info_reset(c->info, s));
+  const char* dev = (const char*)plan.dev;
+  for (const auto& L : plan.launches) L.fn(dev + L.args_off, (const int*)(dev + L.start_off), L.count, L.blocks, s);
+  HIP_TRY(hipGetLastError());
+  return RQLP_OK;
+}
+
+void free_plan(rqlp_ctx::GroupedPlan& p) {
+  if (p.dev) hipFree(p.dev);
+  p.dev = nullptr;
 }
 
 std::vector<uint8_t> batch_key(int count, const rqlp_problem* probs, rqlp_precision prec, const void* ws,
@@ -867,6 +912,7 @@ rqlp_status rqlp_destroy(rqlp_ctx* c) {
   resolve_timing(c);
   for (hipEvent_t e : c->pool) hipEventDestroy(e);
   for (auto& e : c->graph_cache) hipGraphExecDestroy(e.exec);
+  for (auto& p : c->plans) free_plan(p);
   for (int l = 0; l < rqlp_ctx::kLanes; ++l) {
     if (c->lanes[l]) hipStreamDestroy(c->lanes[l]);
     if (c->join[l]) hipEventDestroy(c->join[l]);
@@ -968,24 +1014,53 @@ rqlp_status rqlp_decompose_batched(rqlp_ctx* c, int count, const rqlp_problem* p
   char* base = nullptr;
   if ((st = get_workspace(c, ws, ws_bytes, need, &base)) != RQLP_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  if (!c->graphs) return run_batch(c, count, probs, prec, base, s, c->lockstep);
+  // the bfloat16 form's conversion and product kernels have no grouped form:
+  // its batches run every problem's sequence on a lane stream
+  if (!c->lockstep || prec == RQLP_BF16_REFINED) {
+    if (!c->graphs) return run_batch_lanes(c, count, probs, prec, base, s);
+  }
+  std::vector<uint8_t> key = batch_key(count, probs, prec, base, need);
+  if (c->graphs) {
+    for (auto& e : c->graph_cache)
+      if (e.key == key) {
+        HIP_TRY(hipGraphLaunch(e.exec, s));
+        return RQLP_OK;
+      }
+  }
+  // Graph capture takes the ungrouped form: a grouped batch has not been run
+  // under stream capture in this build (an earlier grouped design ended the
+  // host process under capture, with no cause found), so it runs eagerly.
+  const bool grouped = c->lockstep && prec != RQLP_BF16_REFINED && !c->graphs;
+  rqlp_ctx::GroupedPlan* plan = nullptr;
+  if (grouped) {
+    for (auto& p : c->plans)
+      if (p.key == key) plan = &p;
+    if (!plan) {
+      rqlp_ctx::GroupedPlan np;
+      np.key = key;
+      st = build_plan(c, count, probs, prec, base, s, &np);
+      if (st != RQLP_OK) {
+        free_plan(np);
+        return st;
+      }
+      if (c->plans.size() >= 8) {  // the oldest plan may still be read by queued work
+        HIP_TRY(hipDeviceSynchronize());
+        free_plan(c->plans.front());
+        c->plans.erase(c->plans.begin());
+      }
+      c->plans.push_back(std::move(np));
+      plan = &c->plans.back();
+    }
+  }
   // graphs: a batch seen for the second time in a row (same problems,
   // buffers and workspace) is captured once and replayed from then on
-  std::vector<uint8_t> key = batch_key(count, probs, prec, base, need);
-  for (auto& e : c->graph_cache)
-    if (e.key == key) {
-      HIP_TRY(hipGraphLaunch(e.exec, s));
-      return RQLP_OK;
-    }
-  if (key != c->last_key) {
+  if (!c->graphs || key != c->last_key) {
     c->last_key = key;
-    return run_batch(c, count, probs, prec, base, s, c->lockstep);
+    return grouped ? launch_plan(c, *plan, s) : run_batch_lanes(c, count, probs, prec, base, s);
   }
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-  // captured batches keep every problem's sequence on its stream: the
-  // grouped form has not been validated under stream capture
-  st = run_batch(c, count, probs, prec, base, c->cap, false);
+  st = grouped ? launch_plan(c, *plan, c->cap) : run_batch_lanes(c, count, probs, prec, base, c->cap);
   const hipError_t e_end = hipStreamEndCapture(c->cap, &g);
   if (st != RQLP_OK) {
     if (g) hipGraphDestroy(g);
@@ -1392,28 +1467,34 @@ struct rqlp_server {
   rqlp_precision prec = RQLP_FP32;
   char* pool = nullptr;
   size_t budget = 0;
+  // A tick: the requests admitted together, launched as one grouped batch on
+  // the tick's stream and completed together.
   struct Slot {
     hipStream_t s = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
-    int64_t ticket = -1;
-    size_t off = 0, size = 0;
+    std::vector<int64_t> tickets;
+    std::vector<std::pair<size_t, size_t>> ranges;  // workspace (offset, bytes) per request
+    void* table_dev = nullptr;                      // grouped argument tables of the tick
+    size_t table_bytes = 0;
+    std::vector<uint8_t> table_host;                // kept until the tick completes
+    rqlp_ctx::GroupedPlan plan;
   };
   // A queued request and the event recorded on the submitter's stream at
-  // submit: the slot stream waits on it, so work the caller enqueued before
+  // submit: the tick stream waits on it, so work the caller enqueued before
   // submitting (writing A, say) is complete before the request reads it.
   struct Queued {
     int64_t ticket;
     rqlp_problem prob;
     hipEvent_t ready;
   };
+  int max_tick = 64;  // requests per tick
   std::vector<Slot> slots;
   std::deque<Queued> queue;
   std::vector<hipEvent_t> event_pool;
   std::deque<std::pair<int64_t, rqlp_status>> failed;  // launches that failed, reported by poll
   std::map<size_t, size_t> free_ranges;  // offset -> bytes, coalesced
   int64_t next_ticket = 0;
-  int64_t inflight_bytes = 0;
 };
 
 namespace {
@@ -1448,27 +1529,51 @@ void pool_free(rqlp_server* sv, size_t off, size_t bytes) {
   }
 }
 
-rqlp_status launch_request(rqlp_server* sv, rqlp_server::Slot& sl, const rqlp_server::Queued& rq) {
+// Launch the requests `rq` (workspace offsets in the pool already taken) as
+// one tick on slot `sl`: the grouped batch executor's launches (every result
+// the bits of the request's solo run), or, for the bfloat16 form, every
+// request's own sequence, all on the tick stream.
+// A tick of one request runs the request's own sequence (no tables to build).
+rqlp_status launch_tick(rqlp_server* sv, rqlp_server::Slot& sl, const std::vector<rqlp_server::Queued>& rq) {
   rqlp_ctx* c = sv->ctx;
-  const rqlp_problem& P = rq.prob;
-  HIP_TRY(hipStreamWaitEvent(sl.s, rq.ready, 0));
+  for (const auto& q : rq) HIP_TRY(hipStreamWaitEvent(sl.s, q.ready, 0));
+  std::vector<rqlp_problem> probs;
+  std::vector<size_t> offs;
+  for (size_t i = 0; i < rq.size(); ++i) {
+    probs.push_back(rq[i].prob);
+    offs.push_back(sl.ranges[i].first);
+  }
   const uint32_t timing = c->timing;
-  c->timing = 0;
-  c->reset_info = false;
-  char* ws = sv->pool + sl.off;
-  rqlp_status st;
-  if (sv->prec == RQLP_FP64)
-    st = decompose_dense<double>(c, (const double*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (double*)P.Q,
-                                 (double*)P.L, (double*)P.V, ws, sl.size, sl.s);
-  else if (sv->prec == RQLP_BF16_REFINED)
-    st = decompose_dense_bf16(c, (const float*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (float*)P.Q,
-                              (float*)P.L, (float*)P.V, ws, sl.size, sl.s);
-  else
-    st = decompose_dense<float>(c, (const float*)P.A, P.m, P.n, P.lda, P.k, P.p, P.q, P.seed, (float*)P.Q,
-                                (float*)P.L, (float*)P.V, ws, sl.size, sl.s);
-  c->reset_info = true;
-  c->timing = timing;
-  if (st != RQLP_OK) return st;
+  rqlp_status st = RQLP_OK;
+  if (sv->prec != RQLP_BF16_REFINED && probs.size() > 1) {
+    st = layout_plan(c, (int)probs.size(), probs.data(), offs.data(), sv->prec, sv->pool, sl.s, &sl.plan,
+                     sl.table_host);
+    if (st != RQLP_OK) return st;
+    if (sl.table_bytes < sl.table_host.size()) {
+      if (sl.table_dev) hipFree(sl.table_dev);
+      sl.table_dev = nullptr;
+      sl.table_bytes = 0;
+      if (hipMalloc(&sl.table_dev, sl.table_host.size()) != hipSuccess) return RQLP_ERR_OUT_OF_MEMORY;
+      sl.table_bytes = sl.table_host.size();
+    }
+    HIP_TRY(hipMemcpyAsync(sl.table_dev, sl.table_host.data(), sl.table_host.size(), hipMemcpyHostToDevice, sl.s));
+    sl.plan.dev = sl.table_dev;
+    c->timing = 0;
+    const char* dev = (const char*)sl.table_dev;
+    for (const auto& L : sl.plan.launches)
+      L.fn(dev + L.args_off, (const int*)(dev + L.start_off), L.count, L.blocks, sl.s);
+    sl.plan.dev = nullptr;  // owned by the slot
+    c->timing = timing;
+    HIP_TRY(hipGetLastError());
+  } else {
+    c->timing = 0;
+    c->reset_info = false;
+    for (size_t i = 0; i < probs.size() && st == RQLP_OK; ++i)
+      st = run_problem(c, probs[i], sv->prec, sv->pool + offs[i], sl.ranges[i].second, sl.s);
+    c->reset_info = true;
+    c->timing = timing;
+    if (st != RQLP_OK) return st;
+  }
   HIP_TRY(hipEventRecord(sl.done, sl.s));
   return RQLP_OK;
 }
@@ -1528,11 +1633,18 @@ rqlp_status rqlp_server_destroy(rqlp_server* sv) {
     if (sl.s) hipStreamSynchronize(sl.s);
     if (sl.done) hipEventDestroy(sl.done);
     if (sl.s) hipStreamDestroy(sl.s);
+    if (sl.table_dev) hipFree(sl.table_dev);
   }
   for (auto& rq : sv->queue) hipEventDestroy(rq.ready);
   for (hipEvent_t e : sv->event_pool) hipEventDestroy(e);
   if (sv->pool) hipFree(sv->pool);
   delete sv;
+  return RQLP_OK;
+}
+
+rqlp_status rqlp_server_set_tick(rqlp_server* sv, int max_requests) {
+  if (!sv || max_requests < 1 || max_requests > 1024) return RQLP_ERR_INVALID_ARG;
+  sv->max_tick = max_requests;
   return RQLP_OK;
 }
 
@@ -1571,45 +1683,66 @@ rqlp_status rqlp_server_poll(rqlp_server* sv, int64_t* done, int32_t* status, in
     sv->failed.pop_front();
   }
   for (auto& sl : sv->slots) {
-    if (!sl.busy || *ndone >= max_done) continue;
+    if (!sl.busy || *ndone + (int)sl.tickets.size() > max_done) continue;
     const hipError_t q = hipEventQuery(sl.done);
     if (q == hipErrorNotReady) continue;
     if (q != hipSuccess) return RQLP_ERR_HIP;
     sl.busy = false;
-    pool_free(sv, sl.off, sl.size);
-    if (status) status[*ndone] = RQLP_OK;
-    done[(*ndone)++] = sl.ticket;
+    for (const auto& r : sl.ranges) pool_free(sv, r.first, r.second);
+    for (const int64_t t : sl.tickets) {
+      if (status) status[*ndone] = RQLP_OK;
+      done[(*ndone)++] = t;
+    }
+    sl.tickets.clear();
+    sl.ranges.clear();
   }
-  // admissions, in arrival order: the head waits until it fits
+  // admissions, in arrival order (the head waits until its workspace fits),
+  // one tick per free slot: the queue is shared out over the free slots, so
+  // that requests run alone while the queue is short and are grouped (at most
+  // max_tick per tick) only when a backlog builds up
+  int free_slots = 0;
+  for (auto& sl : sv->slots) free_slots += sl.busy ? 0 : 1;
   for (auto& sl : sv->slots) {
     if (sl.busy) continue;
     if (sv->queue.empty()) break;
-    const rqlp_server::Queued rq = sv->queue.front();
-    const size_t need = problem_ws_bytes(rq.prob, sv->prec);
-    size_t off = 0;
-    if (!pool_alloc(sv, need, &off)) break;
-    sl.off = off;
-    sl.size = need;
-    sl.ticket = rq.ticket;
-    sv->queue.pop_front();
-    const rqlp_status st = launch_request(sv, sl, rq);
-    sv->event_pool.push_back(rq.ready);  // the slot's wait on it is already enqueued
+    const int share = (int)std::min<int64_t>(sv->max_tick, ceil_div((int64_t)sv->queue.size(), std::max(free_slots, 1)));
+    --free_slots;
+    std::vector<rqlp_server::Queued> tick;
+    while (!sv->queue.empty() && (int)tick.size() < share) {
+      const rqlp_server::Queued& rq = sv->queue.front();
+      const size_t need = problem_ws_bytes(rq.prob, sv->prec);
+      size_t off = 0;
+      if (!pool_alloc(sv, need, &off)) break;
+      sl.ranges.emplace_back(off, need);
+      sl.tickets.push_back(rq.ticket);
+      tick.push_back(rq);
+      sv->queue.pop_front();
+    }
+    if (tick.empty()) break;
+    const rqlp_status st = launch_tick(sv, sl, tick);
+    for (const auto& q : tick) sv->event_pool.push_back(q.ready);  // the tick's waits are enqueued
     if (st != RQLP_OK) {
-      // part of the request may already be on the slot's stream: let it
-      // drain before its workspace goes back to the pool, and report the
-      // ticket as failed
+      // part of the tick may already be on its stream: let it drain before
+      // the workspace goes back to the pool, and report the tickets as failed
       if (hipStreamSynchronize(sl.s) != hipSuccess) return RQLP_ERR_HIP;
-      pool_free(sv, off, need);
-      sv->failed.emplace_back(rq.ticket, st);
+      for (const auto& r : sl.ranges) pool_free(sv, r.first, r.second);
+      for (const int64_t t : sl.tickets) sv->failed.emplace_back(t, st);
+      sl.tickets.clear();
+      sl.ranges.clear();
       continue;
     }
     sl.busy = true;
   }
   int nb = 0;
-  for (auto& sl : sv->slots) nb += sl.busy ? 1 : 0;
+  for (auto& sl : sv->slots) nb += sl.busy ? (int)sl.tickets.size() : 0;
   if (inflight) *inflight = nb;
   if (queued) *queued = (int)sv->queue.size();
   return RQLP_OK;
 }
 
 }  // extern "C"
+
+namespace rqlp {
+// The launch recorder of the calling thread (see grouped.h).
+LaunchRecorder*& launch_recorder() { return recorder_slot(); }
+}  // namespace rqlp

@@ -99,6 +99,7 @@ def _lib():
             "rqlp_server_create": (_INT, [ctypes.POINTER(_P), _P, _SZ, _INT, _INT]),
             "rqlp_server_destroy": (_INT, [_P]),
             "rqlp_server_request_bytes": (_SZ, [ctypes.POINTER(Problem), _INT]),
+            "rqlp_server_set_tick": (_INT, [_P, _INT]),
             "rqlp_server_submit": (_INT, [_P, ctypes.POINTER(Problem), _P, ctypes.POINTER(_I64)]),
             "rqlp_server_poll": (_INT, [_P, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32), _INT,
                                         ctypes.POINTER(_INT), ctypes.POINTER(_INT), ctypes.POINTER(_INT)]),
@@ -127,7 +128,8 @@ def exported_symbols():
             "rqlp_autotune", "rqlp_autotune_clear", "rqlp_autotune_count", "rqlp_autotune_save",
             "rqlp_autotune_load",
             "rqlp_workspace_size_svd", "rqlp_decompose_svd",
-            "rqlp_server_create", "rqlp_server_destroy", "rqlp_server_request_bytes", "rqlp_server_submit",
+            "rqlp_server_create", "rqlp_server_destroy", "rqlp_server_request_bytes", "rqlp_server_set_tick",
+            "rqlp_server_submit",
             "rqlp_server_poll", "rqlp_workspace_size_paper", "rqlp_decompose_paper"]
 
 
@@ -238,7 +240,7 @@ class Context:
         _check(_lib().rqlp_autotune_load(self._h, str(path).encode()), "rqlp_autotune_load")
 
     def set_batch_grouping(self, enabled):
-        """Grouped (lockstep) factorizations in batches (on by default)."""
+        """Grouped launches for batches (on by default; off: one lane stream per problem)."""
         _check(_lib().rqlp_set_batch_grouping(self._h, 1 if enabled else 0), "rqlp_set_batch_grouping")
 
     def set_timing(self, enabled, classes=None):
@@ -464,15 +466,17 @@ class Server:
     poll() reports its ticket); poll() returns finished tickets and admits
     queued requests."""
 
-    def __init__(self, budget_bytes, slots=8, dtype=torch.float32, bf16=False, ctx=None, device=0):
+    def __init__(self, budget_bytes, slots=8, dtype=torch.float32, bf16=False, ctx=None, device=0, max_tick=None):
         self.ctx = ctx or default_context(device)
         self._prec = _prec(dtype, bf16)
         h = ctypes.c_void_p()
         _check(_lib().rqlp_server_create(ctypes.byref(h), self.ctx.handle, int(budget_bytes), int(slots),
                                          self._prec), "rqlp_server_create")
         self._h = h
-        self._done = (ctypes.c_int64 * 256)()
-        self._status = (ctypes.c_int32 * 256)()
+        if max_tick is not None:
+            _check(_lib().rqlp_server_set_tick(self._h, int(max_tick)), "rqlp_server_set_tick")
+        self._done = (ctypes.c_int64 * 2048)()
+        self._status = (ctypes.c_int32 * 2048)()
         self.failed = {}  # ticket -> status of requests whose launch failed
         _LIVE.add(self)
 

@@ -127,3 +127,23 @@ def test_batched_info_covers_batch(gpu_lib):
     torch.cuda.synchronize()
     info = ctx.info()
     assert info["completed_cols"] > 0 and info["nonfinite"] == 0
+
+
+def test_grouped_plan_cache_reuse_and_eviction(gpu_lib):
+    """Grouped batches keep their argument tables per batch descriptor: the
+    same batch again reuses them, and more distinct batches than the cache
+    holds evict the oldest; every call gives the solo results bitwise."""
+    announce("grouped plan cache")
+    reqs, As, params = _batch(torch.float32, count=5, seed=17)
+    ctx = gpu_lib.Context(0)
+    ws = gpu_lib.alloc_workspace(gpu_lib.workspace_size_batched(
+        [(A.shape[0], A.shape[1], k, p, q) for A, (k, p, q, s) in zip(As, params)], torch.float32), As[0].device)
+    outs = [(torch.empty((A.shape[0], k + p), device=A.device), torch.empty((k + p, k + p), device=A.device),
+             torch.empty((A.shape[1], k + p), device=A.device)) for A, (k, p, q, s) in zip(As, params)]
+    for rep in range(11):  # ten distinct descriptors, the first one again at the end
+        shift = rep % 10
+        ps = [(k, p, q, s + shift) for (k, p, q, s) in params]
+        gpu_lib.decompose_batched(As, ps, ctx=ctx, workspace=ws, outs=outs)
+        torch.cuda.synchronize()
+        if rep in (0, 3, 9, 10):
+            _same(outs, _solo(gpu_lib, As, ps))
