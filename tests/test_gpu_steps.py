@@ -125,6 +125,8 @@ def _conditioned(m, d, cond, seed):
                                       (300, 1, 1.0), (4000, 110, 1e6),
                                       # d > 256: the Cholesky keeps its trailing tiles in memory
                                       (3000, 320, 1e4), (2000, 544, 1e2), (1200, 417, 1e6), (600, 257, 10.0),
+                                      # diagonal blocks of 13 and 15 tile columns
+                                      (1500, 400, 1e3), (2000, 470, 1e3),
                                       # tall enough for two row fragments per wave in the solve
                                       (70000, 100, 1e3), (30000, 300, 1e2)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
