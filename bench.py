@@ -47,7 +47,7 @@ WORKLOADS = {
                           svd=True),
     "batch64": dict(kind="batch", count=64, q=1, dtype="f32"),
     # the serving stream: 4096 Poisson-arrival requests over 64 distinct matrices
-    "serve4096": dict(kind="serve", count=4096, pool=64, q=1, dtype="f32", slots=4, tick=16, budget_gb=8.0),
+    "serve4096": dict(kind="serve", count=4096, pool=64, q=1, dtype="f32", slots=8, tick=2, budget_gb=8.0),
     # bfloat16 products with float32 accumulation, float64 Gram and Cholesky
     "bf16_20000x15000": dict(kind="dense", m=20000, n=15000, k=500, p=20, q=1, dtype="f32",
                              spectrum="polynomial", bf16=True),
@@ -366,21 +366,24 @@ def run_batch_bench(args, w, rqlp, torch, dev):
     # one step: the batch as grouped launches (every phase of every problem
     # in one launch per kernel variant, argument tables cached on the device)
     ms = timed(lambda: rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs), args.steps)
-    # for comparison: every problem's sequence on its own lane stream, eager
-    # and replayed from a captured graph
-    ctx.set_batch_grouping(False)
-    ungrouped_ms = timed(lambda: rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs), args.steps)
-    ctx.set_batch_grouping(True)
-    ctx.set_graphs(True)
-    graph_ms = timed(lambda: rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs), args.steps)
-    ctx.set_graphs(False)
-    solo_ws = rqlp.alloc_workspace(max(rqlp.workspace_size(r["m"], r["n"], r["k"], r["p"], w["q"], torch.float32)
-                                       for r in reqs), dev)
+    ungrouped_ms = graph_ms = seq_ms = None
+    if not args.no_compare:
+        # for comparison: every problem's sequence on its own lane stream,
+        # eager and replayed from a captured graph
+        ctx.set_batch_grouping(False)
+        ungrouped_ms = timed(lambda: rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs),
+                             args.steps)
+        ctx.set_batch_grouping(True)
+        ctx.set_graphs(True)
+        graph_ms = timed(lambda: rqlp.decompose_batched(As, params, ctx=ctx, workspace=ws, outs=outs), args.steps)
+        ctx.set_graphs(False)
+        solo_ws = rqlp.alloc_workspace(max(rqlp.workspace_size(r["m"], r["n"], r["k"], r["p"], w["q"],
+                                                               torch.float32) for r in reqs), dev)
 
-    def sequential():
-        for A, (k, p, q, seed), o in zip(As, params, outs):
-            rqlp.decompose(A, k, p, q, seed=seed, ctx=ctx, workspace=solo_ws, out=o)
-    seq_ms = timed(sequential, max(1, args.steps // 4))
+        def sequential():
+            for A, (k, p, q, seed), o in zip(As, params, outs):
+                rqlp.decompose(A, k, p, q, seed=seed, ctx=ctx, workspace=solo_ws, out=o)
+        seq_ms = timed(sequential, max(1, args.steps // 4))
     roof = products_roofline(rqlp, ctx, As, [dict(r, seed=s_) for r, (_, _, _, s_) in zip(reqs, params)], w["q"],
                              torch)
     res = {
@@ -543,7 +546,8 @@ def main():
     ap.add_argument("--slots", type=int, default=0, help="serving: tick streams (default: the workload's)")
     ap.add_argument("--tick", type=int, default=0, help="serving: requests per tick (default: the workload's)")
     ap.add_argument("--no-compare", action="store_true",
-                    help="bfloat16 workload: skip the float32 comparison run")
+                    help="bfloat16 workload: skip the float32 comparison run; batch workload: time the "
+                         "grouped form only (no lane, graph or one-by-one runs)")
     ap.add_argument("--no-svd-split", action="store_true",
                     help="SVD-like workload: skip the separate timing of the small SVD")
     ap.add_argument("--copy-calibration", action="store_true",
