@@ -222,29 +222,34 @@ rqlp_status rqlp_decompose_paper(rqlp_ctx* ctx, const void* A, int64_t m, int64_
                                  int q, rqlp_precision prec, uint64_t seed, void* Q, void* L, void* P,
                                  void* workspace, size_t ws_bytes, void* stream);
 
-/* ---- Autotuning of the products' split-K plans ---- */
+/* ---- Autotuning of the products' plans (tile shape and split-K) ---- */
 
-/* Time the split-K candidates of the two products a dense decomposition of
+/* Time the candidate plans of the two products a dense decomposition of
  * this shape issues (Y = A X and Y = A^T X with d columns, float32 or
- * float64 kernel; the sketch and projection products of Section III-A) and keep the
- * fastest split count per product shape in the context's plan table; later
+ * float64 kernel; the sketch and projection products of Section III-A) and
+ * keep the fastest per product shape in the context's plan table; later
  * calls on the context (decompositions, batches, servers, rqlp_gemm) use
- * it.  The default plan fills about two workgroups per CU; candidates go up
- * to four.  A (m x n, lda >= n) is only read; scratch comes from the
- * context's internal workspace.  Synchronizes `stream`.  The chosen counts
- * are returned in *nsplit_nn and *nsplit_tn (either may be NULL).  A plan
- * changes the summation order of a product, so results are reproducible
- * bit for bit for a given plan table, not across tables. */
+ * it.  A plan is a row tile (128 rows per workgroup, two workgroups per CU;
+ * for float32 also 256 rows, one workgroup per CU) and a split-K count (the
+ * default plan fills about two workgroups per CU; candidates go up to
+ * four).  A (m x n, lda >= n) is only read; scratch comes from the context's
+ * internal workspace.  Synchronizes `stream`.  The chosen split counts are
+ * returned in *nsplit_nn and *nsplit_tn (either may be NULL).  The split
+ * count changes the summation order of a product (the row tile does not),
+ * so results are reproducible bit for bit for a given plan table, not
+ * across tables. */
 rqlp_status rqlp_autotune(rqlp_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda, int d,
                           rqlp_precision prec, void* stream, int* nsplit_nn, int* nsplit_tn);
 /* Forget every tuned plan. */
 rqlp_status rqlp_autotune_clear(rqlp_ctx* ctx);
 /* Number of tuned product shapes in the table. */
 rqlp_status rqlp_autotune_count(rqlp_ctx* ctx, int* count);
-/* Write the plan table to a text file ("rqlp-plans 1", then one line
- * "gemm <element bytes> <trans> <M> <N> <K> <nsplit>" per shape), or merge
- * one read from such a file into the table (RQLP_ERR_INVALID_ARG, table
- * unchanged, on a malformed file). */
+/* Write the plan table to a text file ("rqlp-plans 2", then one line
+ * "gemm <element bytes> <trans> <M> <N> <K> <nsplit> <mb>" per shape, mb = 2
+ * for 128-row and 4 for 256-row tiles), or merge one read from such a file
+ * into the table (version 1 files, without the mb field, are read as 128-row
+ * tiles; RQLP_ERR_INVALID_ARG, table unchanged, on a malformed file or a
+ * 256-row tile for float64). */
 rqlp_status rqlp_autotune_save(rqlp_ctx* ctx, const char* path);
 rqlp_status rqlp_autotune_load(rqlp_ctx* ctx, const char* path);
 

@@ -9,11 +9,14 @@
 // Workgroup ids are remapped so that an XCD works on a contiguous range of
 // (split, slab) pairs: the X chunk of a split then stays in that XCD's L2.
 //
-// Tiles: 8 waves as 4 (rows) x 2 (columns); each wave owns 32 rows and half
-// of the BN = 32 * NBW columns, i.e. 2 x NBW blocks of 16 x 16 accumulated
-// with the 16x16x4 MFMA (float or double).  BK = 16 along the reduction.  A
-// and X tiles are staged through LDS, double buffered with register
-// prefetch, one barrier per K step.
+// Tiles: 8 waves as 4 (rows) x 2 (columns); each wave owns 16 MB rows and
+// half of the BN = 32 * NBW columns, i.e. MB x NBW blocks of 16 x 16
+// accumulated with the 16x16x4 MFMA (float or double).  MB = 2 (128-row
+// slabs, two workgroups per CU) is the default shape; MB = 4 (256-row slabs,
+// float only, one workgroup per CU, fewer LDS operand reads per MFMA) is the
+// alternative the autotuner may pick per product shape.  BK = 16 along the
+// reduction.  A and X tiles are staged through LDS, double buffered with
+// register prefetch, one barrier per K step.
 #include "common.h"
 #include "grouped.h"
 #include "kernels.h"
@@ -26,20 +29,21 @@ constexpr int kGemmThreads = 512;
 constexpr int kBK = 16;
 
 // One workgroup's share: tile `logical` = split * mtiles + slab.
-template <typename T, int NBW, bool TRANS, bool AVEC, bool BVEC>
+template <typename T, int NBW, bool TRANS, bool AVEC, bool BVEC, int MB>
 __device__ __attribute__((always_inline)) inline void gemm_body(
     const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
     T* __restrict__ C, int64_t ldc, int64_t cslice, int M, int N, int K, int kchunk, int mtiles,
     int nst, int logical) {
   typedef Mfma<T> MF;
-  constexpr int BM = 128;                  // 4 row groups x 32 rows
+  constexpr int BM = 64 * MB;              // 4 row groups x 16 MB rows
   constexpr int BN = 32 * NBW;             // 2 column halves x NBW blocks of 16
   constexpr int VEC = 16 / sizeof(T);
   // LDS row strides of 16 (mod 32) words: the two k-rows an operand read
   // touches in one 32-lane half then fall in disjoint banks
   constexpr int AS = BM + 16;              // A tile, k-major
   constexpr int BS = BN + 16;              // X tile
-  constexpr int A_ELEMS = BM * kBK / kGemmThreads;   // 4 per thread
+  constexpr int A_ELEMS = BM * kBK / kGemmThreads;   // 2 MB per thread
+  static_assert(MB == 2 || MB == 4, "row tile of 128 or 256 rows");
   constexpr int A_VECS = A_ELEMS / VEC;
   constexpr int B_VECS = (kBK * BN / VEC + kGemmThreads - 1) / kGemmThreads;
   constexpr int B_ELEMS = BVEC ? B_VECS * VEC : (kBK * BN + kGemmThreads - 1) / kGemmThreads;
@@ -214,13 +218,13 @@ __device__ __attribute__((always_inline)) inline void gemm_body(
     }
   };
 
-  typename MF::acc_t acc[2][NBW];
+  typename MF::acc_t acc[MB][NBW];
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+  for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = MF::zero();
 
-  const int arow = wm * 32 + (lane & 15);
+  const int arow = wm * 16 * MB + (lane & 15);
   const int bcol = wn * (BN / 2) + (lane & 15);
   if (kbeg < kend) {
     load_tile(kbeg);
@@ -234,11 +238,11 @@ __device__ __attribute__((always_inline)) inline void gemm_body(
       // The operands of step ks + 1 are read from LDS while the MFMAs of
       // step ks issue, and the wave's priority is raised for the MFMA loop
       // so that the co-resident workgroup's loads and stores fill its gaps.
-      T a0[2], a1[2], bb[2][NBW];
+      T aa[2][MB], bb[2][NBW];
       {
         const int kr = (lane >> 4);
-        a0[0] = As[buf][kr][arow];
-        a1[0] = As[buf][kr][arow + 16];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) aa[0][mb] = As[buf][kr][arow + 16 * mb];
 #pragma unroll
         for (int nb = 0; nb < NBW; ++nb) bb[0][nb] = Bs[buf][kr][bcol + nb * 16];
       }
@@ -247,16 +251,15 @@ __device__ __attribute__((always_inline)) inline void gemm_body(
         const int cur = ks & 1, nxt = cur ^ 1;
         if (ks + 1 < kBK / 4) {
           const int kr = (ks + 1) * 4 + (lane >> 4);
-          a0[nxt] = As[buf][kr][arow];
-          a1[nxt] = As[buf][kr][arow + 16];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) aa[nxt][mb] = As[buf][kr][arow + 16 * mb];
 #pragma unroll
           for (int nb = 0; nb < NBW; ++nb) bb[nxt][nb] = Bs[buf][kr][bcol + nb * 16];
         }
 #pragma unroll
-        for (int nb = 0; nb < NBW; ++nb) {
-          acc[0][nb] = MF::mma(a0[cur], bb[cur][nb], acc[0][nb]);
-          acc[1][nb] = MF::mma(a1[cur], bb[cur][nb], acc[1][nb]);
-        }
+        for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = MF::mma(aa[cur][mb], bb[cur][nb], acc[mb][nb]);
         __builtin_amdgcn_sched_barrier(0);
       }
       __builtin_amdgcn_s_setprio(0);
@@ -269,25 +272,25 @@ __device__ __attribute__((always_inline)) inline void gemm_body(
   // ---- epilogue: write the slab (or this split's partial slab) ----
   T* Cs = C + (int64_t)split * cslice;
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+  for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NBW; ++nb) {
       const int col = wn * (BN / 2) + nb * 16 + MF::col(lane);
 #pragma unroll
       for (int r = 0; r < MF::NACC; ++r) {
-        const int row = m0 + wm * 32 + mb * 16 + MF::row(lane, r);
+        const int row = m0 + wm * 16 * MB + mb * 16 + MF::row(lane, r);
         if (row < M && col < nst) Cs[(int64_t)row * ldc + col] = acc[mb][nb][r];
       }
     }
 }
 
-template <typename T, int NBW, bool TRANS, bool AVEC, bool BVEC>
+template <typename T, int NBW, bool TRANS, bool AVEC, bool BVEC, int MB>
 __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(
     const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
     T* __restrict__ C, int64_t ldc, int64_t cslice, int M, int N, int K, int kchunk, int mtiles,
     int nst) {
-  gemm_body<T, NBW, TRANS, AVEC, BVEC>(A, lda, B, ldb, C, ldc, cslice, M, N, K, kchunk, mtiles, nst,
-                                       xcd_remap(blockIdx.x, gridDim.x));
+  gemm_body<T, NBW, TRANS, AVEC, BVEC, MB>(A, lda, B, ldb, C, ldc, cslice, M, N, K, kchunk, mtiles, nst,
+                                           xcd_remap(blockIdx.x, gridDim.x));
 }
 
 struct GemmRecArgs {
@@ -298,18 +301,18 @@ struct GemmRecArgs {
   int M, N, K, kchunk, mtiles, nst;
 };
 
-template <typename T, int NBW, bool TRANS, bool AVEC, bool BVEC>
+template <typename T, int NBW, bool TRANS, bool AVEC, bool BVEC, int MB>
 __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmRecArgs* __restrict__ a,
                                                              const int* __restrict__ start, int count) {
   const int p = group_find(start, count, blockIdx.x);
   const GemmRecArgs g = a[p];
-  gemm_body<T, NBW, TRANS, AVEC, BVEC>((const T*)g.A, g.lda, (const T*)g.B, g.ldb, (T*)g.C, g.ldc, g.cslice, g.M,
-                                       g.N, g.K, g.kchunk, g.mtiles, g.nst, (int)blockIdx.x - start[p]);
+  gemm_body<T, NBW, TRANS, AVEC, BVEC, MB>((const T*)g.A, g.lda, (const T*)g.B, g.ldb, (T*)g.C, g.ldc, g.cslice,
+                                           g.M, g.N, g.K, g.kchunk, g.mtiles, g.nst, (int)blockIdx.x - start[p]);
 }
 
-template <typename T, int NBW, bool TRANS, bool AVEC, bool BVEC>
+template <typename T, int NBW, bool TRANS, bool AVEC, bool BVEC, int MB>
 void gemm_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_grouped<T, NBW, TRANS, AVEC, BVEC>), dim3(blocks), dim3(kGemmThreads), 0, s,
+  hipLaunchKernelGGL((gemm_grouped<T, NBW, TRANS, AVEC, BVEC, MB>), dim3(blocks), dim3(kGemmThreads), 0, s,
                      (const GemmRecArgs*)args, start, count);
 }
 
@@ -407,16 +410,16 @@ static void splitk_dispatch(const T* P, int nsplit, int M, int nst, T* Y, int64_
   }
 }
 
-template <typename T, int NBW, bool TRANS>
+template <typename T, int NBW, bool TRANS, int MB>
 static void launch_nb(const GemmArgs<T>& g, hipStream_t s, int grid, T* C, int64_t ldc,
                       int64_t cslice, int nst) {
 #define RQLP_GEMM_LAUNCH(AV, BV)                                                                                 \
   do {                                                                                                             \
-    if (!record_launch(&gemm_grouped_launch<T, NBW, TRANS, AV, BV>,                                                \
+    if (!record_launch(&gemm_grouped_launch<T, NBW, TRANS, AV, BV, MB>,                                            \
                        GemmRecArgs{g.A, g.B, C, g.lda, g.ldb, ldc, cslice, g.M, g.N, g.K, g.kchunk, g.mtiles, nst}, \
                        (unsigned)grid))                                                                            \
-      hipLaunchKernelGGL((gemm_kernel<T, NBW, TRANS, AV, BV>), dim3(grid), dim3(kGemmThreads), 0, s, g.A, g.lda,    \
-                         g.B, g.ldb, C, ldc, cslice, g.M, g.N, g.K, g.kchunk, g.mtiles, nst);                      \
+      hipLaunchKernelGGL((gemm_kernel<T, NBW, TRANS, AV, BV, MB>), dim3(grid), dim3(kGemmThreads), 0, s, g.A,       \
+                         g.lda, g.B, g.ldb, C, ldc, cslice, g.M, g.N, g.K, g.kchunk, g.mtiles, nst);               \
   } while (0)
   if (g.avec && g.bvec) RQLP_GEMM_LAUNCH(true, true);
   else if (g.avec) RQLP_GEMM_LAUNCH(true, false);
@@ -425,25 +428,37 @@ static void launch_nb(const GemmArgs<T>& g, hipStream_t s, int grid, T* C, int64
 #undef RQLP_GEMM_LAUNCH
 }
 
-template <typename T, bool TRANS>
-static void dispatch_nb(const GemmArgs<T>& g, hipStream_t s, int grid, T* C, int64_t ldc,
-                        int64_t cslice, int nst) {
+template <typename T, bool TRANS, int MB>
+static void dispatch_nb_mb(const GemmArgs<T>& g, hipStream_t s, int grid, T* C, int64_t ldc,
+                           int64_t cslice, int nst) {
   switch (gemm_block_cols<T>(g.N) / 32) {
-    case 1: launch_nb<T, 1, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
-    case 2: launch_nb<T, 2, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
-    case 3: launch_nb<T, 3, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
-    case 4: launch_nb<T, 4, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
-    case 5: launch_nb<T, 5, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
-    case 6: launch_nb<T, 6, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
-    case 7: launch_nb<T, 7, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
-    default: launch_nb<T, 8, TRANS>(g, s, grid, C, ldc, cslice, nst); break;
+    case 1: launch_nb<T, 1, TRANS, MB>(g, s, grid, C, ldc, cslice, nst); break;
+    case 2: launch_nb<T, 2, TRANS, MB>(g, s, grid, C, ldc, cslice, nst); break;
+    case 3: launch_nb<T, 3, TRANS, MB>(g, s, grid, C, ldc, cslice, nst); break;
+    case 4: launch_nb<T, 4, TRANS, MB>(g, s, grid, C, ldc, cslice, nst); break;
+    case 5: launch_nb<T, 5, TRANS, MB>(g, s, grid, C, ldc, cslice, nst); break;
+    case 6: launch_nb<T, 6, TRANS, MB>(g, s, grid, C, ldc, cslice, nst); break;
+    case 7: launch_nb<T, 7, TRANS, MB>(g, s, grid, C, ldc, cslice, nst); break;
+    default: launch_nb<T, 8, TRANS, MB>(g, s, grid, C, ldc, cslice, nst); break;
   }
 }
 
+template <typename T, bool TRANS>
+static void dispatch_nb(const GemmArgs<T>& g, hipStream_t s, int grid, T* C, int64_t ldc,
+                        int64_t cslice, int nst) {
+  if constexpr (sizeof(T) == 4) {
+    if (g.mb == 4) {
+      dispatch_nb_mb<T, TRANS, 4>(g, s, grid, C, ldc, cslice, nst);
+      return;
+    }
+  }
+  dispatch_nb_mb<T, TRANS, 2>(g, s, grid, C, ldc, cslice, nst);
+}
+
 template <typename T>
-int gemm_block_rows() { return 128; }
-template int gemm_block_rows<float>();
-template int gemm_block_rows<double>();
+int gemm_block_rows(int mb) { return 64 * ((sizeof(T) == 4 && mb == 4) ? 4 : 2); }
+template int gemm_block_rows<float>(int);
+template int gemm_block_rows<double>(int);
 
 template <typename T>
 int gemm_block_cols(int N) { return (int)round_up(N, 32); }

@@ -24,13 +24,15 @@ struct GemmArgs {
   int64_t ldb;
   int M, N, K;     // output M x N, reduction K
   int trans;       // 0: Y = A B, 1: Y = A^T B
-  int mtiles;      // ceil(M / gemm_block_rows)
+  int mtiles;      // ceil(M / gemm_block_rows(mb))
   int nsplit;      // split-K count
   int kchunk;      // reduction length per split (multiple of 16)
   bool avec;       // A rows 16-byte aligned: vector loads
   bool bvec;       // X rows padded to the tile width with zeros: vector loads
+  int mb = 2;      // row tile: 16 mb rows per wave, 64 mb per workgroup (4: float only)
 };
-template <typename T> int gemm_block_rows();
+// Rows of one workgroup's slab for row-tile parameter mb (128 or 256).
+template <typename T> int gemm_block_rows(int mb);
 template <typename T> int gemm_block_cols(int N);
 // Y (M x nst, ldy) = op(A) B; columns [N, nst) of Y are written as zero.
 // P: partial buffer of nsplit * M * nst elements (unused when nsplit == 1).

@@ -56,16 +56,18 @@ struct rqlp_ctx {
   // Grouped batches: every problem's launch sequence is recorded once (host
   // only), then replayed phase by phase as grouped launches whose argument
   // tables live in device memory; plans are cached per batch descriptor.
-  struct GroupedLaunch { GroupedFn fn; size_t args_off, start_off; int count; unsigned blocks; };
+  struct GroupedLaunch { GroupedFn fn; size_t args_off, start_off; int count; unsigned blocks; int lane; };
   struct GroupedPlan {
     std::vector<uint8_t> key;
     void* dev = nullptr;  // argument tables and block offsets
     std::vector<GroupedLaunch> launches;
+    int lanes = 1;  // streams the launches are spread over (lane 0: the caller's)
   };
   std::vector<GroupedPlan> plans;
   bool lockstep = true;  // grouped batches (else every problem on its lane stream)
-  // autotuned split-K counts: (element bytes, trans, M, N, K) -> nsplit
-  std::map<std::tuple<int, int, int, int, int>, int> plan;
+  // autotuned product plans: (element bytes, trans, M, N, K) -> (split-K
+  // count, row tile parameter mb)
+  std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> plan;
 };
 
 namespace {
@@ -137,8 +139,8 @@ GemmArgs<T> plan_gemm(int trans, const T* A, int64_t lda, const T* B, int64_t ld
   g.N = N;
   g.K = K;
   g.trans = trans;
-  const int bm = gemm_block_rows<T>();
-  g.mtiles = (int)ceil_div(M, bm);
+  g.mb = 2;
+  g.mtiles = (int)ceil_div(M, gemm_block_rows<T>(g.mb));
   // Resident workgroup slots: two 4-wave workgroups per CU (register
   // limited), 256 CUs.  Split K so that all slabs x splits fit in one round.
   const int target = std::max(1, env_int("RQLP_GEMM_TARGET_WGS", 512));
@@ -162,6 +164,13 @@ GemmArgs<T> plan_gemm(int trans, const T* A, int64_t lda, const T* B, int64_t ld
 int splitk_cap(int M, int K) {
   const int64_t mt = ceil_div(M, 128);
   return (int)std::max<int64_t>(1, std::min<int64_t>(1024 / mt, ceil_div(std::max(K, 1), 256)));
+}
+
+// Row tile of 128 (mb = 2) or, for float, 256 (mb = 4) rows per workgroup.
+template <typename T>
+void set_tile(GemmArgs<T>& g, int mb) {
+  g.mb = (sizeof(T) == 4 && mb == 4) ? 4 : 2;
+  g.mtiles = (int)ceil_div(g.M, gemm_block_rows<T>(g.mb));
 }
 
 // Split the reduction into (about) ns parts of whole 16-element chunks.
@@ -323,7 +332,10 @@ rqlp_status gemm(rqlp_ctx* c, int trans, const T* A, int64_t lda, int64_t m, int
   const int M = (int)(trans ? n : m), K = (int)(trans ? m : n);
   GemmArgs<T> g = plan_gemm<T>(trans, A, lda, X, ldx, M, d, K);
   auto it = c->plan.find(std::make_tuple((int)sizeof(T), trans, M, d, K));
-  if (it != c->plan.end()) set_split(g, std::min(it->second, splitk_cap(M, K)));
+  if (it != c->plan.end()) {
+    set_tile(g, it->second.second);
+    set_split(g, std::min(it->second.first, splitk_cap(M, K)));
+  }
   // internal operands have ld = dp and zero padding columns: vector loads
   const int vec = 16 / (int)sizeof(T);
   g.bvec = padded_x && ldx == gemm_block_cols<T>(d) && ldx % vec == 0 && (((uintptr_t)X & 15) == 0);
@@ -606,13 +618,20 @@ LaunchRecorder*& recorder_slot() {
 
 // Record every problem's launch sequence (host only) and lay the launches
 // out as grouped launches: phase by phase (the factorizations form phases of
-// their own), position by position within a phase, one grouped launch per
-// kernel variant, problems in batch order.  Each problem's own launches keep
-// their order, so its results are the bits of its solo run.  The argument
-// tables and block offsets are uploaded once into device memory.
+// their own), position by position within a phase, problems in batch order.
+// Each problem's own launches keep their order, so its results are the bits
+// of its solo run.  The argument tables and block offsets are uploaded once
+// into device memory.
+// With nlanes == 1 every position takes one grouped launch per kernel
+// variant, all on one stream.  With nlanes > 1 the problems are first
+// split into sub-batches of identical launch sequences (the variants follow
+// from d, alignment and the split-K plans), each sub-batch takes one grouped
+// launch per position, and the sub-batches are spread over the lanes
+// (largest first onto the least loaded): launches of different variants then
+// run side by side instead of one after another.
 rqlp_status layout_plan(rqlp_ctx* c, int count, const rqlp_problem* probs, const size_t* offs,
                         rqlp_precision prec, char* base, hipStream_t s, rqlp_ctx::GroupedPlan* plan,
-                        std::vector<uint8_t>& table) {
+                        std::vector<uint8_t>& table, int nlanes = 1) {
   std::vector<LaunchRecorder> recs((size_t)count);
   const uint32_t timing = c->timing;
   c->timing = 0;
@@ -653,6 +672,72 @@ rqlp_status layout_plan(rqlp_ctx* c, int count, const rqlp_problem* probs, const
     return o;
   };
   plan->launches.clear();
+  plan->lanes = 1;
+  // one grouped launch of the given records (one kernel, same position)
+  auto emit = [&](const std::vector<const LaunchRec*>& items, int lane) -> rqlp_status {
+    const size_t asz = items[0]->size;
+    const size_t aoff = reserve(asz * items.size());
+    const size_t soff = reserve(sizeof(int) * (items.size() + 1));
+    int total = 0;
+    for (size_t t = 0; t < items.size(); ++t) {
+      std::memcpy(table.data() + aoff + t * asz, items[t]->args, asz);
+      std::memcpy(table.data() + soff + t * sizeof(int), &total, sizeof(int));
+      if ((int64_t)total + items[t]->blocks > INT32_MAX) return RQLP_ERR_UNSUPPORTED;
+      total += (int)items[t]->blocks;
+    }
+    std::memcpy(table.data() + soff + items.size() * sizeof(int), &total, sizeof(int));
+    plan->launches.push_back({items[0]->fn, aoff, soff, (int)items.size(), (unsigned)total, lane});
+    return RQLP_OK;
+  };
+  if (nlanes > 1) {
+    // sub-batches: problems with the same (kernel, non-empty) sequence
+    std::vector<std::vector<int>> subs;
+    std::vector<int> sub_of((size_t)count, -1);
+    auto same_seq = [&](int a, int b) {
+      const LaunchRecorder& x = recs[(size_t)a];
+      const LaunchRecorder& y = recs[(size_t)b];
+      if (x.seq.size() != y.seq.size()) return false;
+      for (size_t k = 0; k < x.seq.size(); ++k)
+        if (x.seq[k].fn != y.seq[k].fn || (x.seq[k].blocks > 0) != (y.seq[k].blocks > 0)) return false;
+      return true;
+    };
+    for (int i = 0; i < count; ++i) {
+      for (size_t b = 0; b < subs.size() && sub_of[(size_t)i] < 0; ++b)
+        if (same_seq(subs[b][0], i)) sub_of[(size_t)i] = (int)b;
+      if (sub_of[(size_t)i] < 0) {
+        sub_of[(size_t)i] = (int)subs.size();
+        subs.emplace_back();
+      }
+      subs[(size_t)sub_of[(size_t)i]].push_back(i);
+    }
+    // work estimate of a sub-batch: its workgroups over all launches
+    std::vector<std::pair<double, int>> order;
+    for (size_t b = 0; b < subs.size(); ++b) {
+      double w = 0.0;
+      for (int i : subs[b])
+        for (const auto& x : recs[(size_t)i].seq) w += x.blocks;
+      order.push_back({w, (int)b});
+    }
+    std::sort(order.begin(), order.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    const int nl = std::min<int>(nlanes, (int)subs.size());
+    std::vector<double> load((size_t)nl, 0.0);
+    for (const auto& ob : order) {
+      const int lane = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[(size_t)lane] += ob.first;
+      const std::vector<int>& mem = subs[(size_t)ob.second];
+      const LaunchRecorder& r0 = recs[(size_t)mem[0]];
+      for (size_t k = 0; k < r0.seq.size(); ++k) {
+        if (r0.seq[k].blocks == 0) continue;
+        std::vector<const LaunchRec*> items;
+        for (int i : mem) items.push_back(&recs[(size_t)i].seq[k]);
+        const rqlp_status es = emit(items, lane);
+        if (es != RQLP_OK) return es;
+      }
+    }
+    plan->lanes = nl;
+    if (table.empty()) table.resize(16);
+    return RQLP_OK;
+  }
   for (int ph = 0; ph < nphase; ++ph) {
     for (size_t j = 0; j < maxlen; ++j) {
       // kernel variants at this position, in order of first appearance
@@ -671,18 +756,8 @@ rqlp_status layout_plan(rqlp_ctx* c, int count, const rqlp_problem* probs, const
           const LaunchRec& x = recs[(size_t)i].seq[sp.first + j];
           if (x.fn == fn && x.blocks > 0) items.push_back(&x);
         }
-        const size_t asz = items[0]->size;
-        const size_t aoff = reserve(asz * items.size());
-        const size_t soff = reserve(sizeof(int) * (items.size() + 1));
-        int total = 0;
-        for (size_t t = 0; t < items.size(); ++t) {
-          std::memcpy(table.data() + aoff + t * asz, items[t]->args, asz);
-          std::memcpy(table.data() + soff + t * sizeof(int), &total, sizeof(int));
-          if ((int64_t)total + items[t]->blocks > INT32_MAX) return RQLP_ERR_UNSUPPORTED;
-          total += (int)items[t]->blocks;
-        }
-        std::memcpy(table.data() + soff + items.size() * sizeof(int), &total, sizeof(int));
-        plan->launches.push_back({fn, aoff, soff, (int)items.size(), (unsigned)total});
+        const rqlp_status es = emit(items, 0);
+        if (es != RQLP_OK) return es;
       }
     }
   }
@@ -694,7 +769,7 @@ rqlp_status layout_plan(rqlp_ctx* c, int count, const rqlp_problem* probs, const
 rqlp_status build_plan(rqlp_ctx* c, int count, const rqlp_problem* probs, rqlp_precision prec, char* base,
                        hipStream_t s, rqlp_ctx::GroupedPlan* plan) {
   std::vector<uint8_t> table;
-  rqlp_status st = layout_plan(c, count, probs, nullptr, prec, base, s, plan, table);
+  rqlp_status st = layout_plan(c, count, probs, nullptr, prec, base, s, plan, table, rqlp_ctx::kLanes);
   if (st != RQLP_OK) return st;
   if (hipMalloc(&plan->dev, table.size()) != hipSuccess) {
     plan->dev = nullptr;
@@ -704,13 +779,23 @@ rqlp_status build_plan(rqlp_ctx* c, int count, const rqlp_problem* probs, rqlp_p
   return RQLP_OK;
 }
 
-// The grouped launches of a plan on one stream (graph-capturable: kernel
-// launches only).
+// The grouped launches of a plan: lane 0 on `s`, the other lanes on the
+// context's lane streams, forked from and joined back into `s`.
 rqlp_status launch_plan(rqlp_ctx* c, const rqlp_ctx::GroupedPlan& plan, hipStream_t s) {
   HIP_TRY(launch_info_reset(c->info, s));
+  const int nl = std::min(plan.lanes, (int)rqlp_ctx::kLanes);
+  if (nl > 1) {
+    HIP_TRY(hipEventRecord(c->fork, s));
+    for (int l = 1; l < nl; ++l) HIP_TRY(hipStreamWaitEvent(c->lanes[l], c->fork, 0));
+  }
   const char* dev = (const char*)plan.dev;
-  for (const auto& L : plan.launches) L.fn(dev + L.args_off, (const int*)(dev + L.start_off), L.count, L.blocks, s);
+  for (const auto& L : plan.launches)
+    L.fn(dev + L.args_off, (const int*)(dev + L.start_off), L.count, L.blocks, L.lane == 0 ? s : c->lanes[L.lane]);
   HIP_TRY(hipGetLastError());
+  for (int l = 1; l < nl; ++l) {
+    HIP_TRY(hipEventRecord(c->join[l], c->lanes[l]));
+    HIP_TRY(hipStreamWaitEvent(s, c->join[l], 0));
+  }
   return RQLP_OK;
 }
 
@@ -776,9 +861,10 @@ rqlp_status svd_like(rqlp_ctx* c, const SvdLayout& Ly, char* b, int64_t m, int64
 
 // ---- autotuner --------------------------------------------------------------
 
-// Time every split-K candidate of one product shape (Y = op(A) X with d
-// columns, as the decomposition issues it: X and Y with ld dp, zero padding)
-// and keep the fastest in the context's plan table.  Synchronizes.
+// Time every candidate plan of one product shape (Y = op(A) X with d
+// columns, as the decomposition issues it: X and Y with ld dp, zero padding):
+// each row tile (128 rows; for float also 256) with each split-K count, and
+// keep the fastest in the context's plan table.  Synchronizes.
 template <typename T>
 rqlp_status autotune_product(rqlp_ctx* c, int trans, const T* A, int64_t lda, int64_t m, int64_t n, int d, T* X,
                              T* Y, T* P, hipStream_t s, int* best_out) {
@@ -797,12 +883,20 @@ rqlp_status autotune_product(rqlp_ctx* c, int trans, const T* A, int64_t lda, in
     return RQLP_ERR_HIP;
   }
   float best_ms = 0.f;
-  int best = g0.nsplit, best_eff = -1;
+  int best = g0.nsplit, best_mb = g0.mb;
+  bool any = false;
   rqlp_status st = RQLP_OK;
+  std::vector<std::pair<int, int>> tried;
+  std::vector<int> tiles = {2};
+  if (sizeof(T) == 4) tiles.push_back(4);
+  for (int mb : tiles)
   for (int ns : cand) {
     GemmArgs<T> g = g0;
+    set_tile(g, mb);
     set_split(g, ns);
-    if (g.nsplit == best_eff) continue;  // the same plan as one already timed
+    const std::pair<int, int> key{g.mb, g.nsplit};
+    if (std::find(tried.begin(), tried.end(), key) != tried.end()) continue;  // a plan already timed
+    tried.push_back(key);
     float ms = 0.f, t = 0.f;
     bool ok = true;
     for (int r = 0; r < 7 && ok; ++r) {  // two warm-ups, then the fastest of five
@@ -812,16 +906,17 @@ rqlp_status autotune_product(rqlp_ctx* c, int trans, const T* A, int64_t lda, in
       if (r >= 2) ms = (r == 2) ? t : std::min(ms, t);
     }
     if (!ok) { st = RQLP_ERR_HIP; break; }
-    if (best_eff < 0 || ms < best_ms) {
+    if (!any || ms < best_ms) {
       best_ms = ms;
       best = g.nsplit;
-      best_eff = g.nsplit;
+      best_mb = g.mb;
+      any = true;
     }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (st != RQLP_OK) return st;
-  c->plan[std::make_tuple((int)sizeof(T), trans, M, d, K)] = best;
+  c->plan[std::make_tuple((int)sizeof(T), trans, M, d, K)] = {best, best_mb};
   if (best_out) *best_out = best;
   return RQLP_OK;
 }
@@ -1117,11 +1212,11 @@ rqlp_status rqlp_autotune_save(rqlp_ctx* c, const char* path) {
   if (!c || !path) return RQLP_ERR_INVALID_ARG;
   std::ofstream f(path);
   if (!f) return RQLP_ERR_INVALID_ARG;
-  f << "rqlp-plans 1\n";
+  f << "rqlp-plans 2\n";
   for (const auto& e : c->plan) {
     const auto& k = e.first;
     f << "gemm " << std::get<0>(k) << ' ' << std::get<1>(k) << ' ' << std::get<2>(k) << ' ' << std::get<3>(k) << ' '
-      << std::get<4>(k) << ' ' << e.second << "\n";
+      << std::get<4>(k) << ' ' << e.second.first << ' ' << e.second.second << "\n";
   }
   return f.good() ? RQLP_OK : RQLP_ERR_INVALID_ARG;
 }
@@ -1132,15 +1227,16 @@ rqlp_status rqlp_autotune_load(rqlp_ctx* c, const char* path) {
   if (!f) return RQLP_ERR_INVALID_ARG;
   std::string tag;
   int version = 0;
-  if (!(f >> tag >> version) || tag != "rqlp-plans" || version != 1) return RQLP_ERR_INVALID_ARG;
-  std::map<std::tuple<int, int, int, int, int>, int> plan;
+  if (!(f >> tag >> version) || tag != "rqlp-plans" || (version != 1 && version != 2)) return RQLP_ERR_INVALID_ARG;
+  std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> plan;
   std::string kind;
   while (f >> kind) {
-    int es, trans, M, N, K, ns;
-    if (kind != "gemm" || !(f >> es >> trans >> M >> N >> K >> ns) || (es != 4 && es != 8) ||
-        (trans != 0 && trans != 1) || M < 1 || N < 1 || K < 1 || ns < 1)
+    int es, trans, M, N, K, ns, mb = 2;  // version 1 files hold no row tile (128 rows)
+    if (kind != "gemm" || !(f >> es >> trans >> M >> N >> K >> ns) || (version == 2 && !(f >> mb)) ||
+        (es != 4 && es != 8) || (trans != 0 && trans != 1) || M < 1 || N < 1 || K < 1 || ns < 1 ||
+        (mb != 2 && mb != 4) || (mb == 4 && es != 4))
       return RQLP_ERR_INVALID_ARG;
-    plan[std::make_tuple(es, trans, M, N, K)] = ns;
+    plan[std::make_tuple(es, trans, M, N, K)] = {ns, mb};
   }
   for (const auto& e : plan) c->plan[e.first] = e.second;
   return RQLP_OK;

@@ -1,6 +1,7 @@
-"""The split-K autotuner (rqlp_autotune): tuned plans keep parity with the
-oracle, are reproducible bit for bit through save / load, and clearing the
-table returns the default plans."""
+"""The product autotuner (rqlp_autotune: row tile and split-K count): tuned
+plans keep parity with the oracle, are reproducible bit for bit through
+save / load, the row tile leaves the bits unchanged, and clearing the table
+returns the default plans."""
 import numpy as np
 import pytest
 import torch
@@ -37,7 +38,7 @@ def test_tuned_plans_keep_parity_and_roundtrip(gpu_lib, tmp_path, m, n, k, p, dt
     path = tmp_path / "plans.txt"
     ctx.autotune_save(path)
     text = path.read_text().split("\n")
-    assert text[0] == "rqlp-plans 1" and sum(1 for t in text if t.startswith("gemm ")) == 2
+    assert text[0] == "rqlp-plans 2" and sum(1 for t in text if t.startswith("gemm ")) == 2
     ctx2 = gpu_lib.Context(0)
     ctx2.autotune_load(path)
     assert ctx2.autotune_count() == 2
@@ -64,3 +65,47 @@ def test_malformed_plan_file_is_rejected(gpu_lib, tmp_path):
     bad.write_text("something else\n")
     with pytest.raises(gpu_lib.RqlpError):
         ctx.autotune_load(bad)
+
+
+def test_row_tile_keeps_bits(gpu_lib, tmp_path):
+    """The same split counts with the other row tile (128 <-> 256 rows per
+    workgroup) give the same bits: each output's summation order depends on
+    the split only.  Version 1 plan files (no row tile) still load."""
+    announce("autotune row tile")
+    m, n, k, p, q, seed = 2600, 1900, 90, 10, 1, 5
+    A = _matrix(m, n, torch.float32)
+    ctx = gpu_lib.Context(0)
+    ctx.autotune(A, k + p)
+    path = tmp_path / "plans.txt"
+    ctx.autotune_save(path)
+    tuned = [x.clone() for x in gpu_lib.decompose(A, k, p, q, seed=seed, ctx=ctx)]
+    lines = path.read_text().strip().split("\n")
+    for mb in ("2", "4"):
+        flipped = [lines[0]] + [" ".join(t.split()[:-1] + [mb]) for t in lines[1:]]
+        path.write_text("\n".join(flipped) + "\n")
+        c2 = gpu_lib.Context(0)
+        c2.autotune_load(path)
+        out = gpu_lib.decompose(A, k, p, q, seed=seed, ctx=c2)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(tuned, out)), mb
+    A64 = to_np(A)
+    Qo, Lo, Vo = oracle.ruqlp(A64, k, p, q, seed, omega_dtype="f32")
+    assert recon_diff(*(to_np(x) for x in tuned), Qo, Lo, Vo) / np.linalg.norm(A64) <= 1e-5
+    v1 = ["rqlp-plans 1"] + [" ".join(t.split()[:-1]) for t in lines[1:]]
+    path.write_text("\n".join(v1) + "\n")
+    c3 = gpu_lib.Context(0)
+    c3.autotune_load(path)
+    assert c3.autotune_count() == 2
+    out = gpu_lib.decompose(A, k, p, q, seed=seed, ctx=c3)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(tuned, out))
+
+
+def test_float64_rejects_wide_row_tile(gpu_lib, tmp_path):
+    announce("autotune float64 row tile")
+    bad = tmp_path / "bad64.txt"
+    bad.write_text("rqlp-plans 2\ngemm 8 0 1000 30 800 2 4\n")
+    ctx = gpu_lib.Context(0)
+    with pytest.raises(gpu_lib.RqlpError):
+        ctx.autotune_load(bad)
+    assert ctx.autotune_count() == 0
