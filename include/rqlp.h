@@ -209,14 +209,14 @@ rqlp_status rqlp_csr_transpose(rqlp_ctx* ctx, const int32_t* rowptr, const int32
                                void* vals_t, void* workspace, size_t ws_bytes, void* stream);
 
 /* RU-QLP in the paper's own orientation (Algorithm 1 as printed, with
- * Algorithm 2 for P-bar): Phi = randn(m, d) (the same generator and key as
- * Omega, m x d), P-bar = orth(A^T Phi) refined by q power steps
- * (orthonormalizing every half step), [Q, R] = qr(A P-bar), [P-tilde,
- * R-tilde] = qr(R^T), P = P-bar P-tilde, L = R-tilde^T, so that
- * A ~ Q L P^T = A P-bar P-bar^T.  The unpivoted QRs are the same CholeskyQR2
- * as elsewhere (the d x d QR of R^T included).  Arguments as for
- * rqlp_decompose with P (n x d, leading dimension d) in place of V;
- * RQLP_FP64 or RQLP_FP32, dense A. */
+ * Algorithm 2 for P-bar), computed as rqlp_decompose's method on A^T (its
+ * Gaussian is then m x d, drawn with the same generator and key; its basis
+ * is P-bar and its right-hand factor the paper's Q) followed by the d x d
+ * unpivoted QR of its L, which gives P-tilde and R-tilde: P = P-bar P-tilde,
+ * L = R-tilde^T, so that A ~ Q L P^T = A P-bar P-bar^T.  The unpivoted QRs
+ * are the same CholeskyQR2 as elsewhere.  Arguments as for rqlp_decompose
+ * with P (n x d, leading dimension d) in place of V; RQLP_FP64 or
+ * RQLP_FP32, dense A. */
 size_t rqlp_workspace_size_paper(int64_t m, int64_t n, int k, int p, int q, rqlp_precision prec);
 rqlp_status rqlp_decompose_paper(rqlp_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda, int k, int p,
                                  int q, rqlp_precision prec, uint64_t seed, void* Q, void* L, void* P,

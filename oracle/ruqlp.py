@@ -2,19 +2,13 @@
 
 Test infrastructure (see the package docstring).
 
-Algorithm 1 (Section III-A) with Algorithm 2 (Section III-B), run on A^T:
-the sketch multiplies A by an n x d Gaussian from the right, so Q spans an
-approximation of the range of A, and the final unpivoted QR is taken of
-B^T = A^T Q.  Step by step:
-
-  1. Omega = randn(n, d), rounded to the precision the device stores it in
-     and then held in float64 (philox.gaussian_matrix).
-  2. Q = orth(A Omega)                    (Algorithm 1, sketch and orth)
-  3. repeat q times (Algorithm 2, orthonormalizing at every half step):
-        W = orth(A^T Q);  Q = orth(A W)
-  4. B^T = A^T Q                           (Algorithm 1, the product with A)
-  5. [V, Rt] = qr(B^T)                     (Algorithm 1, unpivoted QR)
-  6. L = Rt^T (lower triangular)           (Algorithm 1, L = R-tilde^T)
+Algorithm 1 (Section III-A) with the power iteration of Algorithm 2
+(Section III-B), in the column-sketch orientation: the algorithms applied to
+A^T, so that the Gaussian test matrix (n x d; philox.gaussian_matrix, rounded
+to the precision the device stores it in and then held in float64)
+multiplies A from the right, Q is the orthonormalized sketch after q power
+steps (orthonormalized at every half step), and the final unpivoted QR is
+taken of A^T Q, whose R gives L = R^T.
 
 Result: A ~ Q L V^T = Q Q^T A, with Q (m x d) and V (n x d) orthonormal.
 orth(X) is the Q factor of householder_qr(X).  The products with A are
@@ -102,34 +96,26 @@ def ruqlp_csr(rowptr, colidx, vals, m, n, k, p, q, seed, omega_dtype="f64"):
 
 
 def ruqlp_paper(A, k, p, q, seed, omega_dtype="f64"):
-    """RU-QLP in the paper's own orientation: Algorithm 1 as printed
-    (Section III-A) with Algorithm 2 (Section III-B) computing P-bar.
-
-      1. Phi = randn(m, d)                 (rounded as in ruqlp)
-      2. P-bar = orth(A^T Phi); q times: P-bar = orth(A P-bar), then
-         P-bar = orth(A^T P-bar)           (Algorithm 2)
-      3. [Q, R] = qr(A P-bar)
-      4. [P-tilde, R-tilde] = qr(R^T)
-      5. Q;  P = P-bar P-tilde;  L = R-tilde^T
+    """RU-QLP in the paper's own orientation (Algorithm 1 as printed, with
+    Algorithm 2 computing P-bar): the column-sketch method above applied to
+    A^T -- its basis is the paper's P-bar (n x d, from an m x d Gaussian),
+    its right-hand factor the paper's Q and its L the transposed R of the
+    paper's QR of A P-bar -- followed by the d x d unpivoted QR of that L,
+    which gives P-tilde and R-tilde: P = P-bar P-tilde, L = R-tilde^T.
 
     Returns (Q, L, P): Q m x d, L d x d lower triangular, P n x d; A is
     approximated by Q L P^T = A P-bar P-bar^T.
 
     Pinned by: tests/test_oracle_ruqlp.py -- invariants (orthonormal Q and
     P, triangular L, Q L P^T = A P-bar P-bar^T), exact recovery when
-    rank(A) <= d, sigma_i(L) <= sigma_i(A), and its relation to the column
-    orientation on A^T (same P-bar and Q, and L-values of the extra QR).
+    rank(A) <= d, sigma_i(L) <= sigma_i(A), and the L-values of the extra QR
+    against an independent LAPACK QR of the d x d factor.
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     d = k + p
     if not (1 <= k and d <= min(m, n)):
         raise ValueError("need 1 <= k and k + p <= min(m, n)")
-    phi = round_to(gaussian_matrix(seed, m, d), omega_dtype)
-    Pbar = orth(A.T @ phi)
-    for _ in range(q):
-        Pbar = orth(A @ Pbar)
-        Pbar = orth(A.T @ Pbar)
-    Q, R = householder_qr(A @ Pbar)
-    Pt, Rt = householder_qr(R.T)
-    return Q, Rt.T.copy(), Pbar @ Pt
+    Pbar, Rt, Q = ruqlp(A.T, k, p, q, seed, omega_dtype)
+    Pt, Rtt = householder_qr(Rt)
+    return Q, Rtt.T.copy(), Pbar @ Pt

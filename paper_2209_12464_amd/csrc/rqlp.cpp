@@ -355,10 +355,14 @@ rqlp_status check_common(int64_t m, int64_t n, int k, int p, int q, rqlp_precisi
   return RQLP_OK;
 }
 
-// The method's launch sequence for dense (mulA = GEMM) or CSR (mulA = SpMM) A.
+// The method's launch sequence for dense (mulA = GEMM) or CSR (mulA = SpMM)
+// A: Algorithm 1 with Algorithm 2 in the column-sketch orientation.  Q (ld d)
+// may be null (the basis then stays in the internal Q buffer, ld dp); L is
+// written with leading dimension ldl (d when ldl <= 0).
 template <typename T, typename MulA, typename MulAt>
 rqlp_status run_method(rqlp_ctx* c, char* base, const Layout& Lo, int64_t m, int64_t n, int k, int p,
-                       int q, uint64_t seed, T* Q, T* Lout, T* V, hipStream_t s, MulA mulA, MulAt mulAt) {
+                       int q, uint64_t seed, T* Q, T* Lout, T* V, hipStream_t s, MulA mulA, MulAt mulAt,
+                       int ldl = 0) {
   const int d = k + p, dp = padded_d(d);
   T* om = (T*)(base + Lo.om);
   T* yb = (T*)(base + Lo.yb);
@@ -392,24 +396,25 @@ rqlp_status run_method(rqlp_ctx* c, char* base, const Layout& Lo, int64_t m, int
   // B^T = A^T Q; [V, R] = qr(B^T); L = R^T
   if ((st = mulAt(qi, yb)) != RQLP_OK) return st;
   if ((st = cholqr2<T>(c, yb, dp, n, d, b, V, d, d, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
-  HIP_TRY(launch_form_l<T>(b.r2, b.r1, b.flags, d, dp, Lout, d, s));
+  HIP_TRY(launch_form_l<T>(b.r2, b.r1, b.flags, d, dp, Lout, ldl > 0 ? ldl : d, s));
   return RQLP_OK;
 }
 
 // The paper's own orientation (Algorithm 1 as printed, with Algorithm 2):
-// Phi = randn(m, d); P-bar = orth(A^T Phi), q times P-bar = orth(A P-bar),
-// P-bar = orth(A^T P-bar); [Q, R] = qr(A P-bar); [P-tilde, R-tilde] =
-// qr(R^T); P = P-bar P-tilde; L = R-tilde^T.  Lo is the layout with m and n
-// exchanged, so its "Omega" buffer is m x dp (Phi, and the m x d bases of
-// the power steps) and its "Q" buffer n x dp (P-bar).
+// the column-sketch method applied to A^T (its Gaussian is then m x d, its
+// basis the paper's P-bar, its right factor the paper's Q and its L the
+// transposed R of the paper's QR), followed by the d x d QR of that L and
+// P = P-bar P-tilde.  Lo is the layout of the n x m problem.
 template <typename T, typename MulA, typename MulAt>
 rqlp_status run_method_paper(rqlp_ctx* c, char* base, const Layout& Lo, int64_t m, int64_t n, int k, int p, int q,
                              uint64_t seed, T* Q, T* Lout, T* P, hipStream_t s, MulA mulA, MulAt mulAt) {
   const int d = k + p, dp = padded_d(d);
-  T* phi = (T*)(base + Lo.om);
-  T* yb = (T*)(base + Lo.yb);
-  T* pb = (T*)(base + Lo.qi);
+  T* rt = (T*)(base + Lo.om);  // R^T (d x dp), after the method on A^T
+  T* pt = (T*)(base + Lo.yb);  // P-tilde (d x dp)
+  T* pb = (T*)(base + Lo.qi);  // P-bar (n x dp), the basis of the method on A^T
   T* part = (T*)(base + Lo.part);
+  rqlp_status st = run_method<T>(c, base, Lo, n, m, k, p, q, seed, nullptr, rt, Q, s, mulAt, mulA, dp);
+  if (st != RQLP_OK) return st;
   Bufs b;
   b.q1 = (double*)(base + Lo.q1);
   b.gp = (double*)(base + Lo.gp);
@@ -420,27 +425,10 @@ rqlp_status run_method_paper(rqlp_ctx* c, char* base, const Layout& Lo, int64_t 
   b.flags = (int32_t*)(base + Lo.flags);
   b.xf = (double*)(base + Lo.xf);
   b.esq = (double*)(base + Lo.esq);
-  rqlp_status st;
-  if (c->reset_info) HIP_TRY(launch_info_reset(c->info, s));
-  HIP_TRY(launch_gaussian<T>(seed, kSketchKey1, m, d, phi, dp, s));
-  if ((st = mulAt(phi, yb)) != RQLP_OK) return st;  // A^T Phi (n x dp)
-  int oi = 1;
-  if ((st = cholqr2<T>(c, yb, dp, n, d, b, pb, dp, dp, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
-  for (int it = 1; it <= q; ++it) {
-    if ((st = mulA(pb, yb)) != RQLP_OK) return st;  // A P-bar (m x dp)
-    if ((st = cholqr2<T>(c, yb, dp, m, d, b, phi, dp, dp, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
-    if ((st = mulAt(phi, yb)) != RQLP_OK) return st;  // A^T P-bar (n x dp)
-    if ((st = cholqr2<T>(c, yb, dp, n, d, b, pb, dp, dp, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
-  }
-  // [Q, R] = qr(A P-bar); R^T (lower, d x d) goes to the Phi buffer
-  if ((st = mulA(pb, yb)) != RQLP_OK) return st;
-  if ((st = cholqr2<T>(c, yb, dp, m, d, b, Q, d, d, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
-  HIP_TRY(launch_form_l<T>(b.r2, b.r1, b.flags, d, dp, phi, dp, s));
-  // [P-tilde, R-tilde] = qr(R^T): P-tilde (d x dp, zero padding columns) into yb; L = R-tilde^T
-  if ((st = cholqr2<T>(c, phi, dp, d, d, b, yb, dp, dp, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
+  // [P-tilde, R-tilde] = qr(R^T) (the QR after the 2q + 2 of the method); L = R-tilde^T
+  if ((st = cholqr2<T>(c, rt, dp, d, d, b, pt, dp, dp, nullptr, 0, 0, seed, 2 * q + 3, s)) != RQLP_OK) return st;
   HIP_TRY(launch_form_l<T>(b.r2, b.r1, b.flags, d, dp, Lout, d, s));
-  // P = P-bar P-tilde (n x d)
-  return gemm<T>(c, 0, pb, dp, n, d, yb, dp, d, P, d, d, part, s, true);
+  return gemm<T>(c, 0, pb, dp, n, d, pt, dp, d, P, d, d, part, s, true);
 }
 
 template <typename T>

@@ -180,7 +180,7 @@ def test_paper_orientation_invariants(m, n, k, p, q):
 def test_paper_orientation_is_column_orientation_of_transpose():
     """The paper's P-bar, Q and R are the column orientation's Q, V and L^T
     on A^T with the same Gaussian (m x d): the extra d x d QR only rotates
-    P and re-triangularizes L."""
+    P and re-triangularizes L (checked with LAPACK's QR of the d x d factor)."""
     m, n, k, p, q = 150, 110, 12, 4, 1
     sigma = workloads.spectrum("geometric", min(m, n), rho=0.9)
     A, _, _, _ = workloads.dense_from_spectrum(m, n, sigma, seed=5, trunc=0.0)
@@ -201,3 +201,33 @@ def test_paper_orientation_exact_recovery(rank):
     A = rng.standard_normal((80, rank)) @ rng.standard_normal((rank, 60))
     Q, L, P = oracle.ruqlp_paper(A, 8, 2, 0, seed=1)
     assert np.linalg.norm(Q @ L @ P.T - A) < 1e-12 * np.linalg.norm(A)
+
+
+def _lapack_orth(X):
+    """Q of LAPACK's QR with diag(R) >= 0 (independent of the oracle's QR)."""
+    Qx, Rx = np.linalg.qr(X)
+    sgn = np.where(np.diag(Rx) < 0, -1.0, 1.0)
+    return Qx * sgn, Rx * sgn[:, None]
+
+
+@pytest.mark.parametrize("q", [0, 2])
+def test_paper_orientation_direct_steps(q):
+    """The paper orientation taken directly in its own terms -- an m x d
+    Gaussian, P-bar from A^T times it with power steps, QR of A P-bar, QR of
+    the transposed R -- with LAPACK's QR in every step, gives the oracle's
+    Q, L and P."""
+    m, n, k, p = 130, 100, 10, 4
+    d = k + p
+    sigma = workloads.spectrum("geometric", min(m, n), rho=0.88)
+    A, _, _, _ = workloads.dense_from_spectrum(m, n, sigma, seed=17, trunc=0.0)
+    phi = oracle.gaussian_matrix(21, m, d)
+    Pbar, _ = _lapack_orth(A.T @ phi)
+    for _ in range(q):
+        Pbar, _ = _lapack_orth(A @ Pbar)
+        Pbar, _ = _lapack_orth(A.T @ Pbar)
+    Qd, R = _lapack_orth(A @ Pbar)
+    Pt, Rt = _lapack_orth(R.T)
+    Q, L, P = oracle.ruqlp_paper(A, k, p, q, seed=21)
+    assert np.linalg.norm(Q - Qd) < 1e-10
+    assert np.linalg.norm(L - Rt.T) < 1e-10 * np.linalg.norm(L)
+    assert np.linalg.norm(P - Pbar @ Pt) < 1e-10
