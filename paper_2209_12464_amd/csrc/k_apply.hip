@@ -25,7 +25,7 @@ __host__ __device__ inline size_t apply_lds_doubles(int rf) {
 }
 
 // Workgroup (bx, by): rows bx * 64 RF .. and column blocks 4 by .. 4 by + 3.
-template <typename Tin, typename Tout, int RF>
+template <typename Tin, typename Tout, int RF, typename C = double>
 __device__ __attribute__((always_inline)) inline void apply_body(const Tin* __restrict__ Y, int64_t ldy, int64_t rows,
                                                                  int d, int dp, const int32_t* __restrict__ flags,
                                                                  const int32_t* __restrict__ mode,
@@ -35,7 +35,8 @@ __device__ __attribute__((always_inline)) inline void apply_body(const Tin* __re
                                                                  uint64_t seed, uint64_t key1, double inv_sqrt_rows,
                                                                  int bx, int by) {
   constexpr int kApRows = 64 * RF;  // rows per workgroup (16 RF per wave)
-  extern __shared__ double smem[];
+  extern __shared__ double smem_raw[];
+  C* smem = reinterpret_cast<C*>(smem_raw);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane >> 4, lc = lane & 15;
@@ -49,8 +50,8 @@ __device__ __attribute__((always_inline)) inline void apply_body(const Tin* __re
   const int J0 = 4 * by;
   if (J0 >= T) return;
   const int J1 = min(T, J0 + 4);
-  double* Xs = smem;                           // [2][16][kApXS]
-  double* Ys = smem + 2 * kTile * kApXS;       // [2][64][kApYS]
+  C* Xs = smem;                                // [2][16][kApXS]
+  C* Ys = smem + 2 * kTile * kApXS;            // [2][64 RF][kApYS]
   double xr[4];
   Tin yr[4 * RF];
   auto load = [&](int t) {
@@ -74,19 +75,19 @@ __device__ __attribute__((always_inline)) inline void apply_body(const Tin* __re
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
-      Xs[buf * kTile * kApXS + (e >> 6) * kApXS + (e & 63)] = xr[q];
+      Xs[buf * kTile * kApXS + (e >> 6) * kApXS + (e & 63)] = (C)xr[q];
     }
 #pragma unroll
     for (int q = 0; q < 4 * RF; ++q) {
       const int e = tid + 256 * q;
-      Ys[buf * kApRows * kApYS + (e >> 4) * kApYS + (e & 15)] = (double)yr[q];
+      Ys[buf * kApRows * kApYS + (e >> 4) * kApYS + (e & 15)] = (C)yr[q];
     }
   };
-  doublex4 acc[RF][4];
+  typename Mfma<C>::acc_t acc[RF][4];
 #pragma unroll
   for (int f = 0; f < RF; ++f)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc[f][u] = Mfma<double>::zero();
+    for (int u = 0; u < 4; ++u) acc[f][u] = Mfma<C>::zero();
   load(0);
   store(0);
   __syncthreads();
@@ -94,9 +95,9 @@ __device__ __attribute__((always_inline)) inline void apply_body(const Tin* __re
   for (int t = 0; t < J1; ++t) {
     const bool more = t + 1 < J1;
     if (more) load(t + 1);
-    const double* xs = Xs + buf * kTile * kApXS;
-    const double* ys = Ys + buf * kApRows * kApYS + (wave * kTile * RF + lc) * kApYS;
-    double a[RF][4];
+    const C* xs = Xs + buf * kTile * kApXS;
+    const C* ys = Ys + buf * kApRows * kApYS + (wave * kTile * RF + lc) * kApYS;
+    C a[RF][4];
 #pragma unroll
     for (int f = 0; f < RF; ++f)
 #pragma unroll
@@ -107,9 +108,9 @@ __device__ __attribute__((always_inline)) inline void apply_body(const Tin* __re
       if (J0 + u >= t && J0 + u < J1) {
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
-          const double b = xs[(ks * 4 + lr) * kApXS + u * kTile + lc];
+          const C b = xs[(ks * 4 + lr) * kApXS + u * kTile + lc];
 #pragma unroll
-          for (int f = 0; f < RF; ++f) acc[f][u] = Mfma<double>::mma(a[f][ks], b, acc[f][u]);
+          for (int f = 0; f < RF; ++f) acc[f][u] = Mfma<C>::mma(a[f][ks], b, acc[f][u]);
         }
       }
     }
@@ -120,15 +121,15 @@ __device__ __attribute__((always_inline)) inline void apply_body(const Tin* __re
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     if (J0 + u >= J1) break;
-    const int col = (J0 + u) * kTile + lc;
 #pragma unroll
     for (int f = 0; f < RF; ++f)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + (wave * RF + f) * kTile + lr + 4 * r;
+        const int64_t row = r0 + (wave * RF + f) * kTile + Mfma<C>::row(lane, r);
+        const int cc = (J0 + u) * kTile + Mfma<C>::col(lane);
         if (row < rows) {
-          if (col < ncols1) out1[row * ld1 + col] = (Tout)acc[f][u][r];
-          if (out2 && col < ncols2) out2[row * ld2 + col] = (Tout)acc[f][u][r];
+          if (cc < ncols1) out1[row * ld1 + cc] = (Tout)acc[f][u][r];
+          if (out2 && cc < ncols2) out2[row * ld2 + cc] = (Tout)acc[f][u][r];
         }
       }
   }
@@ -211,6 +212,76 @@ hipError_t launch_apply(const Tin* Y, int64_t ldy, int64_t rows, int d, int dp, 
     if (!record_launch(&apply_grouped_launch<Tin, Tout, 1>, a, gx * groups))
       hipLaunchKernelGGL((apply_kernel<Tin, Tout, 1>), dim3(gx, groups), dim3(256), shmem, s, Y, ldy, rows, d, dp,
                          flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2, seed, key1, isr);
+  }
+  if (ev1) (void)hipEventRecord(ev1, s);
+  return hipGetLastError();
+}
+
+// Second pass of the bfloat16 form: float32 arithmetic when the Cholesky
+// took its fast path (X = I - F), float64 otherwise.
+template <int RF>
+__device__ __attribute__((always_inline)) inline void apply_f32fast_body(
+    const double* __restrict__ Y, int64_t ldy, int64_t rows, int d, int dp, const int32_t* __restrict__ flags,
+    const int32_t* __restrict__ mode, const double* __restrict__ Xfull, float* __restrict__ out1, int64_t ld1,
+    int ncols1, float* __restrict__ out2, int64_t ld2, int ncols2, uint64_t seed, uint64_t key1,
+    double inv_sqrt_rows, int bx, int by) {
+  if (*mode == 2)
+    apply_body<double, float, RF, float>(Y, ldy, rows, d, dp, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2,
+                                         ncols2, seed, key1, inv_sqrt_rows, bx, by);
+  else
+    apply_body<double, float, RF, double>(Y, ldy, rows, d, dp, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2,
+                                          ncols2, seed, key1, inv_sqrt_rows, bx, by);
+}
+
+template <int RF>
+__global__ __launch_bounds__(256) void apply_f32fast_kernel(const double* __restrict__ Y, int64_t ldy, int64_t rows,
+                                                            int d, int dp, const int32_t* __restrict__ flags,
+                                                            const int32_t* __restrict__ mode,
+                                                            const double* __restrict__ Xfull,
+                                                            float* __restrict__ out1, int64_t ld1, int ncols1,
+                                                            float* __restrict__ out2, int64_t ld2, int ncols2,
+                                                            uint64_t seed, uint64_t key1, double inv_sqrt_rows) {
+  apply_f32fast_body<RF>(Y, ldy, rows, d, dp, flags, mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2, seed, key1,
+                         inv_sqrt_rows, blockIdx.x, blockIdx.y);
+}
+
+template <int RF>
+__global__ __launch_bounds__(256) void apply_f32fast_grouped(const ApplyArgs* __restrict__ a,
+                                                             const int* __restrict__ start, int count) {
+  const int p = group_find(start, count, blockIdx.x);
+  const ApplyArgs g = a[p];
+  const int b = (int)blockIdx.x - start[p];
+  apply_f32fast_body<RF>((const double*)g.Y, g.ldy, g.rows, g.d, g.dp, g.flags, g.mode, g.X, (float*)g.out1, g.ld1,
+                         g.ncols1, (float*)g.out2, g.ld2, g.ncols2, g.seed, g.key1, g.isr, b % g.gx, b / g.gx);
+}
+
+template <int RF>
+void apply_f32fast_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL((apply_f32fast_grouped<RF>), dim3(blocks), dim3(256), apply_lds_doubles(RF) * sizeof(double), s,
+                     (const ApplyArgs*)args, start, count);
+}
+
+hipError_t launch_apply_f32fast(const double* Y, int64_t ldy, int64_t rows, int d, int dp, const int32_t* flags,
+                                const int32_t* mode, const double* Xfull, float* out1, int64_t ld1, int ncols1,
+                                float* out2, int64_t ld2, int ncols2, uint64_t seed, uint64_t key1, hipStream_t s,
+                                hipEvent_t ev0, hipEvent_t ev1) {
+  if (rows <= 0) return hipSuccess;
+  const double isr = 1.0 / sqrt((double)rows);
+  const unsigned groups = (unsigned)ceil_div(dp / kTile, 4);
+  const int rf = (groups >= 5 && ceil_div(rows, 128) * groups >= 1024) ? 2 : 1;  // as launch_apply
+  const size_t shmem = apply_lds_doubles(rf) * sizeof(double);
+  if (ev0) (void)hipEventRecord(ev0, s);
+  const unsigned gx = (unsigned)ceil_div(rows, 64 * rf);
+  const ApplyArgs a{Y, flags, mode, Xfull, out1, out2, ldy, rows, ld1, ld2, seed, key1, isr, d, dp, ncols1, ncols2,
+                    (int)gx};
+  if (rf == 2) {
+    if (!record_launch(&apply_f32fast_grouped_launch<2>, a, gx * groups))
+      hipLaunchKernelGGL((apply_f32fast_kernel<2>), dim3(gx, groups), dim3(256), shmem, s, Y, ldy, rows, d, dp, flags,
+                         mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2, seed, key1, isr);
+  } else {
+    if (!record_launch(&apply_f32fast_grouped_launch<1>, a, gx * groups))
+      hipLaunchKernelGGL((apply_f32fast_kernel<1>), dim3(gx, groups), dim3(256), shmem, s, Y, ldy, rows, d, dp, flags,
+                         mode, Xfull, out1, ld1, ncols1, out2, ld2, ncols2, seed, key1, isr);
   }
   if (ev1) (void)hipEventRecord(ev1, s);
   return hipGetLastError();

@@ -1,6 +1,10 @@
 // Gram matrix G = Y^T Y in float64, the first step of each CholeskyQR pass.
 // Float inputs are widened to double: a product of two floats is exact in
-// double, so only the summation rounds.  The d x d upper triangle is cut
+// double, so only the summation rounds.  A float32-arithmetic variant
+// (inputs rounded to float, float32 MFMA within a row chunk, chunk sums in
+// float64) serves the second pass of the bfloat16 form, whose basis is
+// orthonormal to working accuracy (G = I + E, E small), so that float32
+// rounding of the Gram entries is far below the form's own error.  The d x d upper triangle is cut
 // into 64 x 64 tiles and the rows of Y into chunks; each workgroup forms one
 // tile over one chunk with the float64 MFMA (16x16x4), and a second kernel
 // adds the chunk partials in a fixed order (deterministic) and mirrors the
@@ -26,13 +30,16 @@ __device__ inline void tile_pair(int p, int& I, int& J) {
   I = p - j * (j + 1) / 2;
 }
 
-template <typename T>
+template <typename T, typename C>
 __device__ __attribute__((always_inline)) inline void gram_partial_body(const T* __restrict__ Y, int64_t ldy,
                                                                         int64_t rows, int d, int dp,
                                                                         int64_t chunk_rows, int npairs,
                                                                         double* __restrict__ P, int bid) {
-  __shared__ double YI[2][kGK][kGT + 1];
-  __shared__ double YJ[2][kGK][kGT + 1];
+  // rows of kGT + 1 doubles, or kGT + 16 floats: the two k-rows one operand
+  // read touches fall in disjoint banks
+  constexpr int LS = sizeof(C) == 8 ? kGT + 1 : kGT + 16;
+  __shared__ C YI[2][kGK][LS];
+  __shared__ C YJ[2][kGK][LS];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int pair = bid % npairs;
@@ -42,9 +49,9 @@ __device__ __attribute__((always_inline)) inline void gram_partial_body(const T*
   const int64_t r0 = (int64_t)chunk * chunk_rows;
   const int64_t r1 = min(rows, r0 + chunk_rows);
   const int wi = wave >> 1, wj = wave & 1;
-  doublex4 acc[2][2];
+  typename Mfma<C>::acc_t acc[2][2];
   for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<double>::zero();
+    for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<C>::zero();
 
   // The prefetch registers hold the raw inputs: widening to double happens
   // at the LDS store, so the loads stay in flight across the MFMA loop.
@@ -65,8 +72,8 @@ __device__ __attribute__((always_inline)) inline void gram_partial_body(const T*
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int idx = tid + 256 * i;
-      YI[buf][idx / kGT][idx % kGT] = (double)ri[i];
-      YJ[buf][idx / kGT][idx % kGT] = (double)rj[i];
+      YI[buf][idx / kGT][idx % kGT] = (C)ri[i];
+      YJ[buf][idx / kGT][idx % kGT] = (C)rj[i];
     }
   };
 
@@ -80,7 +87,7 @@ __device__ __attribute__((always_inline)) inline void gram_partial_body(const T*
       if (more) load(k0 + kGK);
 #pragma unroll
       for (int ks = 0; ks < kGK / 4; ++ks) {
-        double a[2], b[2];
+        C a[2], b[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           a[t] = YI[buf][ks * 4 + lane / 16][wi * 32 + t * 16 + (lane & 15)];
@@ -89,7 +96,7 @@ __device__ __attribute__((always_inline)) inline void gram_partial_body(const T*
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
-          for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<double>::mma(a[x], b[y], acc[x][y]);
+          for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<C>::mma(a[x], b[y], acc[x][y]);
       }
       if (more) store(buf ^ 1);
       __syncthreads();
@@ -103,17 +110,17 @@ __device__ __attribute__((always_inline)) inline void gram_partial_body(const T*
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = I * kGT + wi * 32 + x * 16 + Mfma<double>::row(lane, r);
-        const int col = J * kGT + wj * 32 + y * 16 + Mfma<double>::col(lane);
-        if (row < dp && col < dp) Pc[(int64_t)row * dp + col] = acc[x][y][r];
+        const int row = I * kGT + wi * 32 + x * 16 + Mfma<C>::row(lane, r);
+        const int col = J * kGT + wj * 32 + y * 16 + Mfma<C>::col(lane);
+        if (row < dp && col < dp) Pc[(int64_t)row * dp + col] = (double)acc[x][y][r];
       }
 }
 
-template <typename T>
+template <typename T, typename C>
 __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__ Y, int64_t ldy, int64_t rows, int d,
                                                            int dp, int64_t chunk_rows, int npairs,
                                                            double* __restrict__ P) {
-  gram_partial_body<T>(Y, ldy, rows, d, dp, chunk_rows, npairs, P, blockIdx.x);
+  gram_partial_body<T, C>(Y, ldy, rows, d, dp, chunk_rows, npairs, P, blockIdx.x);
 }
 
 struct GramPartialArgs {
@@ -123,19 +130,19 @@ struct GramPartialArgs {
   int d, dp, npairs;
 };
 
-template <typename T>
+template <typename T, typename C>
 __global__ __launch_bounds__(256) void gram_partial_grouped(const GramPartialArgs* __restrict__ a,
                                                             const int* __restrict__ start, int count) {
   const int p = group_find(start, count, blockIdx.x);
   const GramPartialArgs g = a[p];
-  gram_partial_body<T>((const T*)g.Y, g.ldy, g.rows, g.d, g.dp, g.chunk_rows, g.npairs, g.P,
-                       (int)blockIdx.x - start[p]);
+  gram_partial_body<T, C>((const T*)g.Y, g.ldy, g.rows, g.d, g.dp, g.chunk_rows, g.npairs, g.P,
+                          (int)blockIdx.x - start[p]);
 }
 
-template <typename T>
+template <typename T, typename C>
 void gram_partial_grouped_launch(const void* args, const int* start, int count, unsigned blocks, hipStream_t s) {
-  hipLaunchKernelGGL(gram_partial_grouped<T>, dim3(blocks), dim3(256), 0, s, (const GramPartialArgs*)args, start,
-                     count);
+  hipLaunchKernelGGL((gram_partial_grouped<T, C>), dim3(blocks), dim3(256), 0, s, (const GramPartialArgs*)args,
+                     start, count);
 }
 
 // G[i][j] = G[j][i] = sum over chunks of P[c][i][j] for i <= j (fixed order).
@@ -225,26 +232,38 @@ int gram_chunks(int64_t rows, int dp) {
   return (int)ceil_div(rows, chunk_rows);
 }
 
-template <typename T>
-hipError_t launch_gram(const T* Y, int64_t ldy, int64_t rows, int d, int dp, double* P,
-                       int nchunks, double* G, double* esq, void* info, hipStream_t s,
-                       hipEvent_t ev0, hipEvent_t ev1) {
+template <typename T, typename C>
+hipError_t launch_gram_c(const T* Y, int64_t ldy, int64_t rows, int d, int dp, double* P,
+                         int nchunks, double* G, double* esq, void* info, hipStream_t s,
+                         hipEvent_t ev0, hipEvent_t ev1) {
   const int t = (int)ceil_div(dp, kGT);
   const int npairs = t * (t + 1) / 2;
   const int64_t chunk_rows = std::max<int64_t>(128, round_up(ceil_div(rows, nchunks), kGK));
   if (ev0) (void)hipEventRecord(ev0, s);
   const unsigned pb = (unsigned)(npairs * nchunks);
-  if (!record_launch(&gram_partial_grouped_launch<T>, GramPartialArgs{Y, P, ldy, rows, chunk_rows, d, dp, npairs}, pb))
-    hipLaunchKernelGGL(gram_partial_kernel<T>, dim3(pb), dim3(256), 0, s, Y, ldy, rows, d, dp, chunk_rows, npairs, P);
+  if (!record_launch(&gram_partial_grouped_launch<T, C>, GramPartialArgs{Y, P, ldy, rows, chunk_rows, d, dp, npairs},
+                     pb))
+    hipLaunchKernelGGL((gram_partial_kernel<T, C>), dim3(pb), dim3(256), 0, s, Y, ldy, rows, d, dp, chunk_rows, npairs,
+                       P);
   if (ev1) (void)hipEventRecord(ev1, s);
   const unsigned rb = (unsigned)gram_reduce_blocks(dp);
   if (!record_launch(&gram_reduce_grouped_launch, GramReduceArgs{P, G, esq, (DevInfo*)info, nchunks, d, dp}, rb))
     hipLaunchKernelGGL(gram_reduce_kernel, dim3(rb), dim3(256), 0, s, P, nchunks, d, dp, G, esq, (DevInfo*)info);
   return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_gram(const T* Y, int64_t ldy, int64_t rows, int d, int dp, double* P, int nchunks, double* G,
+                       double* esq, void* info, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  return launch_gram_c<T, double>(Y, ldy, rows, d, dp, P, nchunks, G, esq, info, s, ev0, ev1);
+}
 template hipError_t launch_gram<float>(const float*, int64_t, int64_t, int, int, double*, int,
                                        double*, double*, void*, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_gram<double>(const double*, int64_t, int64_t, int, int, double*, int,
                                         double*, double*, void*, hipStream_t, hipEvent_t, hipEvent_t);
+
+hipError_t launch_gram_f32c(const double* Y, int64_t ldy, int64_t rows, int d, int dp, double* P, int nchunks,
+                            double* G, double* esq, void* info, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  return launch_gram_c<double, float>(Y, ldy, rows, d, dp, P, nchunks, G, esq, info, s, ev0, ev1);
+}
 
 }  // namespace rqlp

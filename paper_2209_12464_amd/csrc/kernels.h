@@ -71,6 +71,11 @@ template <typename T>
 hipError_t launch_gram(const T* Y, int64_t ldy, int64_t rows, int d, int dp, double* P,
                        int nchunks, double* G, double* esq, void* info, hipStream_t s,
                        hipEvent_t ev0, hipEvent_t ev1);
+// The same with float32 arithmetic (Y rounded to float, float32 MFMA within
+// a row chunk, chunk partials and their sum in float64): for a basis that
+// is orthonormal to working accuracy (the bfloat16 form's second pass).
+hipError_t launch_gram_f32c(const double* Y, int64_t ldy, int64_t rows, int d, int dp, double* P, int nchunks,
+                            double* G, double* esq, void* info, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 int gram_chunks(int64_t rows, int dp);
 
 // X = R^-1 (dp x dp, row-major; the blocks on and above the diagonal are
@@ -129,6 +134,14 @@ hipError_t launch_apply(const Tin* Y, int64_t ldy, int64_t rows, int d, int dp, 
                         const int32_t* mode, const double* Xfull, Tout* out1, int64_t ld1, int ncols1, Tout* out2,
                         int64_t ld2, int ncols2, uint64_t seed, uint64_t key1, hipStream_t s,
                         hipEvent_t ev0, hipEvent_t ev1);
+// The same, but when the Cholesky took its fast path (*mode == 2: Xfull =
+// I - F with F small) Y and Xfull are rounded to float and multiplied with
+// float32 MFMA (the product is within float32 rounding of Y itself);
+// otherwise as launch_apply.
+hipError_t launch_apply_f32fast(const double* Y, int64_t ldy, int64_t rows, int d, int dp, const int32_t* flags,
+                                const int32_t* mode, const double* Xfull, float* out1, int64_t ld1, int ncols1,
+                                float* out2, int64_t ld2, int ncols2, uint64_t seed, uint64_t key1, hipStream_t s,
+                                hipEvent_t ev0, hipEvent_t ev1);
 
 // ---- small d x d helpers (k_small.hip) ----
 // L (d x d, ld ldl, type T) = (R2 * R1')^T where R1' is R1 with the rows of

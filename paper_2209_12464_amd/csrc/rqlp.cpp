@@ -304,7 +304,7 @@ hipError_t factor(rqlp_ctx* c, const Bufs& b, double* R, int32_t* flags, int d, 
 template <typename T>
 rqlp_status cholqr2(rqlp_ctx* c, const T* Y, int64_t ldy, int64_t rows, int d, const Bufs& b,
                     T* out1, int64_t ld1, int ncols1, T* out2, int64_t ld2, int ncols2,
-                    uint64_t seed, int orth_index, hipStream_t s) {
+                    uint64_t seed, int orth_index, hipStream_t s, bool lowp2 = false) {
   const int dp = padded_d(d);
   const int gch = gram_chunks(rows, dp);
   const double ftol = fast_tol_for(sizeof(T) == 8);
@@ -316,10 +316,24 @@ rqlp_status cholqr2(rqlp_ctx* c, const T* Y, int64_t ldy, int64_t rows, int d, c
   t = timer(c, RQLP_KT_APPLY);
   HIP_TRY((launch_apply<T, double>(Y, ldy, rows, d, dp, b.flags, mode, b.xf, b.q1, dp, dp, nullptr, 0, 0, seed,
                                    completion_key(orth_index, 0), s, t.a, t.b)));
+  // second pass: Q1 is orthonormal to working accuracy; for float output
+  // with lowp2 (the bfloat16 form) its Gram matrix and, on the fast path,
+  // the product take float32 arithmetic
+  const bool f32_2 = lowp2 && sizeof(T) == 4;
   t = timer(c, RQLP_KT_GRAM);
-  HIP_TRY(launch_gram<double>(b.q1, dp, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
+  if (f32_2)
+    HIP_TRY(launch_gram_f32c(b.q1, dp, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
+  else
+    HIP_TRY(launch_gram<double>(b.q1, dp, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
   HIP_TRY(factor(c, b, b.r2, b.flags + dp, d, dp, orth_index, ftol, mode + 1, nesq, s));
   t = timer(c, RQLP_KT_APPLY);
+  if constexpr (sizeof(T) == 4) {
+    if (f32_2) {
+      HIP_TRY(launch_apply_f32fast(b.q1, dp, rows, d, dp, b.flags + dp, mode + 1, b.xf, out1, ld1, ncols1, out2, ld2,
+                                   ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b));
+      return RQLP_OK;
+    }
+  }
   HIP_TRY((launch_apply<double, T>(b.q1, dp, rows, d, dp, b.flags + dp, mode + 1, b.xf, out1, ld1, ncols1, out2, ld2,
                                    ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b)));
   return RQLP_OK;
@@ -362,7 +376,7 @@ rqlp_status check_common(int64_t m, int64_t n, int k, int p, int q, rqlp_precisi
 template <typename T, typename MulA, typename MulAt>
 rqlp_status run_method(rqlp_ctx* c, char* base, const Layout& Lo, int64_t m, int64_t n, int k, int p,
                        int q, uint64_t seed, T* Q, T* Lout, T* V, hipStream_t s, MulA mulA, MulAt mulAt,
-                       int ldl = 0) {
+                       int ldl = 0, bool lowp2 = false) {
   const int d = k + p, dp = padded_d(d);
   T* om = (T*)(base + Lo.om);
   T* yb = (T*)(base + Lo.yb);
@@ -383,19 +397,19 @@ rqlp_status run_method(rqlp_ctx* c, char* base, const Layout& Lo, int64_t m, int
   HIP_TRY(launch_gaussian<T>(seed, kSketchKey1, n, d, om, dp, s));
   if ((st = mulA(om, yb)) != RQLP_OK) return st;
   int oi = 1;
-  if ((st = cholqr2<T>(c, yb, dp, m, d, b, qi, dp, dp, q == 0 ? Q : nullptr, d, d, seed, oi++, s)) != RQLP_OK)
+  if ((st = cholqr2<T>(c, yb, dp, m, d, b, qi, dp, dp, q == 0 ? Q : nullptr, d, d, seed, oi++, s, lowp2)) != RQLP_OK)
     return st;
   for (int it = 1; it <= q; ++it) {
     // W = orth(A^T Q) (stored in the Omega buffer), Q = orth(A W)
     if ((st = mulAt(qi, yb)) != RQLP_OK) return st;
-    if ((st = cholqr2<T>(c, yb, dp, n, d, b, om, dp, dp, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
+    if ((st = cholqr2<T>(c, yb, dp, n, d, b, om, dp, dp, nullptr, 0, 0, seed, oi++, s, lowp2)) != RQLP_OK) return st;
     if ((st = mulA(om, yb)) != RQLP_OK) return st;
-    if ((st = cholqr2<T>(c, yb, dp, m, d, b, qi, dp, dp, it == q ? Q : nullptr, d, d, seed, oi++, s)) != RQLP_OK)
+    if ((st = cholqr2<T>(c, yb, dp, m, d, b, qi, dp, dp, it == q ? Q : nullptr, d, d, seed, oi++, s, lowp2)) != RQLP_OK)
       return st;
   }
   // B^T = A^T Q; [V, R] = qr(B^T); L = R^T
   if ((st = mulAt(qi, yb)) != RQLP_OK) return st;
-  if ((st = cholqr2<T>(c, yb, dp, n, d, b, V, d, d, nullptr, 0, 0, seed, oi++, s)) != RQLP_OK) return st;
+  if ((st = cholqr2<T>(c, yb, dp, n, d, b, V, d, d, nullptr, 0, 0, seed, oi++, s, lowp2)) != RQLP_OK) return st;
   HIP_TRY(launch_form_l<T>(b.r2, b.r1, b.flags, d, dp, Lout, ldl > 0 ? ldl : d, s));
   return RQLP_OK;
 }
@@ -461,7 +475,9 @@ rqlp_status decompose_paper(rqlp_ctx* c, const T* A, int64_t m, int64_t n, int64
 
 // RQLP_BF16_REFINED: A (float) is rounded to bfloat16 once, in both layouts;
 // every product rounds its right-hand factor to bfloat16 and accumulates in
-// float32; the rest of the method is the float32 form.
+// float32; the rest of the method is the float32 form, except that the
+// second CholeskyQR pass of every orthonormalization runs its Gram matrix
+// and (on its fast path) its product in float32 arithmetic.
 rqlp_status decompose_dense_bf16(rqlp_ctx* c, const float* A, int64_t m, int64_t n, int64_t lda, int k, int p,
                                  int q, uint64_t seed, float* Q, float* L, float* V, void* ws, size_t ws_bytes,
                                  hipStream_t s) {
@@ -488,7 +504,9 @@ rqlp_status decompose_dense_bf16(rqlp_ctx* c, const float* A, int64_t m, int64_t
     HIP_TRY(launch_gemm_bf16(at, ldm, xt, ldm, (int)n, dp, (int)ldm, Y, dp, dp, part, s, t.a, t.b));
     return RQLP_OK;
   };
-  return run_method<float>(c, base, Lo, m, n, k, p, q, seed, Q, L, V, s, mulA, mulAt);
+  // the second CholeskyQR pass in float32 arithmetic where that is within
+  // the form's own accuracy (bfloat16 operands)
+  return run_method<float>(c, base, Lo, m, n, k, p, q, seed, Q, L, V, s, mulA, mulAt, 0, true);
 }
 
 template <typename T>
