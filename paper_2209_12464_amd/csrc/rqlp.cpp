@@ -316,26 +316,23 @@ rqlp_status cholqr2(rqlp_ctx* c, const T* Y, int64_t ldy, int64_t rows, int d, c
   t = timer(c, RQLP_KT_APPLY);
   HIP_TRY((launch_apply<T, double>(Y, ldy, rows, d, dp, b.flags, mode, b.xf, b.q1, dp, dp, nullptr, 0, 0, seed,
                                    completion_key(orth_index, 0), s, t.a, t.b)));
-  // second pass: Q1 is orthonormal to working accuracy; for float output
-  // with lowp2 (the bfloat16 form) its Gram matrix and, on the fast path,
-  // the product take float32 arithmetic
-  const bool f32_2 = lowp2 && sizeof(T) == 4;
+  // second pass: Q1 is orthonormal to working accuracy.  For float output
+  // the product on the fast path (X = I - F, ||F||_F below 2^-19) takes
+  // float32 arithmetic, which changes Q by less than its own rounding; with
+  // lowp2 (the bfloat16 form) so does the Gram matrix.
   t = timer(c, RQLP_KT_GRAM);
-  if (f32_2)
+  if (lowp2 && sizeof(T) == 4)
     HIP_TRY(launch_gram_f32c(b.q1, dp, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
   else
     HIP_TRY(launch_gram<double>(b.q1, dp, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
   HIP_TRY(factor(c, b, b.r2, b.flags + dp, d, dp, orth_index, ftol, mode + 1, nesq, s));
   t = timer(c, RQLP_KT_APPLY);
-  if constexpr (sizeof(T) == 4) {
-    if (f32_2) {
-      HIP_TRY(launch_apply_f32fast(b.q1, dp, rows, d, dp, b.flags + dp, mode + 1, b.xf, out1, ld1, ncols1, out2, ld2,
-                                   ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b));
-      return RQLP_OK;
-    }
-  }
-  HIP_TRY((launch_apply<double, T>(b.q1, dp, rows, d, dp, b.flags + dp, mode + 1, b.xf, out1, ld1, ncols1, out2, ld2,
-                                   ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b)));
+  if constexpr (sizeof(T) == 4)
+    HIP_TRY(launch_apply_f32fast(b.q1, dp, rows, d, dp, b.flags + dp, mode + 1, b.xf, out1, ld1, ncols1, out2, ld2,
+                                 ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b));
+  else
+    HIP_TRY((launch_apply<double, T>(b.q1, dp, rows, d, dp, b.flags + dp, mode + 1, b.xf, out1, ld1, ncols1, out2,
+                                     ld2, ncols2, seed, completion_key(orth_index, 1), s, t.a, t.b)));
   return RQLP_OK;
 }
 
