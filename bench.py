@@ -75,17 +75,22 @@ def f_alg_csr(nnz, m, n, k, p, q):
     return 2.0 * nnz * d * (2 * q + 2) + qr(m) * (q + 1) + qr(n) * (q + 1)
 
 
-# source files that define each timed kernel class (for the traffic record)
+# source files that define each timed kernel class (for the traffic and
+# MFMA records); the bfloat16 workloads time the bfloat16 product kernel
 KERNEL_SOURCES = {
-    "gemm_nn": ["k_gemm.hip", "k_bf16.hip", "common.h", "kernels.h"],
-    "gemm_tn": ["k_gemm.hip", "k_bf16.hip", "common.h", "kernels.h"],
+    "gemm_nn": ["k_gemm.hip", "common.h", "kernels.h"],
+    "gemm_tn": ["k_gemm.hip", "common.h", "kernels.h"],
     "spmm": ["k_csr.hip", "common.h", "kernels.h"],
 }
+BF16_GEMM_SOURCES = ["k_bf16.hip", "common.h", "kernels.h"]
 
 
-def kernel_source_hash(kernel):
+def kernel_source_hash(kernel, workload):
+    names = KERNEL_SOURCES[kernel]
+    if workload.startswith("bf16") and kernel in ("gemm_nn", "gemm_tn"):
+        names = BF16_GEMM_SOURCES
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES[kernel]:
+    for name in names:
         with open(os.path.join(ROOT, "paper_2209_12464_amd", "csrc", name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -103,36 +108,47 @@ def load_traffic(workload, kernel):
     except (OSError, ValueError):
         return None
     ent = rec.get(workload, {}).get(kernel)
-    if not ent or ent.get("source_hash") != kernel_source_hash(kernel):
+    if not ent or ent.get("source_hash") != kernel_source_hash(kernel, workload):
         return None
     return ent.get("bytes_per_launch")
 
 
-def load_mfma_util(workload, kernel):
+def load_mfma_record(workload, kernel):
     """MFMA utilization (fraction of SIMD cycles with the matrix core busy)
-    of `kernel` from the rocprofv3 SQ_VALU_MFMA_BUSY_CYCLES / GRBM_GUI_ACTIVE
-    run recorded in profiles/mfma.json, if taken on the kernel's current
-    sources; else None."""
+    and shader clock of `kernel` from the rocprofv3 SQ_VALU_MFMA_BUSY_CYCLES /
+    GRBM_GUI_ACTIVE run recorded in profiles/mfma.json, if taken on the
+    kernel's current sources; else (None, None)."""
     path = os.path.join(ROOT, "profiles", "mfma.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
-        return None
+        return None, None
     ent = rec.get(workload, {}).get(kernel)
-    if not ent or ent.get("source_hash") != kernel_source_hash(kernel):
-        return None
-    return ent.get("mfma_util")
+    if not ent or ent.get("source_hash") != kernel_source_hash(kernel, workload):
+        return None, None
+    return ent.get("mfma_util"), ent.get("clock_ghz")
 
 
 def record_mfma(workload, pmc_csv, simds=1024, xcds=8):
     """MFMA utilization per dispatch of the timed product kernels from a
     rocprofv3 counter CSV holding SQ_VALU_MFMA_BUSY_CYCLES (summed over all
     SIMDs) and GRBM_GUI_ACTIVE (summed over the XCDs): busy / (active / xcds
-    * simds); stored in profiles/mfma.json with the kernel's source hash."""
+    * simds); stored in profiles/mfma.json with the kernel's source hash,
+    together with the shader clock the dispatches ran at (active cycles per
+    XCD over the dispatch's duration)."""
+    import csv
     busy = read_counter(pmc_csv, "SQ_VALU_MFMA_BUSY_CYCLES")
     active = read_counter(pmc_csv, "GRBM_GUI_ACTIVE")
-    mops = read_counter(pmc_csv, "SQ_INSTS_VALU_MFMA_MOPS_F32")
+    dur, mops_name = {}, None
+    with open(pmc_csv) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == "GRBM_GUI_ACTIVE":
+                dur.setdefault(r["Kernel_Name"], []).append(
+                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+            elif r["Counter_Name"].startswith("SQ_INSTS_VALU_MFMA_MOPS_"):
+                mops_name = r["Counter_Name"]
+    mops = read_counter(pmc_csv, mops_name) if mops_name else {}
     path = os.path.join(ROOT, "profiles", "mfma.json")
     try:
         with open(path) as f:
@@ -141,16 +157,28 @@ def record_mfma(workload, pmc_csv, simds=1024, xcds=8):
         rec = {}
     out = {}
     for name, bv in busy.items():
-        cls = kernel_class(name)
-        if cls is None or name not in active:
+        if name not in active:
             continue
-        util = [b / (a / xcds * simds) for b, a in zip(bv, active[name])]
-        ent = {"mfma_util": float(np.mean(util)), "dispatches": len(util),
-               "busy_cycles": float(np.mean(bv)), "gui_active_per_xcd": float(np.mean(active[name])) / xcds,
-               "source_hash": kernel_source_hash(cls)}
-        if name in mops:
-            ent["mfma_flops_f32"] = float(np.mean(mops[name])) * 512.0
-        out[cls] = ent
+        if "rqlp::gemm_bf16_kernel" in name:
+            # one kernel for both products: dispatches alternate A X, A^T X
+            parts = (("gemm_nn", slice(0, None, 2)), ("gemm_tn", slice(1, None, 2)))
+        else:
+            cls = kernel_class(name)
+            if cls is None:
+                continue
+            parts = ((cls, slice(None)),)
+        for cls, sl in parts:
+            b, a = bv[sl], active[name][sl]
+            util = [x / (y / xcds * simds) for x, y in zip(b, a)]
+            ent = {"mfma_util": float(np.mean(util)), "dispatches": len(util),
+                   "busy_cycles": float(np.mean(b)), "gui_active_per_xcd": float(np.mean(a)) / xcds,
+                   "source_hash": kernel_source_hash(cls, workload)}
+            if name in dur:
+                ent["clock_ghz"] = float(np.mean([y / xcds / t for y, t in zip(a, dur[name][sl])])) / 1e9
+            if name in mops:
+                ent["mfma_flops"] = float(np.mean(mops[name][sl])) * 512.0
+                ent["mfma_mops_counter"] = mops_name
+            out[cls] = ent
     rec[workload] = out
     with open(path, "w") as f:
         json.dump(rec, f, indent=1, sort_keys=True)
@@ -515,7 +543,7 @@ def record_traffic(workload, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv,
         wb = float(np.mean(wv)) * 1024.0 * f_write
         out[cls] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
                     "fetch_scale": f_fetch, "write_scale": f_write, "dispatches": len(fv),
-                    "source_hash": kernel_source_hash(cls)}
+                    "source_hash": kernel_source_hash(cls, workload)}
     rec[workload] = out
     with open(path, "w") as f:
         json.dump(rec, f, indent=1, sort_keys=True)
@@ -682,9 +710,10 @@ def run_single_bench(args, w, rqlp, torch, dev):
             step_s = per_kernel[kname]["total_ms"] * 1e-3 / args.steps
             achieved = dom_flops[kname] / step_s / 1e12
             traffic = load_traffic(args.workload, kname)
+            util, clock = load_mfma_record(args.workload, kname)
             roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                         "frac": achieved / peak, "traffic": traffic, "kernel": kname,
-                        "mfma_util": load_mfma_util(args.workload, kname),
+                        "mfma_util": util, "clock_ghz": clock,
                         "timed": "product kernel and its split-K reduction, HIP events on the launch stream"}
         else:
             # gather-inclusive bytes of one A X product: indices+values, row

@@ -131,9 +131,10 @@ hipError_t launch_cvt_bf16_t(const float* X, int64_t ldx, int64_t K, int64_t N, 
 // from global memory to LDS (16 bytes per lane, no register staging)
 // through a ring of three stages: the tiles of step i + 2 are requested
 // while step i computes, one barrier per step.  A tile row is 64 bytes (32
-// bf16); its four 16-byte chunks are stored XOR-swizzled by (row / 4) mod
-// 4, so that the 16 rows one MFMA operand read touches fall in distinct
-// banks.  K is a multiple of 32 (zero padded) and so is every split, so no
+// bf16); its four 16-byte chunks are stored XOR-swizzled by (row / 2) mod
+// 4, so that the 8 lanes the LDS serves together (8 consecutive rows of
+// one chunk column) cover all 128 bytes of a bank cycle once (the (row /
+// 4) mod 4 swizzle left two-way conflicts: six times the conflict cycles).  K is a multiple of 32 (zero padded) and so is every split, so no
 // step needs masking; rows past M or N are read clamped (their results are
 // not stored, or stored as zero).
 
@@ -145,7 +146,7 @@ constexpr int kBfStages = 3;
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
-__device__ inline int bf_swz(int row, int chunk) { return chunk ^ ((row >> 2) & 3); }
+__device__ inline int bf_swz(int row, int chunk) { return chunk ^ ((row >> 1) & 3); }
 
 template <int NF>
 __global__ __launch_bounds__(kBfThreads) void gemm_bf16_kernel(const uint16_t* __restrict__ A, int64_t lda,
@@ -198,23 +199,41 @@ __global__ __launch_bounds__(kBfThreads) void gemm_bf16_kernel(const uint16_t* _
 #pragma unroll
     for (int cf = 0; cf < NF; ++cf) acc[rf][cf] = (floatx4)0.0f;
   const int kc = lane >> 4;  // this lane's 8-element chunk of the 32-wide step
+  // Per step: the four A fragments and the first G column fragments are
+  // read, then the column fragments go in groups of G: the reads of group
+  // g + 1 are issued right after the first product of group g (whose
+  // operands the compiler waits for; with direct-to-LDS loads in flight it
+  // can only wait for all outstanding LDS reads), so they complete under the
+  // other 4 G - 1 products of the group.  The scheduling barriers keep that
+  // order.
   auto compute = [&](int st) {
     const uint16_t* T = tiles[st];
+    constexpr int G = 3, NG = (NF + G - 1) / G;
     __builtin_amdgcn_s_setprio(1);
-    bf16x8 a[4];
+    bf16x8 a[4], b[NF];
+    auto frag = [&](int row) {
+      return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&T[row * kBfBK + bf_swz(row, kc) * 8]));
+    };
 #pragma unroll
-    for (int rf = 0; rf < 4; ++rf) {
-      const int row = wm * 64 + rf * 16 + (lane & 15);
-      a[rf] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&T[row * kBfBK + bf_swz(row, kc) * 8]));
-    }
+    for (int rf = 0; rf < 4; ++rf) a[rf] = frag(wm * 64 + rf * 16 + (lane & 15));
 #pragma unroll
-    for (int cf = 0; cf < NF; ++cf) {
-      const int row = BM + wn * 16 * NF + cf * 16 + (lane & 15);
-      const bf16x8 b =
-          __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&T[row * kBfBK + bf_swz(row, kc) * 8]));
+    for (int cf = 0; cf < G && cf < NF; ++cf) b[cf] = frag(BM + wn * 16 * NF + cf * 16 + (lane & 15));
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int rf = 0; rf < 4; ++rf)
-        acc[rf][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rf], b, acc[rf][cf], 0, 0, 0);
+    for (int g = 0; g < NG; ++g) {
+      const int c0 = g * G;
+      acc[0][c0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[c0], acc[0][c0], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int cf = c0 + G; cf < c0 + 2 * G && cf < NF; ++cf) b[cf] = frag(BM + wn * 16 * NF + cf * 16 + (lane & 15));
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int cf = c0; cf < c0 + G && cf < NF; ++cf)
+#pragma unroll
+        for (int rf = 0; rf < 4; ++rf)
+          if (cf != c0 || rf != 0)
+            acc[rf][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rf], b[cf], acc[rf][cf], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
     __builtin_amdgcn_s_setprio(0);
   };
