@@ -97,11 +97,11 @@ def kernel_source_hash(kernel, workload):
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload, kernel):
+def load_traffic(workload, kernel, path=None):
     """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE and
     WRITE_SIZE runs recorded in profiles/traffic.json, if they were taken on
     the kernel's current sources; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = path or os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -113,12 +113,12 @@ def load_traffic(workload, kernel):
     return ent.get("bytes_per_launch")
 
 
-def load_mfma_record(workload, kernel):
+def load_mfma_record(workload, kernel, path=None):
     """MFMA utilization (fraction of SIMD cycles with the matrix core busy)
     and shader clock of `kernel` from the rocprofv3 SQ_VALU_MFMA_BUSY_CYCLES /
     GRBM_GUI_ACTIVE run recorded in profiles/mfma.json, if taken on the
     kernel's current sources; else (None, None)."""
-    path = os.path.join(ROOT, "profiles", "mfma.json")
+    path = path or os.path.join(ROOT, "profiles", "mfma.json")
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -130,7 +130,7 @@ def load_mfma_record(workload, kernel):
     return ent.get("mfma_util"), ent.get("clock_ghz")
 
 
-def record_mfma(workload, pmc_csv, simds=1024, xcds=8):
+def record_mfma(workload, pmc_csv, simds=1024, xcds=8, path=None):
     """MFMA utilization per dispatch of the timed product kernels from a
     rocprofv3 counter CSV holding SQ_VALU_MFMA_BUSY_CYCLES (summed over all
     SIMDs) and GRBM_GUI_ACTIVE (summed over the XCDs): busy / (active / xcds
@@ -149,7 +149,7 @@ def record_mfma(workload, pmc_csv, simds=1024, xcds=8):
             elif r["Counter_Name"].startswith("SQ_INSTS_VALU_MFMA_MOPS_"):
                 mops_name = r["Counter_Name"]
     mops = read_counter(pmc_csv, mops_name) if mops_name else {}
-    path = os.path.join(ROOT, "profiles", "mfma.json")
+    path = path or os.path.join(ROOT, "profiles", "mfma.json")
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -507,7 +507,7 @@ def read_counter(csv_path, counter):
     return out
 
 
-def record_traffic(workload, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, cal_bytes):
+def record_traffic(workload, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, cal_bytes, path=None):
     """Scale the FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the timed
     kernels by what the same counters read for a plain copy of cal_bytes per
     dispatch, and store bytes per launch in profiles/traffic.json."""
@@ -518,7 +518,7 @@ def record_traffic(workload, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv,
     f_write = scale(cal_write_csv, "WRITE_SIZE")
     fetch = read_counter(fetch_csv, "FETCH_SIZE")
     write = read_counter(write_csv, "WRITE_SIZE")
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = path or os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
