@@ -302,12 +302,13 @@ def run_serve_bench(args, w, rqlp, torch, dev):
     sat_rps = n_req / wall
     rng = np.random.default_rng(args.seed)
     levels = []
-    for frac in (0.5, 0.8, 0.95):
-        lam = frac * sat_rps
+    rates = [frac * sat_rps for frac in (0.5, 0.8, 0.95)]
+    rates += [float(x) for x in args.serve_rps.split(",") if x.strip()]
+    for lam in rates:
         arr = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
         arr -= arr[0]
         wl, lt = run(arr)
-        levels.append({"load": frac, "offered_rps": lam, "achieved_rps": n_req / wl,
+        levels.append({"load": lam / sat_rps, "offered_rps": lam, "achieved_rps": n_req / wl,
                        "p50_ms": float(np.percentile(lt, 50) * 1e3), "p99_ms": float(np.percentile(lt, 99) * 1e3)})
     srv.close()
     roof = products_roofline(rqlp, ctx, As, pool, q, torch)
@@ -573,6 +574,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slots", type=int, default=0, help="serving: tick streams (default: the workload's)")
     ap.add_argument("--tick", type=int, default=0, help="serving: requests per tick (default: the workload's)")
+    ap.add_argument("--serve-rps", type=str, default="",
+                    help="serving: extra Poisson arrival rates in requests/s (comma list), run after the load fractions")
     ap.add_argument("--no-compare", action="store_true",
                     help="bfloat16 workload: skip the float32 comparison run; batch workload: time the "
                          "grouped form only (no lane, graph or one-by-one runs)")
