@@ -255,6 +255,10 @@ __device__ __attribute__((always_inline)) inline void chol_body(const double* __
     const double gdl = Gdiag[k * kTile + lc];
     int depmask = 0;
     double* Rt = R + (int64_t)k * kTile * ld + k * kTile;
+    // the diagonal factorization is the latency chain of the whole
+    // factorization: its wave takes issue priority over the co-resident
+    // waves' trailing updates while it runs
+    __builtin_amdgcn_s_setprio(3);
     diag_step4<0>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, ld);
     diag_step4<1>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, ld);
     diag_step4<2>(t, x, lane, lr, lc, gdl, tol, depmask, Rt, ld);
@@ -265,6 +269,7 @@ __device__ __attribute__((always_inline)) inline void chol_body(const double* __
       Di[row][lc] = x[r];                                              // X[row][c]
       Rinv16[(int64_t)k * kTile * kTile + lc * kTile + row] = x[r];    // (L^-1)^T
     }
+    __builtin_amdgcn_s_setprio(0);
     if (lane < kTile) {
       const int dep_c = (depmask >> lane) & 1;
       defl[k * kTile + lane] = dep_c;
@@ -324,6 +329,7 @@ __device__ __attribute__((always_inline)) inline void chol_body(const double* __
     const bool ahead = kn < T && wave == own;
     const int sn = tn / NW;
     if (ahead) {
+      __builtin_amdgcn_s_setprio(3);  // the update of tile (k+1, k+1) is on the chain too
 #pragma unroll
       for (int sl = 0; sl < SLOTS; ++sl)
         if (sl == sn) update_g(tile[sl], kn, kn);
