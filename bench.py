@@ -85,6 +85,11 @@ KERNEL_SOURCES = {
 BF16_GEMM_SOURCES = ["k_bf16.hip", "common.h", "kernels.h"]
 
 
+# workloads whose timed products are the same kernels on the same shapes as
+# another workload's, so that they share its counter records
+RECORD_ALIAS = {"dense8000_q0": "dense8000"}
+
+
 def kernel_source_hash(kernel, workload):
     names = KERNEL_SOURCES[kernel]
     if workload.startswith("bf16") and kernel in ("gemm_nn", "gemm_tn"):
@@ -107,7 +112,7 @@ def load_traffic(workload, kernel, path=None):
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    ent = rec.get(workload, {}).get(kernel)
+    ent = rec.get(RECORD_ALIAS.get(workload, workload), {}).get(kernel)
     if not ent or ent.get("source_hash") != kernel_source_hash(kernel, workload):
         return None
     return ent.get("bytes_per_launch")
@@ -124,7 +129,7 @@ def load_mfma_record(workload, kernel, path=None):
             rec = json.load(f)
     except (OSError, ValueError):
         return None, None
-    ent = rec.get(workload, {}).get(kernel)
+    ent = rec.get(RECORD_ALIAS.get(workload, workload), {}).get(kernel)
     if not ent or ent.get("source_hash") != kernel_source_hash(kernel, workload):
         return None, None
     return ent.get("mfma_util"), ent.get("clock_ghz")

@@ -106,6 +106,15 @@ def test_record_traffic_scales_by_the_copy(tmp_path):
     assert bench.load_traffic("dense8000", "gemm_nn", path=str(out)) == pytest.approx(2000.0 * 2048 + 500.0 * 1024)
 
 
+def test_record_alias_shares_the_product_records(tmp_path):
+    # the q = 0 form of the 8000^2 workload runs the same products
+    out = tmp_path / "mfma.json"
+    h = bench.kernel_source_hash("gemm_nn", "dense8000")
+    out.write_text(json.dumps({"dense8000": {"gemm_nn": {"mfma_util": 0.5, "clock_ghz": 2.0, "source_hash": h}}}))
+    assert bench.load_mfma_record("dense8000_q0", "gemm_nn", path=str(out)) == (0.5, 2.0)
+    assert bench.load_mfma_record("csr100k", "gemm_nn", path=str(out)) == (None, None)
+
+
 def test_committed_records_match_current_sources():
     """The committed records were taken on the kernels as they are now, so
     that the bench line carries them (a kernel change without a new PMC run
