@@ -45,6 +45,10 @@ struct rqlp_ctx {
   // batches: decompositions spread over lanes (streams at the default
   // priority), forked from and joined back into the caller's stream
   static constexpr int kLanes = 8;
+  // lockstep groups of a grouped batch (64 uneven requests: 13.9 ms with 3
+  // groups; 16.8 / 14.7 / 15.2 / 15.1 / 14.3 / 16.5 ms with 1 / 2 / 4 / 5 / 6
+  // / 8; 16.3 ms for sub-batches of identical launch sequences on 8 lanes)
+  static constexpr int kLockGroups = 3;
   hipStream_t lanes[kLanes] = {};
   hipStream_t cap = nullptr;  // origin stream of graph captures
   hipEvent_t fork = nullptr, join[kLanes] = {};
@@ -625,13 +629,12 @@ LaunchRecorder*& recorder_slot() {
 // Each problem's own launches keep their order, so its results are the bits
 // of its solo run.  The argument tables and block offsets are uploaded once
 // into device memory.
-// With nlanes == 1 every position takes one grouped launch per kernel
-// variant, all on one stream.  With nlanes > 1 the problems are first
-// split into sub-batches of identical launch sequences (the variants follow
-// from d, alignment and the split-K plans), each sub-batch takes one grouped
-// launch per position, and the sub-batches are spread over the lanes
-// (largest first onto the least loaded): launches of different variants then
-// run side by side instead of one after another.
+// Within a group of problems, every position takes one grouped launch per
+// kernel variant present (the variants follow from d, alignment and the
+// split-K plans), so the group's problems advance in lockstep.  With nlanes
+// > 1 the problems are split into that many groups of about equal work,
+// each on a lane stream of its own, so that the groups' launches run side by
+// side.
 rqlp_status layout_plan(rqlp_ctx* c, int count, const rqlp_problem* probs, const size_t* offs,
                         rqlp_precision prec, char* base, hipStream_t s, rqlp_ctx::GroupedPlan* plan,
                         std::vector<uint8_t>& table, int nlanes = 1) {
@@ -692,78 +695,72 @@ rqlp_status layout_plan(rqlp_ctx* c, int count, const rqlp_problem* probs, const
     plan->launches.push_back({items[0]->fn, aoff, soff, (int)items.size(), (unsigned)total, lane});
     return RQLP_OK;
   };
-  if (nlanes > 1) {
-    // sub-batches: problems with the same (kernel, non-empty) sequence
-    std::vector<std::vector<int>> subs;
-    std::vector<int> sub_of((size_t)count, -1);
-    auto same_seq = [&](int a, int b) {
-      const LaunchRecorder& x = recs[(size_t)a];
-      const LaunchRecorder& y = recs[(size_t)b];
-      if (x.seq.size() != y.seq.size()) return false;
-      for (size_t k = 0; k < x.seq.size(); ++k)
-        if (x.seq[k].fn != y.seq[k].fn || (x.seq[k].blocks > 0) != (y.seq[k].blocks > 0)) return false;
-      return true;
-    };
-    for (int i = 0; i < count; ++i) {
-      for (size_t b = 0; b < subs.size() && sub_of[(size_t)i] < 0; ++b)
-        if (same_seq(subs[b][0], i)) sub_of[(size_t)i] = (int)b;
-      if (sub_of[(size_t)i] < 0) {
-        sub_of[(size_t)i] = (int)subs.size();
-        subs.emplace_back();
-      }
-      subs[(size_t)sub_of[(size_t)i]].push_back(i);
-    }
-    // work estimate of a sub-batch: its workgroups over all launches
-    std::vector<std::pair<double, int>> order;
-    for (size_t b = 0; b < subs.size(); ++b) {
-      double w = 0.0;
-      for (int i : subs[b])
-        for (const auto& x : recs[(size_t)i].seq) w += x.blocks;
-      order.push_back({w, (int)b});
-    }
-    std::sort(order.begin(), order.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
-    const int nl = std::min<int>(nlanes, (int)subs.size());
-    std::vector<double> load((size_t)nl, 0.0);
-    for (const auto& ob : order) {
-      const int lane = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-      load[(size_t)lane] += ob.first;
-      const std::vector<int>& mem = subs[(size_t)ob.second];
-      const LaunchRecorder& r0 = recs[(size_t)mem[0]];
-      for (size_t k = 0; k < r0.seq.size(); ++k) {
-        if (r0.seq[k].blocks == 0) continue;
-        std::vector<const LaunchRec*> items;
-        for (int i : mem) items.push_back(&recs[(size_t)i].seq[k]);
-        const rqlp_status es = emit(items, lane);
-        if (es != RQLP_OK) return es;
-      }
-    }
-    plan->lanes = nl;
-    if (table.empty()) table.resize(16);
-    return RQLP_OK;
-  }
-  for (int ph = 0; ph < nphase; ++ph) {
-    for (size_t j = 0; j < maxlen; ++j) {
-      // kernel variants at this position, in order of first appearance
-      std::vector<GroupedFn> fns;
-      for (int i = 0; i < count; ++i) {
-        const auto sp = spans[(size_t)i][(size_t)ph];
-        if (sp.first + j >= sp.second) continue;
-        const LaunchRec& x = recs[(size_t)i].seq[sp.first + j];
-        if (x.blocks > 0 && std::find(fns.begin(), fns.end(), x.fn) == fns.end()) fns.push_back(x.fn);
-      }
-      for (GroupedFn fn : fns) {
-        std::vector<const LaunchRec*> items;
-        for (int i = 0; i < count; ++i) {
+  // all members in lockstep on one lane: per (phase, position) one grouped
+  // launch per kernel variant present among them
+  auto emit_lockstep = [&](const std::vector<int>& mem, int lane) -> rqlp_status {
+    for (int ph = 0; ph < nphase; ++ph) {
+      for (size_t j = 0; j < maxlen; ++j) {
+        std::vector<GroupedFn> fns;
+        for (int i : mem) {
           const auto sp = spans[(size_t)i][(size_t)ph];
           if (sp.first + j >= sp.second) continue;
           const LaunchRec& x = recs[(size_t)i].seq[sp.first + j];
-          if (x.fn == fn && x.blocks > 0) items.push_back(&x);
+          if (x.blocks > 0 && std::find(fns.begin(), fns.end(), x.fn) == fns.end()) fns.push_back(x.fn);
         }
-        const rqlp_status es = emit(items, 0);
-        if (es != RQLP_OK) return es;
+        for (GroupedFn fn : fns) {
+          std::vector<const LaunchRec*> items;
+          for (int i : mem) {
+            const auto sp = spans[(size_t)i][(size_t)ph];
+            if (sp.first + j >= sp.second) continue;
+            const LaunchRec& x = recs[(size_t)i].seq[sp.first + j];
+            if (x.fn == fn && x.blocks > 0) items.push_back(&x);
+          }
+          const rqlp_status es = emit(items, lane);
+          if (es != RQLP_OK) return es;
+        }
       }
     }
+    return RQLP_OK;
+  };
+  if (nlanes > 1) {
+    // groups of problems in lockstep, one lane each: problems by work,
+    // largest first, cut into contiguous runs of about equal work, so that
+    // problems of similar size share a lane (lockstep makes a lane's
+    // problems wait for its largest one at every position)
+    std::vector<std::pair<double, int>> byw;
+    double total = 0.0;
+    for (int i = 0; i < count; ++i) {
+      double w = 0.0;
+      for (const auto& x : recs[(size_t)i].seq) w += x.blocks;
+      byw.push_back({w, i});
+      total += w;
+    }
+    std::stable_sort(byw.begin(), byw.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    const int nl = std::max(1, std::min(nlanes, count));
+    std::vector<std::vector<int>> groups((size_t)nl);
+    double acc = 0.0;
+    int g = 0;
+    for (const auto& e : byw) {
+      if (g < nl - 1 && acc >= total * (g + 1) / nl && !groups[(size_t)g].empty()) ++g;
+      groups[(size_t)g].push_back(e.second);
+      acc += e.first;
+    }
+    int used = 0;
+    for (auto& mem : groups) {
+      if (mem.empty()) continue;
+      std::sort(mem.begin(), mem.end());  // batch order within a lane
+      const rqlp_status es = emit_lockstep(mem, used);
+      if (es != RQLP_OK) return es;
+      ++used;
+    }
+    plan->lanes = std::max(used, 1);
+    if (table.empty()) table.resize(16);
+    return RQLP_OK;
   }
+  std::vector<int> all((size_t)count);
+  for (int i = 0; i < count; ++i) all[(size_t)i] = i;
+  const rqlp_status es = emit_lockstep(all, 0);
+  if (es != RQLP_OK) return es;
   if (table.empty()) table.resize(16);
   return RQLP_OK;
 }
@@ -772,7 +769,7 @@ rqlp_status layout_plan(rqlp_ctx* c, int count, const rqlp_problem* probs, const
 rqlp_status build_plan(rqlp_ctx* c, int count, const rqlp_problem* probs, rqlp_precision prec, char* base,
                        hipStream_t s, rqlp_ctx::GroupedPlan* plan) {
   std::vector<uint8_t> table;
-  rqlp_status st = layout_plan(c, count, probs, nullptr, prec, base, s, plan, table, rqlp_ctx::kLanes);
+  rqlp_status st = layout_plan(c, count, probs, nullptr, prec, base, s, plan, table, rqlp_ctx::kLockGroups);
   if (st != RQLP_OK) return st;
   if (hipMalloc(&plan->dev, table.size()) != hipSuccess) {
     plan->dev = nullptr;
