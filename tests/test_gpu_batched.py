@@ -147,3 +147,28 @@ def test_grouped_plan_cache_reuse_and_eviction(gpu_lib):
         torch.cuda.synchronize()
         if rep in (0, 3, 9, 10):
             _same(outs, _solo(gpu_lib, As, ps))
+
+
+def test_large_batch_equals_solo(gpu_lib):
+    """A batch of 60 problems (three lockstep groups of 20) gives the bits of
+    every solo run.  The shapes cover several column widths, both products,
+    alignment of the leading dimension, and a wide sketch (d > 256, two
+    column passes)."""
+    announce("large batch")
+    rng = np.random.default_rng(7)
+    As, params = [], []
+    for i in range(60):
+        m = int(rng.integers(3600, 4600))
+        n = int(rng.integers(500, 900))
+        k = [10, 40, 90, 150, 280][i % 5]
+        if k + 10 > min(m, n):
+            k = min(m, n) - 10
+        A = rng.standard_normal((m, n)).astype(np.float32)
+        As.append(to_dev(A))
+        params.append((k, 10, 1, 1000 + i))
+    ref = _solo(gpu_lib, As, params)
+    ctx = gpu_lib.Context(0)
+    outs = gpu_lib.decompose_batched(As, params, ctx=ctx)
+    torch.cuda.synchronize()
+    _same(outs, ref)
+
