@@ -305,10 +305,12 @@ size_t rqlp_workspace_size_batched(int count, const rqlp_problem* problems, rqlp
  * slice of the workspace.  With grouping on (the default,
  * rqlp_set_batch_grouping) and RQLP_FP64 or RQLP_FP32, every problem's
  * launch sequence is recorded once on the host and the batch runs as
- * grouped launches on `stream`: phase by phase (each Cholesky factorization
- * is a phase of its own), one launch per kernel variant runs that step for
- * all problems, each workgroup working on its problem exactly as in the
- * problem's own launch.  The argument tables of a batch are kept in device
+ * grouped launches: the problems, ordered by work, are cut into three
+ * groups of about equal work, and each group advances in lockstep on its
+ * own stream (forked from and joined back into `stream`): phase by phase
+ * (each Cholesky factorization is a phase of its own), one launch per
+ * kernel variant runs that step for all the group's problems, each
+ * workgroup working on its problem exactly as in the problem's own launch.  The argument tables of a batch are kept in device
  * memory and reused when the same batch (descriptors and workspace) comes
  * again.  With grouping off, or for RQLP_BF16_REFINED, the problems' launch
  * sequences are spread over eight internal streams forked from and joined
