@@ -295,6 +295,7 @@ hipError_t launch_apply_f32fast(const double* Y, int64_t ldy, int64_t rows, int 
 RQLP_APPLY_INST(float, double)
 RQLP_APPLY_INST(double, double)
 RQLP_APPLY_INST(double, float)
+RQLP_APPLY_INST(float, float)
 #undef RQLP_APPLY_INST
 
 }  // namespace rqlp

@@ -305,10 +305,16 @@ hipError_t factor(rqlp_ctx* c, const Bufs& b, double* R, int32_t* flags, int d, 
 // orth()/qr() of a rows x d matrix Y (ld ldy) by CholeskyQR2.  Pass 1 writes
 // the float64 basis Q1; pass 2 writes out1 (ld1, ncols1 columns) and
 // optionally out2.  R1, R2 and the flags of both passes stay in `b`.
+// single: the basis only feeds the next product of a power iteration, and
+// pass 1 writes it to out1 at once.  The second pass would only multiply it
+// by an upper-triangular factor (Q1 = Q R2), which leaves the next
+// orthonormalization's Q factor unchanged (the QR of A^T Q R2 is Z (S R2) when
+// A^T Q = Z S), and pass 1 keeps Q1 well conditioned (its Gram matrix is
+// within c cond(Y)^2 u of I), so only rounding differs.
 template <typename T>
 rqlp_status cholqr2(rqlp_ctx* c, const T* Y, int64_t ldy, int64_t rows, int d, const Bufs& b,
                     T* out1, int64_t ld1, int ncols1, T* out2, int64_t ld2, int ncols2,
-                    uint64_t seed, int orth_index, hipStream_t s, bool lowp2 = false) {
+                    uint64_t seed, int orth_index, hipStream_t s, bool lowp2 = false, bool single = false) {
   const int dp = padded_d(d);
   const int gch = gram_chunks(rows, dp);
   const double ftol = fast_tol_for(sizeof(T) == 8);
@@ -318,6 +324,11 @@ rqlp_status cholqr2(rqlp_ctx* c, const T* Y, int64_t ldy, int64_t rows, int d, c
   HIP_TRY(launch_gram<T>(Y, ldy, rows, d, dp, b.gp, gch, b.g, b.esq, c->info, s, t.a, t.b));
   HIP_TRY(factor(c, b, b.r1, b.flags, d, dp, orth_index, 0.0, mode, nesq, s));
   t = timer(c, RQLP_KT_APPLY);
+  if (single) {
+    HIP_TRY((launch_apply<T, T>(Y, ldy, rows, d, dp, b.flags, mode, b.xf, out1, ld1, ncols1, out2, ld2, ncols2, seed,
+                                completion_key(orth_index, 0), s, t.a, t.b)));
+    return RQLP_OK;
+  }
   HIP_TRY((launch_apply<T, double>(Y, ldy, rows, d, dp, b.flags, mode, b.xf, b.q1, dp, dp, nullptr, 0, 0, seed,
                                    completion_key(orth_index, 0), s, t.a, t.b)));
   // second pass: Q1 is orthonormal to working accuracy.  For float output
@@ -397,15 +408,20 @@ rqlp_status run_method(rqlp_ctx* c, char* base, const Layout& Lo, int64_t m, int
   // Omega (n x d, ld dp), then Y = A Omega and Q = orth(Y)
   HIP_TRY(launch_gaussian<T>(seed, kSketchKey1, n, d, om, dp, s));
   if ((st = mulA(om, yb)) != RQLP_OK) return st;
+  // the bases that only feed the next product of the power iteration take
+  // one CholeskyQR pass (see cholqr2); the returned Q and the final QR two
   int oi = 1;
-  if ((st = cholqr2<T>(c, yb, dp, m, d, b, qi, dp, dp, q == 0 ? Q : nullptr, d, d, seed, oi++, s, lowp2)) != RQLP_OK)
+  if ((st = cholqr2<T>(c, yb, dp, m, d, b, qi, dp, dp, q == 0 ? Q : nullptr, d, d, seed, oi++, s, lowp2, q > 0)) !=
+      RQLP_OK)
     return st;
   for (int it = 1; it <= q; ++it) {
     // W = orth(A^T Q) (stored in the Omega buffer), Q = orth(A W)
     if ((st = mulAt(qi, yb)) != RQLP_OK) return st;
-    if ((st = cholqr2<T>(c, yb, dp, n, d, b, om, dp, dp, nullptr, 0, 0, seed, oi++, s, lowp2)) != RQLP_OK) return st;
+    if ((st = cholqr2<T>(c, yb, dp, n, d, b, om, dp, dp, nullptr, 0, 0, seed, oi++, s, lowp2, true)) != RQLP_OK)
+      return st;
     if ((st = mulA(om, yb)) != RQLP_OK) return st;
-    if ((st = cholqr2<T>(c, yb, dp, m, d, b, qi, dp, dp, it == q ? Q : nullptr, d, d, seed, oi++, s, lowp2)) != RQLP_OK)
+    if ((st = cholqr2<T>(c, yb, dp, m, d, b, qi, dp, dp, it == q ? Q : nullptr, d, d, seed, oi++, s, lowp2,
+                         it < q)) != RQLP_OK)
       return st;
   }
   // B^T = A^T Q; [V, R] = qr(B^T); L = R^T
