@@ -14,6 +14,8 @@
 #include "grouped.h"
 #include "kernels.h"
 
+#include <utility>
+
 namespace rqlp {
 
 constexpr int kApCols = 4 * kTile;    // columns per workgroup (4 blocks)
@@ -45,22 +47,27 @@ __device__ __attribute__((always_inline)) inline void apply_body(const Tin* __re
 
   // out[:, J] = sum_{t <= J} Y[:, t] X[t, J] for column blocks J0..J1-1;
   // per block row t the X tile (16 x 64) and the Y tile (64 x 16, widened
-  // to double) are staged in LDS, double buffered, with the next t held in
-  // registers meanwhile.
+  // to double) are staged in LDS, double buffered, while the tiles of the
+  // next kDepth block rows are in flight into a register ring (slot t mod
+  // kDepth).  Narrow row blocks (RF = 1: short, latency-bound chains) keep
+  // two block rows in flight; RF = 2 keeps one, which leaves room for more
+  // resident waves (measured faster for it).
   const int J0 = 4 * by;
   if (J0 >= T) return;
   const int J1 = min(T, J0 + 4);
+  constexpr int kDepth = RF == 1 ? 2 : 1;
   C* Xs = smem;                                // [2][16][kApXS]
   C* Ys = smem + 2 * kTile * kApXS;            // [2][64 RF][kApYS]
-  double xr[4];
-  Tin yr[4 * RF];
-  auto load = [&](int t) {
+  double xr[kDepth][4];
+  Tin yr[kDepth][4 * RF];
+  auto load = [&](auto Sc, int t) {
+    constexpr int S = decltype(Sc)::value;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
       const int kr = e >> 6, c = e & 63;       // X[t*16 + kr][J0*16 + c]
       const int col = J0 * kTile + c;
-      xr[q] = (col < J1 * kTile) ? Xfull[(int64_t)(t * kTile + kr) * dp + col] : 0.0;
+      xr[S][q] = (col < J1 * kTile) ? Xfull[(int64_t)(t * kTile + kr) * dp + col] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < 4 * RF; ++q) {
@@ -68,19 +75,20 @@ __device__ __attribute__((always_inline)) inline void apply_body(const Tin* __re
       const int rr = e >> 4, cc = e & 15;      // Y[r0 + rr][t*16 + cc]
       const int64_t row = r0 + rr;
       const int ycol = t * kTile + cc;
-      yr[q] = (row < rows && ycol < d) ? Y[row * ldy + ycol] : (Tin)0;
+      yr[S][q] = (row < rows && ycol < d) ? Y[row * ldy + ycol] : (Tin)0;
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](auto Sc, int buf) {
+    constexpr int S = decltype(Sc)::value;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
-      Xs[buf * kTile * kApXS + (e >> 6) * kApXS + (e & 63)] = (C)xr[q];
+      Xs[buf * kTile * kApXS + (e >> 6) * kApXS + (e & 63)] = (C)xr[S][q];
     }
 #pragma unroll
     for (int q = 0; q < 4 * RF; ++q) {
       const int e = tid + 256 * q;
-      Ys[buf * kApRows * kApYS + (e >> 4) * kApYS + (e & 15)] = (C)yr[q];
+      Ys[buf * kApRows * kApYS + (e >> 4) * kApYS + (e & 15)] = (C)yr[S][q];
     }
   };
   typename Mfma<C>::acc_t acc[RF][4];
@@ -88,13 +96,8 @@ __device__ __attribute__((always_inline)) inline void apply_body(const Tin* __re
   for (int f = 0; f < RF; ++f)
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[f][u] = Mfma<C>::zero();
-  load(0);
-  store(0);
-  __syncthreads();
-  int buf = 0;
-  for (int t = 0; t < J1; ++t) {
-    const bool more = t + 1 < J1;
-    if (more) load(t + 1);
+  auto compute = [&](int t) {
+    const int buf = t & 1;
     const C* xs = Xs + buf * kTile * kApXS;
     const C* ys = Ys + buf * kApRows * kApYS + (wave * kTile * RF + lc) * kApYS;
     C a[RF][4];
@@ -114,9 +117,46 @@ __device__ __attribute__((always_inline)) inline void apply_body(const Tin* __re
         }
       }
     }
-    if (more) store(buf ^ 1);
+  };
+  using S0 = std::integral_constant<int, 0>;
+  if constexpr (kDepth == 1) {
+    // one block row in flight: row t + 1 is fetched while row t is used
+    load(S0{}, 0);
+    store(S0{}, 0);
     __syncthreads();
-    buf ^= 1;
+    for (int t = 0; t < J1; ++t) {
+      const bool more = t + 1 < J1;
+      if (more) load(S0{}, t + 1);
+      compute(t);
+      if (more) store(S0{}, (t + 1) & 1);
+      __syncthreads();
+    }
+  } else {
+    // block rows 0 .. kDepth-1 in flight, row 0 staged, row kDepth into its slot
+    [&]<int... Ss>(std::integer_sequence<int, Ss...>) {
+      ((Ss < J1 ? load(std::integral_constant<int, Ss>{}, Ss) : void()), ...);
+    }(std::make_integer_sequence<int, kDepth>{});
+    store(S0{}, 0);
+    if (kDepth < J1) load(S0{}, kDepth);
+    __syncthreads();
+    // block row t = t0 + S (S = t mod kDepth): its products, then row t + 1
+    // staged from slot (S + 1) mod kDepth, which then takes row t + 1 + kDepth
+    auto sub = [&](auto Sc, int t) {
+      constexpr int S = decltype(Sc)::value;
+      constexpr int N = (S + 1) % kDepth;
+      if (t >= J1) return;
+      compute(t);
+      if (t + 1 < J1) {
+        store(std::integral_constant<int, N>{}, (t + 1) & 1);
+        if (t + 1 + kDepth < J1) load(std::integral_constant<int, N>{}, t + 1 + kDepth);
+      }
+      __syncthreads();
+    };
+    for (int t0 = 0; t0 < J1; t0 += kDepth) {
+      [&]<int... Ss>(std::integer_sequence<int, Ss...>) {
+        (sub(std::integral_constant<int, Ss>{}, t0 + Ss), ...);
+      }(std::make_integer_sequence<int, kDepth>{});
+    }
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {

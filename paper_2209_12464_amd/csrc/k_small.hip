@@ -5,6 +5,8 @@
 #include "grouped.h"
 #include "kernels.h"
 
+#include <type_traits>
+
 namespace rqlp {
 
 // R = R2 * R1' (R1' = R1 with the rows of dependent columns zeroed, R2 with
@@ -21,15 +23,49 @@ __device__ __attribute__((always_inline)) inline void form_r_body(const double* 
   const int I = bid / nT, J = bid % nT;  // output tile of R
   const int lane = threadIdx.x, lr = lane >> 4, lc = lane & 15;
   doublex4 acc = Mfma<double>::zero();
-  if (I <= J) {
-    for (int t = I; t <= J; ++t) {
+  // The operands of kFB block columns t are fetched into registers one
+  // batch ahead of their products (two batches alternate), so the chain of
+  // products waits for a load once per batch rather than once per t; the
+  // products run in the order t = I..J, ks = 0..3 all the same.
+  constexpr int kFB = 8;
+  double pa[2][kFB][4], pb[2][kFB][4];
+  auto fetch = [&](auto Bc, int tb) {
+    constexpr int B = decltype(Bc)::value;
+#pragma unroll
+    for (int i = 0; i < kFB; ++i) {
+      const int t = tb + i;
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
         const int kk = t * kTile + ks * 4 + lr;
-        const double a = R2[(int64_t)(I * kTile + lc) * dp + kk];        // A[m][kk], m = lc
-        const double b = f1[kk] ? 0.0 : R1[(int64_t)kk * dp + J * kTile + lc];
-        acc = Mfma<double>::mma(a, b, acc);
+        double a = 0.0, b = 0.0;
+        if (t <= J) {
+          a = R2[(int64_t)(I * kTile + lc) * dp + kk];  // A[m][kk], m = lc
+          const double r = R1[(int64_t)kk * dp + J * kTile + lc];
+          b = f1[kk] ? 0.0 : r;
+        }
+        pa[B][i][ks] = a;
+        pb[B][i][ks] = b;
       }
+    }
+  };
+  auto run = [&](auto Bc, int tb) {
+    constexpr int B = decltype(Bc)::value;
+#pragma unroll
+    for (int i = 0; i < kFB; ++i) {
+      if (tb + i > J) break;
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) acc = Mfma<double>::mma(pa[B][i][ks], pb[B][i][ks], acc);
+    }
+  };
+  if (I <= J) {
+    using B0 = std::integral_constant<int, 0>;
+    using B1 = std::integral_constant<int, 1>;
+    fetch(B0{}, I);
+    for (int tb = I; tb <= J; tb += 2 * kFB) {
+      if (tb + kFB <= J) fetch(B1{}, tb + kFB);
+      run(B0{}, tb);
+      if (tb + 2 * kFB <= J) fetch(B0{}, tb + 2 * kFB);
+      if (tb + kFB <= J) run(B1{}, tb + kFB);
     }
   }
 #pragma unroll
