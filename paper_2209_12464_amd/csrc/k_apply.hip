@@ -26,7 +26,8 @@ __host__ __device__ inline size_t apply_lds_doubles(int rf) {
   return 2 * (size_t)(kTile * kApXS + 64 * rf * kApYS);
 }
 
-// Workgroup (bx, by): rows bx * 64 RF .. and column blocks 4 by .. 4 by + 3.
+// Workgroup (bx, by): rows bx * 64 RF .. and column blocks J0 .. J0 + 3,
+// J0 = 4 (G - 1 - by) for G = ceil(T / 4) column groups.
 template <typename Tin, typename Tout, int RF, typename C = double>
 __device__ __attribute__((always_inline)) inline void apply_body(const Tin* __restrict__ Y, int64_t ldy, int64_t rows,
                                                                  int d, int dp, const int32_t* __restrict__ flags,
@@ -52,8 +53,10 @@ __device__ __attribute__((always_inline)) inline void apply_body(const Tin* __re
   // kDepth).  Narrow row blocks (RF = 1: short, latency-bound chains) keep
   // two block rows in flight; RF = 2 keeps one, which leaves room for more
   // resident waves (measured faster for it).
-  const int J0 = 4 * by;
-  if (J0 >= T) return;
+  // column groups in reverse of the dispatch order: the long triangular
+  // loops of the last column groups start first, the short ones fill in
+  const int J0 = 4 * ((T + 3) / 4 - 1 - by);
+  if (J0 < 0 || J0 >= T) return;
   const int J1 = min(T, J0 + 4);
   constexpr int kDepth = RF == 1 ? 2 : 1;
   C* Xs = smem;                                // [2][16][kApXS]
