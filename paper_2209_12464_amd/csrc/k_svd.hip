@@ -37,7 +37,7 @@ namespace rqlp {
 constexpr int kSvW = 8;               // columns per block
 constexpr int kSvCols = 2 * kSvW;     // columns of a block pair
 constexpr int kSvThreads = 64 * kSvW; // one wave per rotation of a round
-constexpr int kSvRows = (kDMax + 63) / 64;  // rows of each half per lane
+constexpr int kSvRows = (kDMax + 63) / 64;  // rows of each half per lane, at most
 
 inline size_t svd_align(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -98,7 +98,9 @@ __global__ __launch_bounds__(256) void svd_init_kernel(const T* __restrict__ M, 
 }
 
 // One step of a sweep for this workgroup's block pair; flags[sweep] = 1
-// when the step rotated a pair.
+// when the step rotated a pair.  R = ceil(dp / 64) rows of each half per
+// lane.
+template <int R>
 __device__ __attribute__((always_inline)) inline void svd_step(double* __restrict__ XV, int dp, int nb, int step,
                                                               int sweep, int32_t* __restrict__ flags, double tol,
                                                               double* Xs, double* nrm, int& rotated) {
@@ -141,17 +143,25 @@ __device__ __attribute__((always_inline)) inline void svd_step(double* __restric
     double* xp = Xs + p * len;
     double* xq = Xs + q * len;
     const double a = nrm[p], b = nrm[q];
-    // this lane's rows of x_p and x_q, all loaded before the first use
-    double u[kSvRows], v[kSvRows];
+    // this lane's rows of x_p and x_q and of their v halves, all loaded
+    // before the first use (the v halves are needed only for a rotation,
+    // but reading them here takes their latency off the rotation's chain)
+    double u[R], v[R], pu[R], pv[R];
 #pragma unroll
-    for (int i = 0; i < kSvRows; ++i) {
+    for (int i = 0; i < R; ++i) {
       const int r = lane + 64 * i;
       u[i] = r < dp ? xp[r] : 0.0;
       v[i] = r < dp ? xq[r] : 0.0;
     }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = dp + lane + 64 * i;
+      pu[i] = r < len ? xp[r] : 0.0;
+      pv[i] = r < len ? xq[r] : 0.0;
+    }
     double g = 0.0;
 #pragma unroll
-    for (int i = 0; i < kSvRows; ++i) g = fma(u[i], v[i], g);
+    for (int i = 0; i < R; ++i) g = fma(u[i], v[i], g);
     g = wave_sum(g);  // uniform across the wave: all rows see one rotation
     if (g * g > tol * tol * (a * b)) {
       const double zeta = (b - a) * rcp_nr(2.0 * g);
@@ -163,15 +173,8 @@ __device__ __attribute__((always_inline)) inline void svd_step(double* __restric
         t = copysign(rcp_nr(fabs(zeta) + w * rsqrt_nr(w)), zeta);
       }
       const double cs = rsqrt_nr(fma(t, t, 1.0)), sn = cs * t;
-      double pu[kSvRows], pv[kSvRows];  // the v halves
 #pragma unroll
-      for (int i = 0; i < kSvRows; ++i) {
-        const int r = dp + lane + 64 * i;
-        pu[i] = r < len ? xp[r] : 0.0;
-        pv[i] = r < len ? xq[r] : 0.0;
-      }
-#pragma unroll
-      for (int i = 0; i < kSvRows; ++i) {
+      for (int i = 0; i < R; ++i) {
         const int r = lane + 64 * i;
         if (r < dp) {
           xp[r] = cs * u[i] - sn * v[i];
@@ -197,6 +200,7 @@ __device__ __attribute__((always_inline)) inline void svd_step(double* __restric
 }
 
 // Every sweep, in one cooperative launch of nb / 2 workgroups.
+template <int R>
 __global__ __launch_bounds__(kSvThreads) void svd_sweeps_kernel(double* __restrict__ XV, int dp, int nb,
                                                                 int32_t* __restrict__ flags, int max_sweeps,
                                                                 double tol) {
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(kSvThreads) void svd_sweeps_kernel(double* __restri
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     for (int step = 0; step < nb - 1; ++step) {
-      svd_step(XV, dp, nb, step, sweep, flags, tol, svd_smem, nrm, rotated);
+      svd_step<R>(XV, dp, nb, step, sweep, flags, tol, svd_smem, nrm, rotated);
       grid.sync();  // the next step reads columns other workgroups wrote
     }
     if (flags[sweep] == 0) break;  // the same value for every workgroup after the barrier
@@ -301,7 +305,19 @@ hipError_t launch_svd_small(const T* M, int64_t ldm, int d, T* U, int64_t ldu, T
   hipLaunchKernelGGL((svd_init_kernel<T>), dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, M, ldm, d, dp, XV,
                      flags, kSvSweeps);
   const size_t shmem = (size_t)kSvCols * 2 * dp * sizeof(double);
-  const void* fn = reinterpret_cast<const void*>(svd_sweeps_kernel);
+  // R = ceil(dp / 64) rows of each column half per lane (1 .. kSvRows)
+  const void* fn = nullptr;
+  switch ((dp + 63) / 64) {
+    case 1: fn = reinterpret_cast<const void*>(svd_sweeps_kernel<1>); break;
+    case 2: fn = reinterpret_cast<const void*>(svd_sweeps_kernel<2>); break;
+    case 3: fn = reinterpret_cast<const void*>(svd_sweeps_kernel<3>); break;
+    case 4: fn = reinterpret_cast<const void*>(svd_sweeps_kernel<4>); break;
+    case 5: fn = reinterpret_cast<const void*>(svd_sweeps_kernel<5>); break;
+    case 6: fn = reinterpret_cast<const void*>(svd_sweeps_kernel<6>); break;
+    case 7: fn = reinterpret_cast<const void*>(svd_sweeps_kernel<7>); break;
+    case 8: fn = reinterpret_cast<const void*>(svd_sweeps_kernel<8>); break;
+    default: fn = reinterpret_cast<const void*>(svd_sweeps_kernel<kSvRows>); break;
+  }
   if (shmem > 65536) {  // more than 64 KB of LDS for the columns of wide pairs
     const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
