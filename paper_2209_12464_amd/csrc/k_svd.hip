@@ -130,63 +130,127 @@ __device__ __attribute__((always_inline)) inline void svd_step(double* __restric
   }
   __syncthreads();
 
-  const int rounds = step == 0 ? kSvCols - 1 : kSvW;
-  for (int rnd = 0; rnd < rounds; ++rnd) {
-    int p, q;
-    if (step == 0) {  // round-robin over all the pair's columns
-      p = wave == 0 ? 0 : 1 + (wave - 1 + rnd) % (kSvCols - 1);
-      q = 1 + (kSvCols - 2 - wave + rnd) % (kSvCols - 1);
-    } else {          // column wave of the first block with a column of the second
-      p = wave;
-      q = kSvW + (wave + rnd) % kSvW;
+  // The rotation of a pair with squared norms a, b and inner product g
+  // (false when the pair is already orthogonal to working accuracy).
+  auto params = [&](double a, double b, double g, double& t, double& cs, double& sn) {
+    if (!(g * g > tol * tol * (a * b))) return false;
+    const double zeta = (b - a) * rcp_nr(2.0 * g);
+    if (fabs(zeta) > 1e150) {
+      t = 0.5 * rcp_nr(zeta);
+    } else {
+      const double w = fma(zeta, zeta, 1.0);
+      t = copysign(rcp_nr(fabs(zeta) + w * rsqrt_nr(w)), zeta);
     }
+    cs = rsqrt_nr(fma(t, t, 1.0));
+    sn = cs * t;
+    return true;
+  };
+
+  if (step == 0) {
+    // round-robin over all the pair's columns, every column through LDS
+    for (int rnd = 0; rnd < kSvCols - 1; ++rnd) {
+      const int p = wave == 0 ? 0 : 1 + (wave - 1 + rnd) % (kSvCols - 1);
+      const int q = 1 + (kSvCols - 2 - wave + rnd) % (kSvCols - 1);
+      double* xp = Xs + p * len;
+      double* xq = Xs + q * len;
+      const double a = nrm[p], b = nrm[q];
+      // this lane's rows of x_p and x_q and of their v halves, all loaded
+      // before the first use (the v halves are needed only for a rotation,
+      // but reading them here takes their latency off the rotation's chain)
+      double u[R], v[R], pu[R], pv[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int r = lane + 64 * i;
+        u[i] = r < dp ? xp[r] : 0.0;
+        v[i] = r < dp ? xq[r] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int r = dp + lane + 64 * i;
+        pu[i] = r < len ? xp[r] : 0.0;
+        pv[i] = r < len ? xq[r] : 0.0;
+      }
+      double g = 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) g = fma(u[i], v[i], g);
+      g = wave_sum(g);  // uniform across the wave: all rows see one rotation
+      double t, cs, sn;
+      if (params(a, b, g, t, cs, sn)) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int r = lane + 64 * i;
+          if (r < dp) {
+            xp[r] = cs * u[i] - sn * v[i];
+            xq[r] = sn * u[i] + cs * v[i];
+            xp[dp + r] = cs * pu[i] - sn * pv[i];
+            xq[dp + r] = sn * pu[i] + cs * pv[i];
+          }
+        }
+        if (lane == 0) {
+          nrm[p] = a - t * g;
+          nrm[q] = b + t * g;
+          rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+  } else {
+    // column p = wave of the first block meets every column of the second,
+    // q = kSvW + (wave + round) mod kSvW: p (both halves) and its squared
+    // norm stay in this wave's registers for the whole step, and only the
+    // q columns pass through LDS from round to round
+    const int p = wave;
     double* xp = Xs + p * len;
-    double* xq = Xs + q * len;
-    const double a = nrm[p], b = nrm[q];
-    // this lane's rows of x_p and x_q and of their v halves, all loaded
-    // before the first use (the v halves are needed only for a rotation,
-    // but reading them here takes their latency off the rotation's chain)
-    double u[R], v[R], pu[R], pv[R];
+    double u[R], pu[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int r = lane + 64 * i;
       u[i] = r < dp ? xp[r] : 0.0;
-      v[i] = r < dp ? xq[r] : 0.0;
+      pu[i] = r < dp ? xp[dp + r] : 0.0;
     }
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int r = dp + lane + 64 * i;
-      pu[i] = r < len ? xp[r] : 0.0;
-      pv[i] = r < len ? xq[r] : 0.0;
-    }
-    double g = 0.0;
-#pragma unroll
-    for (int i = 0; i < R; ++i) g = fma(u[i], v[i], g);
-    g = wave_sum(g);  // uniform across the wave: all rows see one rotation
-    if (g * g > tol * tol * (a * b)) {
-      const double zeta = (b - a) * rcp_nr(2.0 * g);
-      double t;
-      if (fabs(zeta) > 1e150) {
-        t = 0.5 * rcp_nr(zeta);
-      } else {
-        const double w = fma(zeta, zeta, 1.0);
-        t = copysign(rcp_nr(fabs(zeta) + w * rsqrt_nr(w)), zeta);
-      }
-      const double cs = rsqrt_nr(fma(t, t, 1.0)), sn = cs * t;
+    double a = nrm[p];
+    for (int rnd = 0; rnd < kSvW; ++rnd) {
+      const int q = kSvW + (wave + rnd) % kSvW;
+      double* xq = Xs + q * len;
+      const double b = nrm[q];
+      double v[R], pv[R];
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         const int r = lane + 64 * i;
-        if (r < dp) {
-          xp[r] = cs * u[i] - sn * v[i];
-          xq[r] = sn * u[i] + cs * v[i];
-          xp[dp + r] = cs * pu[i] - sn * pv[i];
-          xq[dp + r] = sn * pu[i] + cs * pv[i];
+        v[i] = r < dp ? xq[r] : 0.0;
+        pv[i] = r < dp ? xq[dp + r] : 0.0;
+      }
+      double g = 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) g = fma(u[i], v[i], g);
+      g = wave_sum(g);
+      double t, cs, sn;
+      if (params(a, b, g, t, cs, sn)) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int r = lane + 64 * i;
+          const double nu = cs * u[i] - sn * v[i], npu = cs * pu[i] - sn * pv[i];
+          if (r < dp) {
+            xq[r] = sn * u[i] + cs * v[i];
+            xq[dp + r] = sn * pu[i] + cs * pv[i];
+          }
+          u[i] = nu;
+          pu[i] = npu;
+        }
+        a = a - t * g;
+        if (lane == 0) {
+          nrm[q] = b + t * g;
+          rotated = 1;
         }
       }
-      if (lane == 0) {
-        nrm[p] = a - t * g;
-        nrm[q] = b + t * g;
-        rotated = 1;
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = lane + 64 * i;
+      if (r < dp) {
+        xp[r] = u[i];
+        xp[dp + r] = pu[i];
       }
     }
     __syncthreads();
