@@ -114,19 +114,49 @@ __device__ __attribute__((always_inline)) inline void svd_step(double* __restric
   // the two blocks' columns are contiguous runs of kSvW * len values
   const int64_t base_a = (int64_t)ba * kSvW * len, base_b = (int64_t)bb * kSvW * len;
   const int half = kSvW * len;
-  for (int e = tid; e < half; e += kSvThreads) {
-    Xs[e] = XV[base_a + e];
-    Xs[half + e] = XV[base_b + e];
+  // batches of kLd values per thread and block, all loads of a batch in
+  // flight before their LDS stores
+  constexpr int kLd = 8;
+  for (int e0 = tid; e0 < half; e0 += kLd * kSvThreads) {
+    double va[kLd], vb[kLd];
+#pragma unroll
+    for (int j = 0; j < kLd; ++j) {
+      const int e = e0 + j * kSvThreads;
+      va[j] = e < half ? XV[base_a + e] : 0.0;
+      vb[j] = e < half ? XV[base_b + e] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kLd; ++j) {
+      const int e = e0 + j * kSvThreads;
+      if (e < half) {
+        Xs[e] = va[j];
+        Xs[half + e] = vb[j];
+      }
+    }
   }
   if (tid == 0) rotated = 0;
   __syncthreads();
-  // squared norms of the pair's columns (two per wave)
-  for (int c = wave; c < kSvCols; c += kSvThreads / 64) {
-    const double* xc = Xs + c * len;
-    double a = 0.0;
-    for (int r = lane; r < dp; r += 64) a = fma(xc[r], xc[r], a);
-    a = wave_sum(a);
-    if (lane == 0) nrm[c] = a;
+  // squared norms of the pair's columns: wave w takes columns w and w + kSvW
+  // (both sums side by side)
+  {
+    static_assert(kSvCols == 2 * (kSvThreads / 64), "two columns per wave");
+    const double* x0 = Xs + wave * len;
+    const double* x1 = Xs + (wave + kSvW) * len;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = lane + 64 * i;
+      if (r < dp) {
+        a0 = fma(x0[r], x0[r], a0);
+        a1 = fma(x1[r], x1[r], a1);
+      }
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    if (lane == 0) {
+      nrm[wave] = a0;
+      nrm[wave + kSvW] = a1;
+    }
   }
   __syncthreads();
 
