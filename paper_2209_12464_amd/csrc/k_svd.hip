@@ -286,11 +286,29 @@ __device__ __attribute__((always_inline)) inline void svd_step(double* __restric
     __syncthreads();
   }
 
-  for (int e = tid; e < half; e += kSvThreads) {
-    XV[base_a + e] = Xs[e];
-    XV[base_b + e] = Xs[half + e];
+  // columns no rotation touched are already in XV as they are; otherwise
+  // batches of kLd values per thread and block, read from LDS before their
+  // stores
+  if (rotated) {
+    for (int e0 = tid; e0 < half; e0 += kLd * kSvThreads) {
+      double va[kLd], vb[kLd];
+#pragma unroll
+      for (int j = 0; j < kLd; ++j) {
+        const int e = e0 + j * kSvThreads;
+        va[j] = e < half ? Xs[e] : 0.0;
+        vb[j] = e < half ? Xs[half + e] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < kLd; ++j) {
+        const int e = e0 + j * kSvThreads;
+        if (e < half) {
+          XV[base_a + e] = va[j];
+          XV[base_b + e] = vb[j];
+        }
+      }
+    }
+    if (tid == 0) flags[sweep] = 1;
   }
-  if (tid == 0 && rotated) flags[sweep] = 1;
 }
 
 // Every sweep, in one cooperative launch of nb / 2 workgroups.
