@@ -17,6 +17,11 @@
  *
  * orth() and qr() are the unpivoted QR with a positive diagonal in R,
  * computed by CholeskyQR2 with a float64 Gram matrix and Cholesky factor.
+ * A basis inside the power iteration that only feeds the next product (Q
+ * before the last step, and W) takes the first CholeskyQR pass alone: it is
+ * the orthonormal factor times an upper-triangular matrix, which leaves the
+ * next orthonormal factor, and so every returned factor, unchanged in exact
+ * arithmetic.  The returned Q and the final qr() take both passes.
  *
  * Conventions for every entry point:
  *  - Matrices are row-major with an explicit leading dimension (elements).
@@ -60,8 +65,9 @@ typedef enum {
  * RQLP_BF16_REFINED (dense rqlp_decompose only; UNSUPPORTED elsewhere): A
  * is float; every product with A rounds A and its right-hand factor to
  * bfloat16 (round to nearest even) and accumulates in float32 on the matrix
- * cores; the orthonormalizations are the same float64-Gram CholeskyQR2 as
- * for RQLP_FP32, whose second pass restores orthogonality.  Results are
+ * cores; the orthonormalizations are the same float64-Gram CholeskyQR as
+ * for RQLP_FP32, whose second pass (returned Q, final qr()) restores
+ * orthogonality.  Results are
  * float.  Its workspace also holds bfloat16 copies of A and A^T. */
 typedef enum {
   RQLP_FP64 = 0,

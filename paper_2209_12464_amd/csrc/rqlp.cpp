@@ -493,8 +493,9 @@ rqlp_status decompose_paper(rqlp_ctx* c, const T* A, int64_t m, int64_t n, int64
 // RQLP_BF16_REFINED: A (float) is rounded to bfloat16 once, in both layouts;
 // every product rounds its right-hand factor to bfloat16 and accumulates in
 // float32; the rest of the method is the float32 form, except that the
-// second CholeskyQR pass of every orthonormalization runs its Gram matrix
-// and (on its fast path) its product in float32 arithmetic.
+// second CholeskyQR pass (of the orthonormalizations that take two: the
+// returned basis and the final QR) runs its Gram matrix and (on its fast
+// path) its product in float32 arithmetic.
 rqlp_status decompose_dense_bf16(rqlp_ctx* c, const float* A, int64_t m, int64_t n, int64_t lda, int k, int p,
                                  int q, uint64_t seed, float* Q, float* L, float* V, void* ws, size_t ws_bytes,
                                  hipStream_t s) {
