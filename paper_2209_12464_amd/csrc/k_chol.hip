@@ -48,15 +48,15 @@ __device__ inline void tile_of(int t, int& i, int& j) {
   j = t - ii * (ii + 1) / 2;
 }
 
-// 1/sqrt(x) to float64 accuracy: hardware estimate and two Newton steps.
+// 1/sqrt(x) to float64 accuracy: the hardware estimate (relative error
+// about 2^-24) and one third-order correction, y (1 + e/2 + 3 e^2/8) with
+// e = 1 - x y^2, which leaves a truncation error near 5 e^3 / 16 and is as
+// accurate as two Newton steps (about an ulp) with four dependent
+// operations instead of six on the pivot chain.
 __device__ inline double rsqrt_f64(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const double r = fma(-x * y, y, 1.0);
-    y = fma(0.5 * y, r, y);
-  }
-  return y;
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
 // One 4-pivot step of the 16 x 16 diagonal-tile factorization S = L L^T,

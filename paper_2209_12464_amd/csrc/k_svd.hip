@@ -68,20 +68,21 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // 1/x and 1/sqrt(x) for finite positive (rsqrt) or nonzero (rcp) x: the
-// hardware estimates refined by two Newton steps, within an ulp or two, on
-// the critical path of every rotation instead of the longer correctly
-// rounded sequences.
+// hardware estimates (relative error about 2^-24) with one third-order
+// correction each, y (1 + e + e^2) with e = 1 - x y for the reciprocal and
+// y (1 + e/2 + 3 e^2/8) with e = 1 - x y^2 for the reciprocal square root,
+// within an ulp or two like two Newton steps but with a shorter dependent
+// chain on the critical path of every rotation (instead of the longer
+// correctly rounded sequences).
 __device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) y = fma(y, fma(-x, y, 1.0), y);
-  return y;
+  const double y = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, y, 1.0);
+  return fma(y, fma(e, e, e), y);
 }
 __device__ __forceinline__ double rsqrt_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-  return y;
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
 // XV: dp columns of length 2 dp, column j = (M[:, j] zero-padded, e_j).
